@@ -1,0 +1,216 @@
+/*
+ * bhpp.h -- C ABI of the MI355X (gfx950) library for approximate BHPP queries.
+ *
+ * Method: Yang, "Efficient and Effective Similarity Search over Bipartite
+ * Graphs", WWW '22 (arXiv 2312.06724).
+ *
+ * Problem (Sec. 3.2, Definition 1): given a weighted undirected bipartite graph
+ * G = (U u V, E), a restart probability alpha in (0,1) and a query node u in U,
+ * return for every x in U a value beta'(u,x) with |beta(u,x) - beta'(u,x)| <= eps,
+ * where beta(u,x) = pi(u,x) + pi(x,u) and pi is hidden personalized PageRank,
+ * the random walk with restart over the two-hop U->V->U transition
+ * P = D_U^-1 W D_V^-1 W^T (Sec. 3.1, Eq. (pmatrix); Eq. (hpp)).
+ * The library runs Approx-BHPP (Algorithm 5): SS-Push (Algorithm 3), then
+ * PI-Push (Algorithm 4, which ends with PowerIteration, Algorithm 1), then
+ * beta' = pi_f + pi_b. For the cold start every returned value also satisfies
+ * 0 <= beta - beta' <= eps up to floating-point rounding (Theorems 1-3).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers documented as "device" must point to GPU memory of the current
+ *    HIP device; pointers documented as "host" to CPU memory.
+ *  - hip_stream is a hipStream_t (NULL = the null stream). All GPU work is
+ *    enqueued on it. Calls return once the work is enqueued unless stated
+ *    otherwise; the caller synchronises the stream before reading outputs.
+ *  - Argument errors are detected before any work is enqueued and return a
+ *    negative status; outputs are then untouched.
+ *  - A HIP runtime failure returns BHPP_DEVICE_ERROR and is remembered on the
+ *    graph handle: every later call on that handle returns BHPP_DEVICE_ERROR.
+ *  - No C++ exception crosses this interface.
+ *  - Node ids are 0-based: U ids in [0, n_u), V ids in [0, n_v).
+ */
+#ifndef BHPP_H
+#define BHPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bhpp_status;
+#define BHPP_OK               0
+#define BHPP_INVALID_ARG     -1  /* alpha not in (0,1), eps <= 0, k < 1, n < 0, NULL pointer, ... */
+#define BHPP_OUT_OF_RANGE    -2  /* a node id outside [0,n_u) or [0,n_v) */
+#define BHPP_ISOLATED_SOURCE -3  /* query source with no edge: ws(u) = 0 */
+#define BHPP_BAD_WEIGHT      -4  /* an edge weight that is <= 0, NaN or infinite */
+#define BHPP_OUT_OF_MEMORY   -5  /* a device or host allocation failed */
+#define BHPP_DEVICE_ERROR    -6  /* HIP runtime error; sticky on the handle */
+#define BHPP_NOT_SUPPORTED   -7  /* unsupported dtype or option */
+#define BHPP_NO_CONVERGENCE  -8  /* the step limit of a query was reached */
+
+#define BHPP_DTYPE_F32 0        /* FP32 weights, residues and scores, FP32 accumulation */
+#define BHPP_DTYPE_F64 1        /* FP64 throughout */
+
+/* Graph build options. */
+typedef struct {
+    double alpha;       /* restart probability in (0,1) used for lambda (Lemma 4) */
+    int32_t tau;        /* PowerIteration rounds for lambda; < 0 selects the smallest tau
+                           with n_u (1-alpha)^(tau+1) <= 1 */
+    int32_t dtype;      /* BHPP_DTYPE_F32 or BHPP_DTYPE_F64; edge_w has this type */
+    uint32_t flags;     /* bitwise OR of BHPP_BUILD_* */
+} bhpp_graph_opts;
+
+/* Keep the external-id CSR/CSC after the build so bhpp_graph_export can return
+   them (doubles the structure memory). */
+#define BHPP_BUILD_KEEP_EXTERNAL 1u
+/* Do not renumber nodes by degree internally (identity order). */
+#define BHPP_BUILD_NO_REORDER    2u
+
+typedef struct bhpp_graph bhpp_graph;  /* opaque; owns all of its device memory */
+
+/* Per-query counters of the two sub-algorithms. */
+typedef struct {
+    int32_t ss_sel_iters;   /* selective push iterations of SS-Push (Algorithm 3) */
+    int32_t ss_seq_iters;   /* sequential push iterations of SS-Push */
+    int32_t pi_sel_iters;   /* selective push iterations of PI-Push (Algorithm 4) */
+    int32_t t;              /* PowerIteration rounds, Eq. (t); 0 if PI-Push returned early */
+    int32_t ss_switched;    /* 1 if Eq. (bwd-np) switched SS-Push to sequential pushes */
+    int32_t pi_returned;    /* 1 if Eq. (fwd-eps) ended PI-Push without power iterations */
+    int32_t steps;          /* two-hop sweeps executed for this source */
+    int32_t reserved;
+    double np_ss;           /* push cost n_p recorded by SS-Push (edges touched) */
+    double np_pi;           /* push cost n_p recorded by PI-Push */
+    double gamma;           /* Eq. (gamma) */
+    double sum_r_ss;        /* sum of the residue r when SS-Push returned */
+    double sum_rf;          /* sum of the forward residue entering PowerIteration */
+} bhpp_query_stats;
+
+/* Graph summary and preprocessing results (Lemma 4, Eq. (epsilon-b)). */
+typedef struct {
+    int32_t n_u, n_v;
+    int64_t n_edges;          /* distinct (u,v) pairs after merging duplicates */
+    int32_t isolated_u;       /* U nodes with no edge */
+    int32_t isolated_v;
+    int32_t dtype;
+    int32_t tau;              /* rounds used for lambda */
+    double alpha;             /* alpha that lambda was computed for */
+    double lambda;            /* Eq. (lambda) */
+    double mu;                /* sqrt(|U||V|)/|E| */
+    double eps_b_ratio;       /* eps_b / eps from Eq. (epsilon-b); 0.5 when mu >= 1 */
+    double ws_u_max, ws_u_min;/* over U nodes with at least one edge */
+    double build_ms;          /* device time of the build, preprocessing included */
+} bhpp_graph_info;
+
+/*
+ * Build the graph and run the preprocessing step (Sec. 3.1; Lemma 4;
+ * Eq. (epsilon-b); the paper excludes this step from query time, Sec. 5.4).
+ *   n_u, n_v       partition sizes (> 0)
+ *   n_edges        number of input edges (>= 0)
+ *   edge_u, edge_v device int32[n_edges], endpoint ids
+ *   edge_w         device float[n_edges] or double[n_edges] (opts->dtype), weights > 0
+ *   opts           host; NULL = {alpha 0.15, tau auto, F32, no flags}
+ *   out            host; receives the new handle
+ * Duplicate (u,v) pairs are merged by summing their weights in FP64 in input
+ * order. Input buffers are only read during the call and may be freed after
+ * the stream has synchronised. This call synchronises hip_stream.
+ * Errors: INVALID_ARG, OUT_OF_RANGE, BAD_WEIGHT, OUT_OF_MEMORY, DEVICE_ERROR,
+ * NOT_SUPPORTED (dtype).
+ */
+bhpp_status bhpp_build_graph(int32_t n_u, int32_t n_v, int64_t n_edges,
+                             const int32_t* edge_u, const int32_t* edge_v, const void* edge_w,
+                             const bhpp_graph_opts* opts, void* hip_stream, bhpp_graph** out);
+
+/*
+ * One eps-approximate BHPP query (Definition 1, Algorithm 5) from source u.
+ *   scores_out  device array of n_u values of the graph dtype; receives
+ *               beta'(u, x) for every x in U, including u itself.
+ *               Isolated x receive 0.
+ *   stats       host, nullable
+ * eps_b = eps * info.eps_b_ratio and eps_f = eps - eps_b (Algorithm 5).
+ * If alpha differs from the graph's alpha, lambda is recomputed for it and cached.
+ * Synchronises hip_stream before returning (phase control runs on the device;
+ * the host waits for the source to finish).
+ * Errors: INVALID_ARG, OUT_OF_RANGE, ISOLATED_SOURCE, NO_CONVERGENCE, DEVICE_ERROR.
+ */
+bhpp_status bhpp_query(bhpp_graph* g, int32_t source, double alpha, double eps,
+                       void* scores_out, bhpp_query_stats* stats, void* hip_stream);
+
+/*
+ * n_src independent queries executed together: up to 64 sources share every
+ * two-hop sweep as columns of one dense residue block, each source with its
+ * own phase, thresholds and stopping point.
+ *   sources      host int32[n_src]
+ *   eps          host double[n_src] (per-source error threshold) or NULL to use eps_all
+ *   scores_out   device [n_src][n_u] row-major of the graph dtype, or NULL
+ *   k            top-k size, 0 to skip top-k, else 1 <= k <= n_u - (exclude_self != 0)
+ *   exclude_self nonzero: the source itself is left out of its own top-k
+ *   topk_ids     device int32[n_src][k] (required if k > 0)
+ *   topk_vals    device [n_src][k] of the graph dtype (required if k > 0)
+ *   stats        host bhpp_query_stats[n_src], nullable
+ * Top-k order is (score descending, node id ascending). Synchronises hip_stream.
+ * Errors: as bhpp_query.
+ */
+bhpp_status bhpp_query_batch(bhpp_graph* g, int32_t n_src, const int32_t* sources,
+                             const double* eps, double alpha, double eps_all,
+                             void* scores_out, int32_t k, int32_t exclude_self,
+                             int32_t* topk_ids, void* topk_vals,
+                             bhpp_query_stats* stats, void* hip_stream);
+
+/*
+ * Top-k of each row of a score matrix, ordered by (score descending, id
+ * ascending); -0 ranks as +0. Used for the paper's retrieval of the nodes most
+ * similar to a query node (Sec. 1; Sec. 5).
+ *   scores       device [n_rows][n] row-major, float (dtype F32) or double (F64)
+ *   exclude_ids  device int32[n_rows] id to leave out per row (-1 none), or NULL
+ *   ids_out      device int32[n_rows][k]
+ *   vals_out     device [n_rows][k] of dtype
+ * Requires 1 <= k <= n (k <= n-1 for a row with an exclusion). Scores must
+ * not be NaN (the order of NaN is unspecified). Does not synchronise.
+ * Errors: INVALID_ARG, NOT_SUPPORTED, OUT_OF_MEMORY, DEVICE_ERROR.
+ */
+bhpp_status bhpp_topk(const void* scores, int32_t n_rows, int32_t n, int32_t k,
+                      const int32_t* exclude_ids, int32_t dtype,
+                      int32_t* ids_out, void* vals_out, void* hip_stream);
+
+/* Fill *out (host) with the graph summary. Errors: INVALID_ARG. */
+bhpp_status bhpp_graph_info(const bhpp_graph* g, bhpp_graph_info* out);
+
+/*
+ * Copy the external-id adjacency (requires BHPP_BUILD_KEEP_EXTERNAL):
+ * rows of U with ascending v (rp_u int64[n_u+1], ci_u int32[nnz], w_u), rows of
+ * V with ascending u (rp_v int64[n_v+1], ci_v int32[nnz], w_v), and the weighted
+ * degrees of Eq. (d) ws_u[n_u], ws_v[n_v], each summed in FP64 along the row
+ * in stored order and rounded once to the dtype. Weight and ws arrays have the
+ * graph dtype. All pointers are device. Synchronises hip_stream.
+ * Errors: INVALID_ARG, NOT_SUPPORTED (handle built without the flag), DEVICE_ERROR.
+ */
+bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u, void* w_u,
+                              int64_t* rp_v, int32_t* ci_v, void* w_v, void* ws_u, void* ws_v,
+                              void* hip_stream);
+
+/*
+ * Device-time profile of the two gather kernels of the two-hop sweep (the
+ * U->V half and the V->U half). While enabled, every launch of those kernels
+ * on a query stream is bracketed by HIP events on that stream and the elapsed
+ * times are accumulated; bhpp_profile_read synchronises and returns the
+ * totals: ms[0], launches[0] for the V-side half, ms[1], launches[1] for the
+ * U-side half, and the algorithmic bytes those launches moved in total
+ * (bytes[0..1]: per launch, the adjacency read once plus each dense vector
+ * read or written once). enable = 0 stops recording; enable = 1 also clears
+ * the totals.
+ */
+bhpp_status bhpp_profile_enable(bhpp_graph* g, int32_t enable);
+bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[2], int64_t launches[2], double bytes[2]);
+
+/* Free the handle and all device memory it owns (NULL is ignored). The caller
+   must make sure no work using it is still running. */
+void bhpp_free_graph(bhpp_graph* g);
+
+/* Static description of a status code. */
+const char* bhpp_status_string(bhpp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BHPP_H */

@@ -1,0 +1,561 @@
+/*
+ * FP64 CPU oracle for approximate BHPP queries.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this code. It shares no code, header
+ * or table with the GPU library, and the GPU library never calls it.
+ *
+ * It follows Yang, "Efficient and Effective Similarity Search over Bipartite
+ * Graphs" (WWW '22), in the paper's own notation:
+ *   ws(.)            weighted degree, Eq. (d)                        Sec. 3.1
+ *   U = D_U^-1 W, V = D_V^-1 W^T, P = U V (never formed here)         Sec. 3.1, Eq. (pmatrix)
+ *   pi(u,x) = sum_l alpha (1-alpha)^l P^l(u,x)                        Eq. (hpp)
+ *   PowerIteration                                                    Algorithm 1 (Sec. 3.3)
+ *   one push iteration (U->V then V->U)                               Algorithm 2 (Sec. 3.3)
+ *   SS-Push: selective pushes, budget Eq. (bwd-np), sequential pushes Algorithm 3 (Sec. 4.1)
+ *   PI-Push: thresholds ws(u)/ws(x) eps_f/lambda, Eq. (fwd-eps),
+ *            Eq. (gamma), Eq. (fwd-np), Eq. (fppr), Eq. (fresidue),
+ *            Eq. (t), then PowerIteration                              Algorithm 4 (Sec. 4.2)
+ *   Approx-BHPP: beta' = pi_f + pi_b                                  Algorithm 5 (Sec. 4.3)
+ *   lambda                                                            Lemma 4, Eq. (lambda)
+ *   eps_b                                                             Eq. (epsilon-b) (Sec. 4.3)
+ * Everything is FP64 and single-threaded per query; loops run over node ids in
+ * increasing order. The only parallelism is across independent queries.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int32_t nu, nv;
+    int64_t ne;              /* distinct edges after merging duplicates */
+    int64_t* rp_u;           /* CSR of W, rows = U: rp_u[nu+1] */
+    int32_t* ci_u;           /* neighbour v of each entry, ascending per row */
+    double* w_u;             /* w(u,v) */
+    int64_t* rp_v;           /* CSR of W^T, rows = V */
+    int32_t* ci_v;           /* neighbour u, ascending per row */
+    double* w_v;
+    double* ws_u;            /* Eq. (d), summed in the row order above */
+    double* ws_v;
+} orc_graph;
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ERANGE = -2, ORC_EISOLATED = -3, ORC_EWEIGHT = -4, ORC_ENOMEM = -5,
+       ORC_ENOCONV = -6 };
+
+/* A query needs O(log 1/eps) push iterations (Sec. 4.3); this cap only turns a
+ * runaway loop into an error. */
+#define ORC_MAX_ITERS 20000
+
+void orc_free(orc_graph* g) {
+    if (!g) return;
+    free(g->rp_u); free(g->ci_u); free(g->w_u);
+    free(g->rp_v); free(g->ci_v); free(g->w_v);
+    free(g->ws_u); free(g->ws_v);
+    free(g);
+}
+
+/* Stable counting sort of idx[0..n) by key[idx[i]] in [0, nk). */
+static int counting_sort(const int32_t* key, int32_t nk, const int64_t* idx, int64_t n, int64_t* out) {
+    int64_t* cnt = (int64_t*)calloc((size_t)nk + 1, sizeof(int64_t));
+    if (!cnt) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; ++i) cnt[key[idx[i]] + 1]++;
+    for (int32_t k = 0; k < nk; ++k) cnt[k + 1] += cnt[k];
+    for (int64_t i = 0; i < n; ++i) out[cnt[key[idx[i]]]++] = idx[i];
+    free(cnt);
+    return ORC_OK;
+}
+
+/*
+ * Build both adjacency directions of the undirected bipartite graph (Sec. 3.1).
+ * Duplicate (u,v) pairs are merged by summing their weights in input order.
+ * Returns NULL and sets *err on failure.
+ */
+orc_graph* orc_build(int32_t nu, int32_t nv, int64_t ne, const int32_t* eu, const int32_t* ev,
+                     const double* w, int* err) {
+    *err = ORC_OK;
+    if (nu <= 0 || nv <= 0 || ne < 0) { *err = ORC_EINVAL; return NULL; }
+    for (int64_t i = 0; i < ne; ++i) {
+        if (eu[i] < 0 || eu[i] >= nu || ev[i] < 0 || ev[i] >= nv) { *err = ORC_ERANGE; return NULL; }
+        if (!(w[i] > 0.0) || !isfinite(w[i])) { *err = ORC_EWEIGHT; return NULL; }
+    }
+    orc_graph* g = (orc_graph*)calloc(1, sizeof(orc_graph));
+    int64_t* a = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne > 0 ? ne : 1));
+    int64_t* b = (int64_t*)malloc(sizeof(int64_t) * (size_t)(ne > 0 ? ne : 1));
+    if (!g || !a || !b) { *err = ORC_ENOMEM; free(a); free(b); orc_free(g); return NULL; }
+    g->nu = nu; g->nv = nv;
+    for (int64_t i = 0; i < ne; ++i) a[i] = i;
+    /* LSD: stable by v, then stable by u => ordered by (u, v, input position) */
+    if (counting_sort(ev, nv, a, ne, b) || counting_sort(eu, nu, b, ne, a)) {
+        *err = ORC_ENOMEM; free(a); free(b); orc_free(g); return NULL;
+    }
+    /* merge duplicates */
+    int64_t m = 0;
+    int32_t* su = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+    int32_t* sv = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ne > 0 ? ne : 1));
+    double* sw = (double*)malloc(sizeof(double) * (size_t)(ne > 0 ? ne : 1));
+    if (!su || !sv || !sw) { *err = ORC_ENOMEM; return NULL; }
+    for (int64_t i = 0; i < ne; ++i) {
+        int64_t e = a[i];
+        if (m > 0 && su[m - 1] == eu[e] && sv[m - 1] == ev[e]) {
+            sw[m - 1] += w[e];
+        } else {
+            su[m] = eu[e]; sv[m] = ev[e]; sw[m] = w[e]; ++m;
+        }
+    }
+    g->ne = m;
+    g->rp_u = (int64_t*)calloc((size_t)nu + 1, sizeof(int64_t));
+    g->rp_v = (int64_t*)calloc((size_t)nv + 1, sizeof(int64_t));
+    g->ci_u = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    g->ci_v = (int32_t*)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    g->w_u = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    g->w_v = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    g->ws_u = (double*)calloc((size_t)nu, sizeof(double));
+    g->ws_v = (double*)calloc((size_t)nv, sizeof(double));
+    if (!g->rp_u || !g->rp_v || !g->ci_u || !g->ci_v || !g->w_u || !g->w_v || !g->ws_u || !g->ws_v) {
+        *err = ORC_ENOMEM; orc_free(g); return NULL;
+    }
+    for (int64_t i = 0; i < m; ++i) {
+        g->rp_u[su[i] + 1]++;
+        g->rp_v[sv[i] + 1]++;
+        g->ci_u[i] = sv[i];
+        g->w_u[i] = sw[i];
+    }
+    for (int32_t x = 0; x < nu; ++x) g->rp_u[x + 1] += g->rp_u[x];
+    for (int32_t y = 0; y < nv; ++y) g->rp_v[y + 1] += g->rp_v[y];
+    /* transpose: walking CSR rows in order keeps each V row sorted by u */
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)nv);
+    if (!fill) { *err = ORC_ENOMEM; orc_free(g); return NULL; }
+    for (int32_t y = 0; y < nv; ++y) fill[y] = g->rp_v[y];
+    for (int64_t i = 0; i < m; ++i) {
+        int64_t p = fill[sv[i]]++;
+        g->ci_v[p] = su[i];
+        g->w_v[p] = sw[i];
+    }
+    free(fill);
+    /* Eq. (d): weighted degrees, summed along each row in stored order */
+    for (int32_t x = 0; x < nu; ++x) {
+        double s = 0.0;
+        for (int64_t p = g->rp_u[x]; p < g->rp_u[x + 1]; ++p) s += g->w_u[p];
+        g->ws_u[x] = s;
+    }
+    for (int32_t y = 0; y < nv; ++y) {
+        double s = 0.0;
+        for (int64_t p = g->rp_v[y]; p < g->rp_v[y + 1]; ++p) s += g->w_v[p];
+        g->ws_v[y] = s;
+    }
+    free(a); free(b); free(su); free(sv); free(sw);
+    return g;
+}
+
+int64_t orc_nnz(const orc_graph* g) { return g->ne; }
+
+void orc_export(const orc_graph* g, int64_t* rp_u, int32_t* ci_u, double* w_u, int64_t* rp_v,
+                int32_t* ci_v, double* w_v, double* ws_u, double* ws_v) {
+    memcpy(rp_u, g->rp_u, sizeof(int64_t) * ((size_t)g->nu + 1));
+    memcpy(rp_v, g->rp_v, sizeof(int64_t) * ((size_t)g->nv + 1));
+    memcpy(ci_u, g->ci_u, sizeof(int32_t) * (size_t)g->ne);
+    memcpy(ci_v, g->ci_v, sizeof(int32_t) * (size_t)g->ne);
+    memcpy(w_u, g->w_u, sizeof(double) * (size_t)g->ne);
+    memcpy(w_v, g->w_v, sizeof(double) * (size_t)g->ne);
+    memcpy(ws_u, g->ws_u, sizeof(double) * (size_t)g->nu);
+    memcpy(ws_v, g->ws_v, sizeof(double) * (size_t)g->nv);
+}
+
+/* ---------------------------------------------------------------------------
+ * Row-vector and column-vector products with P = U V, without forming P.
+ * ------------------------------------------------------------------------- */
+
+/* out = p * U * V  (row vector p over U; Algorithm 1's (pi U) V) */
+static void row_times_P(const orc_graph* g, const double* p, double* tmp_v, double* out) {
+    for (int32_t y = 0; y < g->nv; ++y) {        /* (p U)(v) = sum_x p(x) w(x,v)/ws(x) */
+        double s = 0.0;
+        for (int64_t q = g->rp_v[y]; q < g->rp_v[y + 1]; ++q) {
+            int32_t x = g->ci_v[q];
+            s += p[x] * g->w_v[q] / g->ws_u[x];
+        }
+        tmp_v[y] = s;
+    }
+    for (int32_t x = 0; x < g->nu; ++x) {        /* ((pU) V)(x) = sum_v (pU)(v) w(v,x)/ws(v) */
+        double s = 0.0;
+        for (int64_t q = g->rp_u[x]; q < g->rp_u[x + 1]; ++q) {
+            int32_t y = g->ci_u[q];
+            s += tmp_v[y] * g->w_u[q] / g->ws_v[y];
+        }
+        out[x] = s;
+    }
+}
+
+/* out = P * c  (column vector c over U): (P c)(x) = sum_v U(x,v) sum_y V(v,y) c(y) */
+static void P_times_col(const orc_graph* g, const double* c, double* tmp_v, double* out) {
+    for (int32_t y = 0; y < g->nv; ++y) {
+        double s = 0.0;
+        for (int64_t q = g->rp_v[y]; q < g->rp_v[y + 1]; ++q) s += g->w_v[q] * c[g->ci_v[q]];
+        tmp_v[y] = g->ws_v[y] > 0.0 ? s / g->ws_v[y] : 0.0;
+    }
+    for (int32_t x = 0; x < g->nu; ++x) {
+        if (g->ws_u[x] == 0.0) { out[x] = 0.0; continue; }
+        double s = 0.0;
+        for (int64_t q = g->rp_u[x]; q < g->rp_u[x + 1]; ++q) s += g->w_u[q] * tmp_v[g->ci_u[q]];
+        out[x] = s / g->ws_u[x];
+    }
+}
+
+/*
+ * Algorithm 1 (PowerIteration): pi <- e; t times pi <- e + (1-alpha) (pi U) V;
+ * return alpha * pi. e and out are row vectors over U; out may alias nothing.
+ */
+int orc_power_iteration(const orc_graph* g, const double* e, double alpha, int32_t t, double* out) {
+    double* pi = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    double* nx = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    double* tv = (double*)malloc(sizeof(double) * (size_t)g->nv);
+    if (!pi || !nx || !tv) { free(pi); free(nx); free(tv); return ORC_ENOMEM; }
+    memcpy(pi, e, sizeof(double) * (size_t)g->nu);
+    for (int32_t i = 1; i <= t; ++i) {
+        row_times_P(g, pi, tv, nx);
+        for (int32_t x = 0; x < g->nu; ++x) pi[x] = e[x] + (1.0 - alpha) * nx[x];
+    }
+    for (int32_t x = 0; x < g->nu; ++x) out[x] = alpha * pi[x];
+    free(pi); free(nx); free(tv);
+    return ORC_OK;
+}
+
+/* Number of series terms L so that the dropped mass (1-alpha)^(L+1) <= tail. */
+static int32_t series_terms(double alpha, double tail) {
+    int32_t L = 0;
+    double m = 1.0 - alpha;
+    while (m > tail) { m *= (1.0 - alpha); ++L; }
+    return L;
+}
+
+/*
+ * Eq. (hpp) summed directly as a truncated series, forward direction:
+ * out(x) = sum_{l=0..L} alpha (1-alpha)^l (e_u P^l)(x), i.e. pi(u, x).
+ * Every entry is short of the exact value by at most the tail (1-alpha)^(L+1).
+ */
+int orc_hpp_forward(const orc_graph* g, int32_t u, double alpha, double tail, double* out, int32_t* terms) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    int32_t L = series_terms(alpha, tail);
+    double* p = (double*)calloc((size_t)g->nu, sizeof(double));
+    double* nx = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    double* tv = (double*)malloc(sizeof(double) * (size_t)g->nv);
+    if (!p || !nx || !tv) { free(p); free(nx); free(tv); return ORC_ENOMEM; }
+    p[u] = 1.0;
+    double c = alpha;
+    for (int32_t x = 0; x < g->nu; ++x) out[x] = c * p[x];
+    for (int32_t l = 1; l <= L; ++l) {
+        if (g->ws_u[u] == 0.0) break;
+        row_times_P(g, p, tv, nx);
+        double* t = p; p = nx; nx = t;
+        c *= (1.0 - alpha);
+        for (int32_t x = 0; x < g->nu; ++x) out[x] += c * p[x];
+    }
+    if (terms) *terms = L;
+    free(p); free(nx); free(tv);
+    return ORC_OK;
+}
+
+/* Eq. (hpp), backward direction: out(x) = pi(x, u) = sum_l alpha (1-alpha)^l (P^l e_u)(x). */
+int orc_hpp_backward(const orc_graph* g, int32_t u, double alpha, double tail, double* out, int32_t* terms) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    int32_t L = series_terms(alpha, tail);
+    double* c = (double*)calloc((size_t)g->nu, sizeof(double));
+    double* nx = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    double* tv = (double*)malloc(sizeof(double) * (size_t)g->nv);
+    if (!c || !nx || !tv) { free(c); free(nx); free(tv); return ORC_ENOMEM; }
+    c[u] = 1.0;
+    double k = alpha;
+    for (int32_t x = 0; x < g->nu; ++x) out[x] = k * c[x];
+    for (int32_t l = 1; l <= L; ++l) {
+        P_times_col(g, c, tv, nx);
+        double* t = c; c = nx; nx = t;
+        k *= (1.0 - alpha);
+        for (int32_t x = 0; x < g->nu; ++x) out[x] += k * c[x];
+    }
+    if (terms) *terms = L;
+    free(c); free(nx); free(tv);
+    return ORC_OK;
+}
+
+int orc_hpp_forward_many(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double tail,
+                         double* out, int32_t nthreads) {
+    int rc = ORC_OK;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
+    for (int32_t i = 0; i < n; ++i) {
+        int r = orc_hpp_forward(g, src[i], alpha, tail, out + (size_t)i * (size_t)g->nu, NULL);
+        if (r != ORC_OK) rc = r;
+    }
+    (void)nthreads;
+    return rc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Preprocessing: Lemma 4 and Eq. (epsilon-b)
+ * ------------------------------------------------------------------------- */
+
+/* Eq. (epsilon-b): eps_b = eps (1-mu)/(2-mu), mu = sqrt(|U||V|)/|E|; if mu >= 1
+ * the formula leaves (0, eps), and eps/2 is used instead. */
+double orc_eps_b(int32_t nu, int32_t nv, int64_t ne, double eps) {
+    double mu = sqrt((double)nu * (double)nv) / (double)ne;
+    if (!(mu < 1.0)) return 0.5 * eps;
+    return eps * (1.0 - mu) / (2.0 - mu);
+}
+
+/* tau for Lemma 4: the smallest tau with |U| (1-alpha)^(tau+1) <= 1 */
+int32_t orc_default_tau(int32_t nu, double alpha) {
+    int32_t tau = 0;
+    double m = (double)nu * (1.0 - alpha);
+    while (m > 1.0) { m *= (1.0 - alpha); ++tau; }
+    return tau;
+}
+
+/*
+ * Lemma 4, Eq. (lambda): rho = PowerIteration(e = 1, t = tau);
+ * lambda = min(max rho + |U| (1-alpha)^(tau+1), max ws / min ws), where the
+ * ws ratio runs over nodes with ws > 0 (an isolated node's column sum is alpha).
+ */
+int orc_lambda(const orc_graph* g, double alpha, int32_t tau, double* lambda_out, double* rho_max_out) {
+    double* one = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    double* rho = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    if (!one || !rho) { free(one); free(rho); return ORC_ENOMEM; }
+    for (int32_t x = 0; x < g->nu; ++x) one[x] = 1.0;
+    int rc = orc_power_iteration(g, one, alpha, tau, rho);
+    if (rc) { free(one); free(rho); return rc; }
+    double rmax = 0.0, wmax = 0.0, wmin = INFINITY;
+    for (int32_t x = 0; x < g->nu; ++x) {
+        if (rho[x] > rmax) rmax = rho[x];
+        if (g->ws_u[x] > 0.0) {
+            if (g->ws_u[x] > wmax) wmax = g->ws_u[x];
+            if (g->ws_u[x] < wmin) wmin = g->ws_u[x];
+        }
+    }
+    double a = rmax + (double)g->nu * pow(1.0 - alpha, (double)tau + 1.0);
+    double b = wmax / wmin;
+    *lambda_out = a < b ? a : b;
+    if (rho_max_out) *rho_max_out = rmax;
+    free(one); free(rho);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Approx-BHPP (Algorithms 2-5)
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    int32_t ss_sel_iters, ss_seq_iters, pi_sel_iters, t;
+    int32_t ss_switched;     /* 1 if Eq. (bwd-np) sent SS-Push to sequential pushes */
+    int32_t pi_returned;     /* 1 if Eq. (fwd-eps) ended PI-Push (no power iterations) */
+    double np_ss, np_pi;     /* push cost n_p recorded in each algorithm */
+    double gamma;            /* Eq. (gamma) */
+    double sum_r_ss;         /* sum of r when SS-Push returned */
+    double sum_rf;           /* sum of the forward residue entering PowerIteration */
+} orc_stats;
+
+/* phase ids passed to the trace callback */
+enum { PH_SS_SEL = 0, PH_SS_SEQ = 1, PH_PI_SEL = 2 };
+typedef void (*orc_trace_fn)(void* ctx, int32_t phase, int32_t iter, const double* pi_b, const double* r);
+
+typedef struct {
+    double* r;     /* residue on U */
+    double* rv;    /* residue on V */
+    double* pib;   /* pi_b(x, u) */
+    double* thr;   /* per-node push threshold of the current phase */
+    double* tmp;
+} orc_work;
+
+static void work_free(orc_work* w) { free(w->r); free(w->rv); free(w->pib); free(w->thr); free(w->tmp); }
+
+static int work_alloc(orc_work* w, const orc_graph* g) {
+    memset(w, 0, sizeof(*w));
+    w->r = (double*)calloc((size_t)g->nu, sizeof(double));
+    w->rv = (double*)calloc((size_t)g->nv, sizeof(double));
+    w->pib = (double*)calloc((size_t)g->nu, sizeof(double));
+    w->thr = (double*)calloc((size_t)g->nu, sizeof(double));
+    w->tmp = (double*)calloc((size_t)g->nu, sizeof(double));
+    if (!w->r || !w->rv || !w->pib || !w->thr || !w->tmp) { work_free(w); return ORC_ENOMEM; }
+    return ORC_OK;
+}
+
+/*
+ * One iteration of Algorithm 2's loop body with per-node threshold thr:
+ * every x in U with r(x) > thr(x) gives alpha r(x) to pi_b(x) and sends
+ * (1-alpha) w(x,v)/ws(v) r(x) to each neighbour v, then r(x) <- 0; next every v
+ * in V with r(v) > 0 sends w(y,v)/ws(y) r(v) to each neighbour y, then r(v) <- 0.
+ * The U loop changes only V residues and the pushed node's own residue, so
+ * testing r(x) while walking x in id order selects exactly the nodes that were
+ * above threshold when the loop started. Returns the edges touched (n_p).
+ */
+static double push_iteration(const orc_graph* g, orc_work* w, double alpha) {
+    double np = 0.0;
+    for (int32_t x = 0; x < g->nu; ++x) {
+        double rx = w->r[x];
+        if (!(rx > w->thr[x])) continue;
+        for (int64_t q = g->rp_u[x]; q < g->rp_u[x + 1]; ++q) {
+            int32_t v = g->ci_u[q];
+            w->rv[v] += (1.0 - alpha) * g->w_u[q] / g->ws_v[v] * rx;
+        }
+        w->pib[x] += alpha * rx;
+        w->r[x] = 0.0;
+        np += (double)(g->rp_u[x + 1] - g->rp_u[x]);
+    }
+    for (int32_t v = 0; v < g->nv; ++v) {
+        double rv = w->rv[v];
+        if (!(rv > 0.0)) continue;
+        for (int64_t q = g->rp_v[v]; q < g->rp_v[v + 1]; ++q) {
+            int32_t y = g->ci_v[q];
+            w->r[y] += g->w_v[q] / g->ws_u[y] * rv;
+        }
+        w->rv[v] = 0.0;
+        np += (double)(g->rp_v[v + 1] - g->rp_v[v]);
+    }
+    return np;
+}
+
+static double log_base(double alpha, double x) { return log(x) / log(1.0 / (1.0 - alpha)); }
+
+int32_t orc_t(double sum_rf, double eps_f, double alpha);
+
+/*
+ * Algorithm 5 for source u. Outputs (each |U| doubles, NULL to skip):
+ *   beta   = beta'(u, x)
+ *   pi_f   = the forward estimate of pi(u, x)  (Algorithm 4's output)
+ *   pi_b   = the backward estimate of pi(x, u) (after PI-Push's pushes)
+ */
+int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, double eps_b, double lambda,
+                    double* beta, double* pi_f_out, double* pi_b_out, orc_stats* st,
+                    orc_trace_fn trace, void* ctx) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    if (!(alpha > 0.0 && alpha < 1.0) || !(eps > 0.0) || !(eps_b > 0.0 && eps_b < eps) || !(lambda > 0.0))
+        return ORC_EINVAL;
+    if (g->ws_u[u] == 0.0) return ORC_EISOLATED;
+    orc_stats s;
+    memset(&s, 0, sizeof(s));
+    orc_work w;
+    if (work_alloc(&w, g)) return ORC_ENOMEM;
+    const int32_t nu = g->nu;
+    const double E2 = 2.0 * (double)g->ne;
+    const double wsu = g->ws_u[u];
+
+    /* ---- Algorithm 3 (SS-Push), target u ---- */
+    w.r[u] = 1.0;
+    for (int32_t x = 0; x < nu; ++x) w.thr[x] = eps_b;
+    double np = 0.0;
+    int ss_done = 0;
+    int32_t iters = 0;
+    for (;;) {                                   /* selective pushes */
+        if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
+        np += push_iteration(g, &w, alpha);
+        ++s.ss_sel_iters;
+        if (trace) trace(ctx, PH_SS_SEL, s.ss_sel_iters, w.pib, w.r);
+        double rmax = 0.0, rsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) { if (w.r[x] > rmax) rmax = w.r[x]; rsum += w.r[x]; }
+        if (rmax <= eps_b || rsum <= eps_b) { ss_done = 1; break; }
+        if (np >= E2 * log_base(alpha, 1.0 / rsum)) break;   /* Eq. (bwd-np) */
+    }
+    s.np_ss = np;
+    if (!ss_done) {
+        s.ss_switched = 1;
+        for (int32_t x = 0; x < nu; ++x) w.thr[x] = 0.0;     /* eps_b replaced by 0 */
+        for (;;) {                               /* sequential pushes */
+            double rmax = 0.0, rsum = 0.0;
+            for (int32_t x = 0; x < nu; ++x) { if (w.r[x] > rmax) rmax = w.r[x]; rsum += w.r[x]; }
+            if (!(rmax > eps_b && rsum > eps_b)) break;
+            if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
+            s.np_ss += push_iteration(g, &w, alpha);
+            ++s.ss_seq_iters;
+            if (trace) trace(ctx, PH_SS_SEQ, s.ss_seq_iters, w.pib, w.r);
+        }
+    }
+    {
+        double rsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) rsum += w.r[x];
+        s.sum_r_ss = rsum;
+    }
+
+    /* ---- Algorithm 4 (PI-Push), source u ---- */
+    const double eps_f = eps - eps_b;            /* Algorithm 5 */
+    double gamma = 0.0;                          /* Eq. (gamma) */
+    for (int32_t x = 0; x < nu; ++x) gamma += g->ws_u[x] / wsu * w.r[x];
+    s.gamma = gamma;
+    for (int32_t x = 0; x < nu; ++x)             /* threshold ws(u)/ws(x) eps_f/lambda */
+        w.thr[x] = g->ws_u[x] > 0.0 ? wsu / g->ws_u[x] * eps_f / lambda : INFINITY;
+    np = 0.0;
+    int pi_returned = 0;
+    for (;;) {
+        if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
+        np += push_iteration(g, &w, alpha);
+        ++s.pi_sel_iters;
+        if (trace) trace(ctx, PH_PI_SEL, s.pi_sel_iters, w.pib, w.r);
+        int all_below = 1;                       /* Eq. (fwd-eps) for every node */
+        double fsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) {
+            if (w.r[x] > w.thr[x]) all_below = 0;
+            fsum += g->ws_u[x] / wsu * w.r[x];
+        }
+        if (all_below) { pi_returned = 1; break; }
+        if (np >= E2 * log_base(alpha, gamma / fsum)) break; /* Eq. (fwd-np) */
+    }
+    s.np_pi = np;
+    s.pi_returned = pi_returned;
+    double* pif = w.tmp;
+    for (int32_t x = 0; x < nu; ++x) pif[x] = g->ws_u[x] / wsu * w.pib[x];   /* Eq. (fppr) */
+    if (!pi_returned) {
+        double* rf = (double*)malloc(sizeof(double) * (size_t)nu);
+        double* pr = (double*)malloc(sizeof(double) * (size_t)nu);
+        if (!rf || !pr) { free(rf); free(pr); work_free(&w); return ORC_ENOMEM; }
+        double fsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) { rf[x] = g->ws_u[x] / wsu * w.r[x]; fsum += rf[x]; }  /* Eq. (fresidue) */
+        s.sum_rf = fsum;
+        int32_t t = orc_t(fsum, eps_f, alpha);                                              /* Eq. (t) */
+        s.t = t;
+        int rc = orc_power_iteration(g, rf, alpha, t, pr);                                   /* Algorithm 1 */
+        if (rc) { free(rf); free(pr); work_free(&w); return rc; }
+        for (int32_t x = 0; x < nu; ++x) pif[x] += pr[x];
+        free(rf); free(pr);
+    }
+
+    /* ---- Algorithm 5, combine ---- */
+    if (beta) for (int32_t x = 0; x < nu; ++x) beta[x] = pif[x] + w.pib[x];
+    if (pi_f_out) memcpy(pi_f_out, pif, sizeof(double) * (size_t)nu);
+    if (pi_b_out) memcpy(pi_b_out, w.pib, sizeof(double) * (size_t)nu);
+    if (st) *st = s;
+    work_free(&w);
+    return ORC_OK;
+}
+
+/* Independent queries over a thread pool: the CPU baseline. */
+int orc_approx_bhpp_many(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double eps,
+                         double eps_b, double lambda, double* beta, orc_stats* st, int32_t nthreads) {
+    int rc = ORC_OK;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
+    for (int32_t i = 0; i < n; ++i) {
+        int r = orc_approx_bhpp(g, src[i], alpha, eps, eps_b, lambda,
+                                beta ? beta + (size_t)i * (size_t)g->nu : NULL, NULL, NULL,
+                                st ? st + i : NULL, NULL, NULL);
+        if (r != ORC_OK) rc = r;
+    }
+    (void)nthreads;
+    return rc;
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Eq. (t) rounded up and clamped at 0: the smallest integer t with
+ * (1-alpha)^(t+1) * sum_rf <= eps_f, which is what the proof of Theorem 2 needs. */
+int32_t orc_t(double sum_rf, double eps_f, double alpha) {
+    double tr = ceil(log_base(alpha, sum_rf / eps_f) - 1.0);
+    return tr > 0.0 ? (int32_t)tr : 0;
+}

@@ -1,0 +1,127 @@
+"""Pins of the FP64 oracle against facts other than itself (CPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from pins_lib import (pin_closed_forms, pin_dense_invariants, pin_eps_b, pin_golden_gamma,
+                      pin_golden_rounds, pin_lambda, pin_lemma1_and_mass, pin_power_mass,
+                      pin_random_walk, pin_series_agree, pin_theorems)
+
+
+def test_closed_forms():
+    assert pin_closed_forms() == []
+
+
+def test_random_walk_simulation():
+    assert pin_random_walk() == []
+
+
+def test_dense_invariants(small_graph):
+    assert pin_dense_invariants(small_graph["Pi"], small_graph["ws"]) == []
+
+
+def test_series_forward_backward_lemma3(small_graph):
+    s = small_graph
+    assert pin_series_agree(s["g"], s["sources"], s["wl"].alpha) == []
+
+
+def test_series_match_dense(small_graph):
+    s = small_graph
+    for u in s["sources"][:4]:
+        u = int(u)
+        assert np.allclose(s["g"].hpp_forward(u, 0.15, 1e-14), s["Pi"][u, :], atol=1e-12)
+        assert np.allclose(s["g"].hpp_backward(u, 0.15, 1e-14), s["Pi"][:, u], atol=1e-12)
+
+
+def test_theorems_every_source(small_graph):
+    s = small_graph
+    out, seen = pin_theorems(s["g"], s["Pi"], s["sources"], s["wl"].alpha, [1e-2, 1e-4, 1e-7])
+    assert out == []
+    # every branch of Algorithms 3-4 was exercised by these queries
+    assert any(st["ss_switched"] for st in seen) and any(not st["ss_switched"] for st in seen)
+    assert any(st["t"] > 0 for st in seen)
+
+
+def test_pi_push_early_return_branch():
+    """Eq. (fwd-eps) ending PI-Push (no power iterations) is exercised by the
+    closed-form graphs, where the theorem bands were checked above."""
+    from pins_lib import CLOSED_FORMS
+    hits = 0
+    for mk in CLOSED_FORMS.values():
+        (nu, nv, eu, ev, w), _ = mk()
+        g = oracle.Graph(nu, nv, eu, ev, w)
+        hits += sum(g.approx_bhpp(u, 0.15, 1e-2)[3]["pi_returned"] for u in range(nu))
+    assert hits > 0
+
+
+@pytest.mark.parametrize("k", [0, 1, 5])
+def test_lemma1_every_iteration(small_graph, k):
+    s = small_graph
+    assert pin_lemma1_and_mass(s["g"], s["Pi"], int(s["sources"][k]), 0.15, 1e-7) == []
+
+
+def test_lambda_lemma4(small_graph):
+    s = small_graph
+    assert pin_lambda(s["g"], s["Pi"], 0.15) == []
+
+
+def test_power_iteration_mass(small_graph):
+    assert pin_power_mass(small_graph["g"], 0.15) == []
+
+
+def test_golden_gamma_fig1(small_graph):
+    s = small_graph
+    assert pin_golden_gamma(s["g"], s["sources"], 0.15) == []
+
+
+def test_golden_power_rounds():
+    assert pin_golden_rounds() == []
+
+
+def test_eps_b_closed_form():
+    assert pin_eps_b() == []
+
+
+def test_gamma_decreases_with_eps_b(small_graph):
+    """Sec. 4.3: as eps_b decreases and SS-Push progresses, gamma decreases (Fig. 1)."""
+    g = small_graph["g"]
+    for u in small_graph["sources"][:4]:
+        gam = []
+        for eb in (0.5, 0.1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+            gam.append(g.approx_bhpp(int(u), 0.15, 2 * eb, eps_b=eb)[3]["gamma"])
+        assert all(b <= a + 1e-12 for a, b in zip(gam, gam[1:])), gam
+
+
+def test_random_graphs_theorem3():
+    """Theorem 3 on several random graphs, including ones with isolated nodes
+    and hub-heavy degree sequences."""
+    import synth
+    for seed, (nu, nv, ne, gam) in enumerate([(50, 80, 300, 2.1), (200, 40, 900, 2.5),
+                                               (120, 300, 400, 2.05)]):
+        el = synth.chung_lu(nu, nv, ne, gam, "lognormal", 90 + seed)
+        g = oracle.Graph.from_edges(el)
+        Pi, _, ws = oracle.exact_dense(nu, nv, el.u, el.v, el.w, 0.15)
+        assert pin_dense_invariants(Pi, ws) == []
+        src = np.nonzero(ws > 0)[0][:10]
+        out, _ = pin_theorems(g, Pi, src, 0.15, [1e-3, 1e-8])
+        assert out == []
+        assert pin_lambda(g, Pi, 0.15) == []
+
+
+def test_isolated_source_rejected():
+    import synth
+    el = synth.chung_lu(40, 60, 50, 2.1, "int10", 4)
+    g = oracle.Graph.from_edges(el)
+    iso = np.nonzero(g.ws_u == 0)[0]
+    assert iso.size > 0
+    with pytest.raises(ValueError, match="isolated"):
+        g.approx_bhpp(int(iso[0]), 0.15, 1e-4)
+
+
+def test_topk_bruteforce_hand_example():
+    # ties broken by ascending id, -0 ranks as +0, excluded id left out
+    s = np.array([0.5, 0.7, 0.7, -0.0, 0.0, 0.1])
+    ids, vals = oracle.topk_bruteforce(s, 4, exclude=1)
+    assert ids.tolist() == [2, 0, 5, 3]
+    ids, _ = oracle.topk_bruteforce(s, 6, exclude=-1)
+    assert ids.tolist() == [1, 2, 0, 5, 3, 4]
