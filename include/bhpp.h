@@ -99,7 +99,7 @@ typedef struct {
     double eps_b_ratio;       /* eps_b / eps from Eq. (epsilon-b); 0.5 when mu >= 1 */
     double ws_u_max, ws_u_min;/* over U nodes with at least one edge */
     double build_ms;          /* device time of the build, preprocessing included */
-} bhpp_graph_info;
+} bhpp_graph_summary;
 
 /*
  * Build the graph and run the preprocessing step (Sec. 3.1; Lemma 4;
@@ -173,7 +173,7 @@ bhpp_status bhpp_topk(const void* scores, int32_t n_rows, int32_t n, int32_t k,
                       int32_t* ids_out, void* vals_out, void* hip_stream);
 
 /* Fill *out (host) with the graph summary. Errors: INVALID_ARG. */
-bhpp_status bhpp_graph_info(const bhpp_graph* g, bhpp_graph_info* out);
+bhpp_status bhpp_graph_info(const bhpp_graph* g, bhpp_graph_summary* out);
 
 /*
  * Copy the external-id adjacency (requires BHPP_BUILD_KEEP_EXTERNAL):

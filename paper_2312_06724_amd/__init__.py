@@ -1,0 +1,251 @@
+"""MI355X (gfx950) approximate BHPP queries: Python binding of libbhpp.so.
+
+The binding only marshals arguments: device buffers come from PyTorch tensors
+(``data_ptr``) and work is enqueued on torch's current HIP stream. Every step
+of the computation runs in the HIP kernels of ``csrc/``; there is no CPU
+fallback. Importing works without a GPU (for symbol checks); any call that
+needs the device fails loudly when the library or the GPU is missing.
+
+Method: Yang, "Efficient and Effective Similarity Search over Bipartite
+Graphs", WWW '22 (Algorithms 1-5).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libbhpp.so")
+
+STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range", -3: "source node has no edge",
+          -4: "edge weight not finite and positive", -5: "out of memory", -6: "HIP device error",
+          -7: "not supported", -8: "step limit reached"}
+
+DTYPE_F32, DTYPE_F64 = 0, 1
+BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER = 1, 2
+
+# names exported by include/bhpp.h
+EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
+            "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_free_graph",
+            "bhpp_status_string"]
+
+
+class BhppError(RuntimeError):
+    def __init__(self, code, where=""):
+        self.code = code
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code})")
+
+
+class GraphOpts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tau", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [("ss_sel_iters", ctypes.c_int32), ("ss_seq_iters", ctypes.c_int32),
+                ("pi_sel_iters", ctypes.c_int32), ("t", ctypes.c_int32),
+                ("ss_switched", ctypes.c_int32), ("pi_returned", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("np_ss", ctypes.c_double), ("np_pi", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("sum_r_ss", ctypes.c_double), ("sum_rf", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class GraphSummary(ctypes.Structure):
+    _fields_ = [("n_u", ctypes.c_int32), ("n_v", ctypes.c_int32), ("n_edges", ctypes.c_int64),
+                ("isolated_u", ctypes.c_int32), ("isolated_v", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("tau", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("mu", ctypes.c_double),
+                ("eps_b_ratio", ctypes.c_double), ("ws_u_max", ctypes.c_double),
+                ("ws_u_min", ctypes.c_double), ("build_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
+
+
+_lib = None
+
+
+def load_library():
+    """Load libbhpp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() or "
+                           "python paper_2312_06724_amd/build_lib.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.bhpp_build_graph.restype = I32
+    L.bhpp_build_graph.argtypes = [I32, I32, I64, P, P, P, ctypes.POINTER(GraphOpts), P, ctypes.POINTER(P)]
+    L.bhpp_query.restype = I32
+    L.bhpp_query.argtypes = [P, I32, D, D, P, ctypes.POINTER(QueryStats), P]
+    L.bhpp_query_batch.restype = I32
+    L.bhpp_query_batch.argtypes = [P, I32, P, P, D, D, P, I32, I32, P, P, P, P]
+    L.bhpp_topk.restype = I32
+    L.bhpp_topk.argtypes = [P, I32, I32, I32, P, I32, P, P, P]
+    L.bhpp_graph_info.restype = I32
+    L.bhpp_graph_info.argtypes = [P, ctypes.POINTER(GraphSummary)]
+    L.bhpp_graph_export.restype = I32
+    L.bhpp_graph_export.argtypes = [P] * 9 + [P]
+    L.bhpp_profile_enable.restype = I32
+    L.bhpp_profile_enable.argtypes = [P, I32]
+    L.bhpp_profile_read.restype = I32
+    L.bhpp_profile_read.argtypes = [P, P, P, P]
+    L.bhpp_free_graph.restype = None
+    L.bhpp_free_graph.argtypes = [P]
+    L.bhpp_status_string.restype = ctypes.c_char_p
+    L.bhpp_status_string.argtypes = [I32]
+    _lib = L
+    return L
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise BhppError(rc, where)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no HIP device: the BHPP library runs on the GPU only")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, dtype):
+    """A contiguous device tensor of `dtype` holding x (numpy or tensor)."""
+    torch = _torch()
+    if isinstance(x, torch.Tensor):
+        return x.to(device="cuda", dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+class Graph:
+    """A built bipartite graph resident in HBM (bhpp_build_graph)."""
+
+    def __init__(self, n_u, n_v, edge_u, edge_v, edge_w, alpha=0.15, dtype="f32", tau=-1,
+                 keep_external=False, reorder=True):
+        torch = _torch()
+        L = load_library()
+        self.dtype = dtype
+        self._tdtype = torch.float64 if dtype == "f64" else torch.float32
+        eu = _dev(edge_u, torch.int32)
+        ev = _dev(edge_v, torch.int32)
+        ew = _dev(edge_w, self._tdtype)
+        flags = (BUILD_KEEP_EXTERNAL if keep_external else 0) | (0 if reorder else BUILD_NO_REORDER)
+        opts = GraphOpts(alpha, tau, DTYPE_F64 if dtype == "f64" else DTYPE_F32, flags)
+        h = ctypes.c_void_p()
+        rc = L.bhpp_build_graph(n_u, n_v, eu.numel(), eu.data_ptr(), ev.data_ptr(), ew.data_ptr(),
+                                ctypes.byref(opts), _stream(), ctypes.byref(h))
+        _check(rc, "bhpp_build_graph")
+        self._h = h
+        self.n_u, self.n_v = int(n_u), int(n_v)
+        self.alpha = alpha
+
+    @classmethod
+    def from_edges(cls, el, **kw):
+        return cls(el.n_u, el.n_v, el.u, el.v, el.w, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bhpp_free_graph(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        s = GraphSummary()
+        _check(load_library().bhpp_graph_info(self._h, ctypes.byref(s)), "bhpp_graph_info")
+        return s.as_dict()
+
+    def export(self):
+        """External-id adjacency and ws (needs keep_external=True)."""
+        torch = _torch()
+        inf = self.info()
+        m = inf["n_edges"]
+        out = dict(rp_u=torch.empty(self.n_u + 1, dtype=torch.int64, device="cuda"),
+                   ci_u=torch.empty(max(m, 1), dtype=torch.int32, device="cuda"),
+                   w_u=torch.empty(max(m, 1), dtype=self._tdtype, device="cuda"),
+                   rp_v=torch.empty(self.n_v + 1, dtype=torch.int64, device="cuda"),
+                   ci_v=torch.empty(max(m, 1), dtype=torch.int32, device="cuda"),
+                   w_v=torch.empty(max(m, 1), dtype=self._tdtype, device="cuda"),
+                   ws_u=torch.empty(self.n_u, dtype=self._tdtype, device="cuda"),
+                   ws_v=torch.empty(self.n_v, dtype=self._tdtype, device="cuda"))
+        keys = ("rp_u", "ci_u", "w_u", "rp_v", "ci_v", "w_v", "ws_u", "ws_v")
+        rc = load_library().bhpp_graph_export(self._h, *[out[k].data_ptr() for k in keys], _stream())
+        _check(rc, "bhpp_graph_export")
+        for k in ("ci_u", "w_u", "ci_v", "w_v"):
+            out[k] = out[k][:m]
+        return out
+
+    def query(self, source, eps, alpha=None, with_stats=True):
+        """One query (bhpp_query): beta'(u, x) for every x, as a device tensor."""
+        torch = _torch()
+        out = torch.empty(self.n_u, dtype=self._tdtype, device="cuda")
+        st = QueryStats()
+        rc = load_library().bhpp_query(self._h, int(source), alpha or self.alpha, eps, out.data_ptr(),
+                                       ctypes.byref(st), _stream())
+        _check(rc, "bhpp_query")
+        return (out, st.as_dict()) if with_stats else out
+
+    def query_batch(self, sources, eps, alpha=None, k=0, exclude_self=True, scores=True, stats=True):
+        """Many queries (bhpp_query_batch). ``eps`` is a float or one per source.
+        Returns dict(scores=[n, n_u] tensor or None, ids, vals, stats)."""
+        torch = _torch()
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        n = src.size
+        eps_arr = np.broadcast_to(np.asarray(eps, dtype=np.float64), (n,)).copy()
+        sc = torch.empty((n, self.n_u), dtype=self._tdtype, device="cuda") if scores else None
+        ids = torch.empty((n, k), dtype=torch.int32, device="cuda") if k else None
+        vals = torch.empty((n, k), dtype=self._tdtype, device="cuda") if k else None
+        st = (QueryStats * max(1, n))()
+        rc = load_library().bhpp_query_batch(
+            self._h, n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha, float(eps_arr[0]),
+            sc.data_ptr() if sc is not None else None, int(k), 1 if exclude_self else 0,
+            ids.data_ptr() if ids is not None else None, vals.data_ptr() if vals is not None else None,
+            ctypes.cast(st, ctypes.c_void_p) if stats else None, _stream())
+        _check(rc, "bhpp_query_batch")
+        return dict(scores=sc, ids=ids, vals=vals, stats=[st[i].as_dict() for i in range(n)] if stats else None)
+
+    def profile(self, enable):
+        _check(load_library().bhpp_profile_enable(self._h, 1 if enable else 0), "bhpp_profile_enable")
+
+    def profile_read(self):
+        ms = (ctypes.c_double * 2)()
+        n = (ctypes.c_int64 * 2)()
+        b = (ctypes.c_double * 2)()
+        _check(load_library().bhpp_profile_read(self._h, ms, n, b), "bhpp_profile_read")
+        return dict(ms=list(ms), launches=list(n), bytes=list(b))
+
+
+def topk(scores, k, exclude=None):
+    """bhpp_topk on a [rows, n] device tensor: (ids int32, vals)."""
+    torch = _torch()
+    scores = scores.contiguous()
+    if scores.dim() == 1:
+        scores = scores[None, :]
+    rows, n = scores.shape
+    dt = DTYPE_F64 if scores.dtype == torch.float64 else DTYPE_F32
+    ids = torch.empty((rows, k), dtype=torch.int32, device="cuda")
+    vals = torch.empty((rows, k), dtype=scores.dtype, device="cuda")
+    ex = _dev(exclude, torch.int32) if exclude is not None else None
+    rc = load_library().bhpp_topk(scores.data_ptr(), rows, n, k, ex.data_ptr() if ex is not None else None,
+                                  dt, ids.data_ptr(), vals.data_ptr(), _stream())
+    _check(rc, "bhpp_topk")
+    return ids, vals

@@ -1,0 +1,226 @@
+// C ABI entry points (include/bhpp.h): argument checking, handle ownership,
+// error mapping. All computation happens in the kernels of build.hip,
+// sweep.hip and topk.hip.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+using bhpp::Graph;
+
+struct bhpp_graph {
+    Graph* g;
+};
+
+namespace {
+
+hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool valid_alpha(double a) { return a > 0.0 && a < 1.0 && std::isfinite(a); }
+bool valid_eps(double e) { return e > 0.0 && e < 1e30 && std::isfinite(e); }
+
+bhpp_status sticky(Graph* g, bhpp_status rc) {
+    if (rc == BHPP_DEVICE_ERROR) g->sticky_error = true;
+    return rc;
+}
+
+// lambda for this alpha (Lemma 4), computed once per alpha and cached
+bhpp_status lambda_for(Graph* g, double alpha, hipStream_t s, double* out) {
+    auto it = g->lambda_cache.find(alpha);
+    if (it != g->lambda_cache.end()) {
+        *out = it->second;
+        return BHPP_OK;
+    }
+    int32_t tau = 0;
+    double mm = (double)g->nu * (1.0 - alpha);
+    while (mm > 1.0) { mm *= (1.0 - alpha); ++tau; }
+    bhpp_status rc = bhpp::compute_lambda(g, alpha, tau, s, out);
+    if (rc == BHPP_OK) g->lambda_cache[alpha] = *out;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bhpp_status_string(bhpp_status s) {
+    switch (s) {
+        case BHPP_OK: return "ok";
+        case BHPP_INVALID_ARG: return "invalid argument";
+        case BHPP_OUT_OF_RANGE: return "node id out of range";
+        case BHPP_ISOLATED_SOURCE: return "source node has no edge";
+        case BHPP_BAD_WEIGHT: return "edge weight not finite and positive";
+        case BHPP_OUT_OF_MEMORY: return "out of memory";
+        case BHPP_DEVICE_ERROR: return "HIP device error";
+        case BHPP_NOT_SUPPORTED: return "not supported";
+        case BHPP_NO_CONVERGENCE: return "step limit reached";
+        default: return "unknown status";
+    }
+}
+
+bhpp_status bhpp_build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* edge_u,
+                             const int32_t* edge_v, const void* edge_w, const bhpp_graph_opts* opts,
+                             void* hip_stream, bhpp_graph** out) {
+    if (!out) return BHPP_INVALID_ARG;
+    *out = nullptr;
+    bhpp_graph_opts o{0.15, -1, BHPP_DTYPE_F32, 0u};
+    if (opts) o = *opts;
+    if (n_u <= 0 || n_v <= 0 || n_edges < 0 || n_edges > 0x7FFFFFFFLL) return BHPP_INVALID_ARG;
+    if (n_edges > 0 && (!edge_u || !edge_v || !edge_w)) return BHPP_INVALID_ARG;
+    if (!valid_alpha(o.alpha)) return BHPP_INVALID_ARG;
+    if (o.dtype != BHPP_DTYPE_F32 && o.dtype != BHPP_DTYPE_F64) return BHPP_NOT_SUPPORTED;
+    try {
+        Graph* g = nullptr;
+        bhpp_status rc = bhpp::build_graph(n_u, n_v, n_edges, edge_u, edge_v, edge_w, o, stream_of(hip_stream), &g);
+        if (rc) return rc;
+        bhpp_graph* h = new (std::nothrow) bhpp_graph{g};
+        if (!h) {
+            bhpp::free_graph(g);
+            return BHPP_OUT_OF_MEMORY;
+        }
+        *out = h;
+        return BHPP_OK;
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_query_batch(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps,
+                             double alpha, double eps_all, void* scores_out, int32_t k, int32_t exclude_self,
+                             int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, void* hip_stream) {
+    if (!h || !h->g) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    if (n_src < 0 || (n_src > 0 && !sources) || !valid_alpha(alpha)) return BHPP_INVALID_ARG;
+    if (n_src == 0) return BHPP_OK;
+    if (k < 0 || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
+    if (k > 0 && (!topk_ids || !topk_vals)) return BHPP_INVALID_ARG;
+    std::vector<double> e((size_t)n_src);
+    for (int32_t i = 0; i < n_src; ++i) {
+        e[i] = eps ? eps[i] : eps_all;
+        if (!valid_eps(e[i])) return BHPP_INVALID_ARG;
+    }
+    for (int32_t i = 0; i < n_src; ++i) {
+        if (sources[i] < 0 || sources[i] >= g->nu) return BHPP_OUT_OF_RANGE;
+        if (!(g->h_ws_u[sources[i]] > 0.0)) return BHPP_ISOLATED_SOURCE;
+    }
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        hipStream_t s = stream_of(hip_stream);
+        double lam = 0.0;
+        bhpp_status rc = lambda_for(g, alpha, s, &lam);
+        if (rc) return sticky(g, rc);
+        rc = bhpp::run_queries(g, n_src, sources, e.data(), alpha, lam, scores_out, k, exclude_self, topk_ids,
+                               topk_vals, stats, s);
+        if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+        return sticky(g, rc);
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_query(bhpp_graph* h, int32_t source, double alpha, double eps, void* scores_out,
+                       bhpp_query_stats* stats, void* hip_stream) {
+    if (!scores_out) return BHPP_INVALID_ARG;
+    return bhpp_query_batch(h, 1, &source, nullptr, alpha, eps, scores_out, 0, 0, nullptr, nullptr, stats,
+                            hip_stream);
+}
+
+bhpp_status bhpp_topk(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude_ids,
+                      int32_t dtype, int32_t* ids_out, void* vals_out, void* hip_stream) {
+    if (n_rows < 0 || n <= 0 || k < 1 || k > n) return BHPP_INVALID_ARG;
+    if (n_rows > 0 && (!scores || !ids_out || !vals_out)) return BHPP_INVALID_ARG;
+    if (dtype != BHPP_DTYPE_F32 && dtype != BHPP_DTYPE_F64) return BHPP_NOT_SUPPORTED;
+    if (exclude_ids && k > n - 1) return BHPP_INVALID_ARG;
+    try {
+        return bhpp::topk_rows(scores, n_rows, n, k, exclude_ids, dtype, ids_out, vals_out, stream_of(hip_stream));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_graph_info(const bhpp_graph* h, bhpp_graph_summary* out) {
+    if (!h || !h->g || !out) return BHPP_INVALID_ARG;
+    *out = h->g->info;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_graph_export(const bhpp_graph* h, int64_t* rp_u, int32_t* ci_u, void* w_u, int64_t* rp_v,
+                              int32_t* ci_v, void* w_v, void* ws_u, void* ws_v, void* hip_stream) {
+    if (!h || !h->g) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (!g->x_rp_u) return BHPP_NOT_SUPPORTED;
+    if (!rp_u || !ci_u || !w_u || !rp_v || !ci_v || !w_v || !ws_u || !ws_v) return BHPP_INVALID_ARG;
+    hipStream_t s = stream_of(hip_stream);
+    const size_t m = (size_t)g->ne, e = (size_t)g->elem;
+    BHPP_HIP(hipMemcpyAsync(rp_u, g->x_rp_u, 8 * ((size_t)g->nu + 1), hipMemcpyDeviceToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(rp_v, g->x_rp_v, 8 * ((size_t)g->nv + 1), hipMemcpyDeviceToDevice, s));
+    if (m > 0) {
+        BHPP_HIP(hipMemcpyAsync(ci_u, g->x_ci_u, 4 * m, hipMemcpyDeviceToDevice, s));
+        BHPP_HIP(hipMemcpyAsync(ci_v, g->x_ci_v, 4 * m, hipMemcpyDeviceToDevice, s));
+        BHPP_HIP(hipMemcpyAsync(w_u, g->x_w_u, e * m, hipMemcpyDeviceToDevice, s));
+        BHPP_HIP(hipMemcpyAsync(w_v, g->x_w_v, e * m, hipMemcpyDeviceToDevice, s));
+    }
+    BHPP_HIP(hipMemcpyAsync(ws_u, g->x_ws_u, e * g->nu, hipMemcpyDeviceToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(ws_v, g->x_ws_v, e * g->nv, hipMemcpyDeviceToDevice, s));
+    BHPP_HIP(hipStreamSynchronize(s));
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_profile_enable(bhpp_graph* h, int32_t enable) {
+    if (!h || !h->g) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (enable) {
+        for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
+        g->prof_ev.clear();
+        g->prof_kind.clear();
+        g->prof_b.clear();
+        g->prof_ms[0] = g->prof_ms[1] = 0.0;
+        g->prof_n[0] = g->prof_n[1] = 0;
+        g->prof_bytes[0] = g->prof_bytes[1] = 0.0;
+    }
+    g->prof_on = enable != 0;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[2], int64_t launches[2], double bytes[2]) {
+    if (!h || !h->g || !ms || !launches || !bytes) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    std::lock_guard<std::mutex> lock(g->mu);
+    // fold the recorded event pairs into the totals
+    const size_t pairs = g->prof_ev.size() / 2;
+    for (size_t i = 0; i < pairs; ++i) {
+        hipEvent_t a = g->prof_ev[2 * i], b = g->prof_ev[2 * i + 1];
+        if (hipEventSynchronize(b) != hipSuccess) return BHPP_DEVICE_ERROR;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, a, b) != hipSuccess) return BHPP_DEVICE_ERROR;
+        const int kind = g->prof_kind[i];
+        g->prof_ms[kind] += t;
+        g->prof_n[kind] += 1;
+        g->prof_bytes[kind] += g->prof_b[i];
+        hipEventDestroy(a);
+        hipEventDestroy(b);
+    }
+    g->prof_ev.clear();
+    g->prof_kind.clear();
+    g->prof_b.clear();
+    for (int k = 0; k < 2; ++k) {
+        ms[k] = g->prof_ms[k];
+        launches[k] = g->prof_n[k];
+        bytes[k] = g->prof_bytes[k];
+    }
+    return BHPP_OK;
+}
+
+void bhpp_free_graph(bhpp_graph* h) {
+    if (!h) return;
+    if (h->g) {
+        hipDeviceSynchronize();
+        bhpp::free_graph(h->g);
+    }
+    delete h;
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Internal declarations of the BHPP library (gfx950). Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "../../include/bhpp.h"
+
+namespace bhpp {
+
+constexpr int kWave = 64;            // CDNA wavefront width
+constexpr int kTileEdges = 512;      // target adjacency entries per work tile
+constexpr int kMaxCols = 64;         // sources per dense residue block (one per lane)
+constexpr int kPassThreads = 256;    // threads per block of the sweep kernels
+constexpr int kNumRed = 5;           // per-source reductions after a step (see Red)
+
+// A unit of work for one wavefront: either a run of whole rows whose degrees
+// are similar (rows are numbered by decreasing degree) or one piece of a row
+// that is longer than kTileEdges. Pieces of a split row write partial sums to
+// slot `slot`; a fix-up pass adds them in slot order.
+struct Tile {
+    int32_t row_begin, row_end;   // rows [row_begin, row_end)
+    int64_t e_begin, e_end;       // adjacency range covered
+    int32_t slot;                 // partial-sum slot, -1 for whole rows
+    int32_t epar_log2;            // log2 of the edge-parallel lanes per row
+};
+
+struct SplitRow {
+    int32_t row;
+    int32_t slot_begin, slot_end; // pieces in order
+    int32_t pad;
+};
+
+struct TileSet {
+    Tile* tiles = nullptr;        // device
+    int32_t n_tiles = 0;
+    SplitRow* split = nullptr;    // device
+    int32_t n_split = 0;
+    int32_t n_slots = 0;
+};
+
+// Push rule of a source for one half of a sweep (which nodes x are pushed).
+enum Rule : int32_t {
+    RULE_NONE = 0,   // nothing
+    RULE_SS = 1,     // r(x) > eps_b, i.e. y(x)/ws(x) > eps_b/ws(u)     (Algorithm 3, selective)
+    RULE_PI = 2,     // r_f(x) > eps_f/lambda, i.e. y(x) > eps_f/lambda (Algorithm 4, selective)
+    RULE_ALL = 3,    // every x with y(x) > 0                           (sequential pushes, PowerIteration)
+};
+
+// Phase of a source.
+enum Mode : int32_t {
+    MODE_SS_SEL = 0, MODE_SS_SEQ = 1, MODE_PI_SEL = 2, MODE_POWER = 3,
+    MODE_FINAL = 4, MODE_DONE = 5,
+};
+
+// Reductions taken over U after every sweep, per source.
+enum Red : int32_t {
+    RED_NP = 0,      // push cost n_p of the sweep (edges of pushed U and active V nodes)
+    RED_CNT_SS = 1,  // #{x : r(x) > eps_b}
+    RED_SUM_R = 2,   // sum_x y(x)/ws(x)   (times ws(u) = sum of r)
+    RED_CNT_PI = 3,  // #{x : y(x) > eps_f/lambda}
+    RED_SUM_Y = 4,   // sum_x y(x)          (= sum of the forward residue)
+};
+
+// Per-source state. The sweep kernels read the first block; the control
+// kernel owns the rest.
+struct ColState {
+    int32_t ruleA, ruleB, convert, mode;
+    double k_ss;         // eps_b / ws(u)
+    double k_pi;         // eps_f / lambda
+    double ws_src;       // ws(u)
+    double alpha;
+    // control
+    double eps, eps_b, eps_f;
+    double np;           // n_p of the current sub-algorithm
+    double gamma;
+    double two_e;        // 2|E|
+    double ln_inv;       // ln(1/(1-alpha))
+    int32_t t_rem;
+    int32_t steps;
+    // statistics
+    int32_t ss_sel_iters, ss_seq_iters, pi_sel_iters, t, ss_switched, pi_returned;
+    double np_ss, np_pi, sum_r_ss, sum_rf;
+};
+
+struct Workspace {
+    int cols = 0;                // allocated column count (power of 2)
+    int elem = 0;                // bytes per value
+    void* Y = nullptr;           // [n_u][cols] forward residue y = (ws/ws(u)) r
+    void* ACC = nullptr;         // [n_u][cols] push estimate, later beta'
+    void* Q = nullptr;           // [n_v][cols] V-side residue of the current sweep
+    void* partA = nullptr;       // [slots_v][cols] split-row partial sums
+    int32_t* partA_any = nullptr;
+    void* partB = nullptr;       // [slots_u][cols]
+    double* red = nullptr;       // [kNumRed][cols][n_part] per-block reductions
+    int n_part = 0;
+    ColState* st = nullptr;      // [cols]
+    int32_t* n_active = nullptr; // device counter of unfinished sources
+    int32_t* h_active = nullptr; // pinned host mirror
+    void* scores = nullptr;      // [cols][n_u] row-major scratch for top-k
+    size_t bytes = 0;
+};
+
+struct Graph {
+    int32_t nu = 0, nv = 0;
+    int64_t ne = 0;
+    int32_t dtype = BHPP_DTYPE_F32;
+    int elem = 4;
+    // internal (degree-ordered) adjacency
+    int64_t* rp_u = nullptr; int32_t* ci_u = nullptr; void* w_u = nullptr;
+    int64_t* rp_v = nullptr; int32_t* ci_v = nullptr; void* w_v = nullptr;
+    float* inv_ws_u_f = nullptr; float* inv_ws_v_f = nullptr;     // F32 graphs
+    double* inv_ws_u_d = nullptr; double* inv_ws_v_d = nullptr;   // both dtypes
+    int32_t* perm_u = nullptr;   // external U id -> internal
+    int32_t* iperm_u = nullptr;  // internal -> external
+    TileSet tiles_u, tiles_v;
+    // external-order copies (BHPP_BUILD_KEEP_EXTERNAL)
+    int64_t* x_rp_u = nullptr; int32_t* x_ci_u = nullptr; void* x_w_u = nullptr;
+    int64_t* x_rp_v = nullptr; int32_t* x_ci_v = nullptr; void* x_w_v = nullptr;
+    void* x_ws_u = nullptr; void* x_ws_v = nullptr;
+    // host copies
+    std::vector<double> h_ws_u;       // external order, FP64
+    std::vector<int32_t> h_perm_u;    // external -> internal
+    bhpp_graph_summary info{};
+    std::map<double, double> lambda_cache;   // alpha -> lambda
+    int32_t tau = 0;
+    // runtime
+    std::mutex mu;
+    Workspace ws;
+    bool sticky_error = false;
+    // profiling of the sweep kernels
+    bool prof_on = false;
+    double prof_ms[2] = {0, 0};
+    int64_t prof_n[2] = {0, 0};
+    double prof_bytes[2] = {0, 0};
+    std::vector<hipEvent_t> prof_ev;      // pairs, recorded on the query stream
+    std::vector<int32_t> prof_kind;
+    std::vector<double> prof_b;
+};
+
+// ---- host helpers (api.hip / build.hip / sweep.hip / topk.hip) ----
+#define BHPP_HIP(expr)                                      \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return BHPP_DEVICE_ERROR;     \
+    } while (0)
+
+bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t* eu,
+                        const int32_t* ev, const void* ew, const bhpp_graph_opts& opts,
+                        hipStream_t s, Graph** out);
+void free_graph(Graph* g);
+bhpp_status compute_lambda(Graph* g, double alpha, int32_t tau, hipStream_t s, double* lambda_out);
+bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const double* eps, double alpha,
+                        double lambda, void* scores_out, int32_t k, int32_t exclude_self,
+                        int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, hipStream_t s);
+bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
+                      int32_t dtype, int32_t* ids_out, void* vals_out, hipStream_t s);
+bhpp_status ensure_workspace(Graph* g, int cols);
+bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, TileSet* ts);
+void free_tiles(TileSet* ts);
+
+inline int next_pow2(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace bhpp

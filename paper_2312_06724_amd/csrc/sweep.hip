@@ -1,0 +1,794 @@
+// Two-hop sweep kernels and device-side phase control for Approx-BHPP.
+//
+// Coordinates. The kernels keep, per source u and node x in U, the forward
+// residue y(x) = ws(x)/ws(u) * r(x) (Eq. (fresidue)) instead of the backward
+// residue r of Algorithms 2-3. By Lemma 3 a backward push of r is the same
+// operation as a forward push of y (Eq. (bwd2fwd)), so one array serves
+// SS-Push, PI-Push and PowerIteration, and only the push rule changes:
+//   SS-Push:   push x iff r(x) > eps_b        <=> y(x)/ws(x) > eps_b/ws(u)
+//   PI-Push:   push x iff r(x) > ws(u)/ws(x) eps_f/lambda <=> y(x) > eps_f/lambda
+//   sequential pushes and PowerIteration: push every x with y(x) > 0.
+// Pushing a set S (Algorithm 2, one iteration): ACC(x) += alpha y(x) for x in
+// S, then y <- y - y_S + (1-alpha) y_S P with P = D_U^-1 W D_V^-1 W^T. ACC
+// then equals pi_f = ws/ws(u) pi_b (Eq. (fppr)); at the end it is converted to
+// beta' = pi_f + pi_b = ACC (1 + ws(u)/ws(x)) plus the PowerIteration part
+// (Algorithm 5). PowerIteration(y, t) (Algorithm 1) is t pushes of every node
+// followed by ACC += alpha y: alpha sum_{l<=t} (1-alpha)^l y P^l.
+//
+// One sweep is two gathers, each over one adjacency direction:
+//   pass A (rows v of W^T): Q(v) = (1-alpha)/ws(v) * sum_x w(x,v) y_S(x)/ws(x)
+//   pass B (rows x of W):   y(x) <- y(x) - y_S(x) + sum_v w(x,v) Q(v),
+//                           ACC(x) += alpha y_S(x), and the reductions that
+//                           the phase control needs (Red in common.h).
+// Up to 64 sources run together; source c of a block occupies column c of the
+// node-major arrays Y[n_u][C], ACC[n_u][C], Q[n_v][C] so one adjacency entry
+// feeds C lanes with one contiguous load.
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+namespace bhpp {
+
+// ---------------------------------------------------------------------------
+// launch geometry
+// ---------------------------------------------------------------------------
+constexpr int kWavesPerBlock = kPassThreads / kWave;
+constexpr int kMaxPassBlocks = 2048;
+constexpr int kMaxFixBlocks = 256;
+
+struct Geometry {
+    int blkA, blkFA, blkB, blkFB;
+    int offA, offFA, offB, offFB, n_part;
+};
+
+static Geometry geometry(const Graph* g) {
+    Geometry G;
+    auto clampi = [](long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); };
+    G.blkA = clampi((g->tiles_v.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxPassBlocks);
+    G.blkB = clampi((g->tiles_u.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxPassBlocks);
+    G.blkFA = clampi((g->tiles_v.n_split + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxFixBlocks);
+    G.blkFB = clampi((g->tiles_u.n_split + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxFixBlocks);
+    G.offA = 0;
+    G.offFA = G.blkA;
+    G.offB = G.offFA + G.blkFA;
+    G.offFB = G.offB + G.blkB;
+    G.n_part = G.offFB + G.blkFB;
+    return G;
+}
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+template <typename VT>
+__device__ __forceinline__ bool select_push(int rule, VT y, VT yw, VT kss, VT kpi) {
+    // yw = y / ws(x) (0 for isolated x)
+    return rule == RULE_SS ? (yw > kss) : rule == RULE_PI ? (y > kpi) : rule == RULE_ALL ? (y > VT(0)) : false;
+}
+
+// Sum `v` over the lanes of the block that serve the same column and store
+// it at out[col * n_part + blockIdx.x] (deterministic order).
+template <int COLS>
+__device__ __forceinline__ void block_column_sum(double v, double* sh, double* out, int n_part) {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int m = COLS; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+    sh[wid * kWave + lane] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < COLS) {
+        double s = 0.0;
+        for (int w = 0; w < kWavesPerBlock; ++w) s += sh[w * kWave + threadIdx.x];
+        out[(size_t)threadIdx.x * n_part + blockIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+template <typename VT, typename WT>
+struct PassArgs {
+    const Tile* tiles;
+    int n_tiles;
+    const int64_t* rp;
+    const int32_t* ci;
+    const WT* w;
+    const VT* inv_ws_row;   // 1/ws of the row side
+    const VT* inv_ws_col;   // 1/ws of the neighbour side
+    const VT* X;            // gathered vector (pass A: Y over U, pass B: Q over V)
+    VT* OUT;                // pass A: Q; pass B: Y (updated in place)
+    VT* ACC;                // pass B only
+    VT* part;               // split-row partial sums
+    int32_t* part_any;
+    const ColState* st;
+    const int32_t* n_active;
+    double* red;            // [kNumRed][COLS][n_part]
+    int n_part;
+    int red_off;
+};
+
+// Epilogue of pass B for row x and one column: apply the push of x decided by
+// ruleB, add the gathered inflow g, and accumulate the reductions.
+template <typename VT>
+__device__ __forceinline__ void epilogue_b(VT* Y, VT* ACC, size_t idx, VT g, VT iw, int ruleB, int convert,
+                                           VT kss, VT kpi, VT ws_src, VT alpha, double deg, double (&r)[kNumRed]) {
+    VT y = Y[idx];
+    VT yw = y * iw;
+    bool sel = select_push<VT>(ruleB, y, yw, kss, kpi);
+    VT s = sel ? y : VT(0);
+    VT a = ACC[idx];
+    if (convert) a = a * (VT(1) + ws_src * iw);   // Eq. (fppr) + pi_b: ACC -> beta' part
+    a += alpha * s;
+    VT yn = (y - s) + g;
+    Y[idx] = yn;
+    ACC[idx] = a;
+    VT tn = yn * iw;
+    if (sel) r[RED_NP] += deg;
+    r[RED_CNT_SS] += (tn > kss) ? 1.0 : 0.0;
+    r[RED_SUM_R] += (double)tn;
+    r[RED_CNT_PI] += (yn > kpi) ? 1.0 : 0.0;
+    r[RED_SUM_Y] += (double)yn;
+}
+
+// ---------------------------------------------------------------------------
+// pass A / pass B: one wavefront per tile, lanes = (row group, edge slot, column)
+// ---------------------------------------------------------------------------
+template <int COLS, typename VT, typename WT, bool PASS_B>
+__global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs<VT, WT> p) {
+    __shared__ double sh[kPassThreads];
+    if (*p.n_active == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int col = lane & (COLS - 1);
+    const ColState& cs = p.st[col];
+    const int rule = PASS_B ? cs.ruleB : cs.ruleA;
+    const int convert = cs.convert;
+    const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
+    const VT one_minus_alpha = VT(1) - alpha;
+    double r[kNumRed] = {0, 0, 0, 0, 0};
+    const int n_waves = gridDim.x * kWavesPerBlock;
+    for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
+        const Tile T = p.tiles[t];
+        const int epar = min(1 << T.epar_log2, kWave / COLS);
+        const int gl = epar * COLS;            // lanes per row
+        const int ngroups = kWave / gl;
+        const int grp = lane / gl;
+        const int slot = (lane % gl) / COLS;
+        for (int r0 = T.row_begin; r0 < T.row_end; r0 += ngroups) {
+            const int row = r0 + grp;
+            const bool valid = row < T.row_end;
+            int64_t e0 = 0, e1 = 0;
+            if (T.slot >= 0) {
+                e0 = T.e_begin;
+                e1 = T.e_end;
+            } else if (valid) {
+                e0 = p.rp[row];
+                e1 = p.rp[row + 1];
+            }
+            VT acc = VT(0);
+            int any = 0;
+            if (PASS_B || rule != RULE_NONE) {
+#pragma unroll 4
+                for (int64_t e = e0 + slot; e < e1; e += epar) {
+                    const int32_t x = p.ci[e];
+                    const VT ww = (VT)p.w[e];
+                    const VT v = p.X[(size_t)x * COLS + col];
+                    if (PASS_B) {
+                        acc += ww * v;
+                    } else {
+                        const VT vw = v * p.inv_ws_col[x];
+                        if (select_push<VT>(rule, v, vw, kss, kpi)) {
+                            acc += ww * vw;
+                            any = 1;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = COLS; m < kWave; m <<= 1) {
+                if (m < gl) {
+                    acc += __shfl_xor(acc, m);
+                    if (!PASS_B) any |= __shfl_xor(any, m);
+                }
+            }
+            if (slot == 0 && valid) {
+                const size_t idx = (size_t)row * COLS + col;
+                if (T.slot >= 0) {
+                    p.part[(size_t)T.slot * COLS + col] = acc;
+                    if (!PASS_B) p.part_any[(size_t)T.slot * COLS + col] = any;
+                } else if (!PASS_B) {
+                    p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * acc;
+                    if (any) r[RED_NP] += (double)(e1 - e0);
+                } else {
+                    epilogue_b<VT>(p.OUT, p.ACC, idx, acc, p.inv_ws_row[row], rule, convert, kss, kpi, ws_src,
+                                   alpha, (double)(e1 - e0), r);
+                }
+            }
+        }
+    }
+    double* base = p.red + p.red_off;
+#pragma unroll
+    for (int k = 0; k < kNumRed; ++k)
+        block_column_sum<COLS>(r[k], sh, base + (size_t)k * COLS * p.n_part, p.n_part);
+}
+
+// Fix-up of split rows: add the pieces in slot order, then the same epilogue.
+template <int COLS, typename VT, typename WT, bool PASS_B>
+__global__ __launch_bounds__(kPassThreads) void k_fixup(PassArgs<VT, WT> p, const SplitRow* split, int n_split) {
+    __shared__ double sh[kPassThreads];
+    if (*p.n_active == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int col = lane & (COLS - 1);
+    const ColState& cs = p.st[col];
+    const int rule = PASS_B ? cs.ruleB : cs.ruleA;
+    const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
+    const VT one_minus_alpha = VT(1) - alpha;
+    double r[kNumRed] = {0, 0, 0, 0, 0};
+    const int n_waves = gridDim.x * kWavesPerBlock;
+    for (int i = blockIdx.x * kWavesPerBlock + wid; i < n_split; i += n_waves) {
+        const SplitRow S = split[i];
+        if (lane >= COLS) continue;
+        VT acc = VT(0);
+        int any = 0;
+        for (int s = S.slot_begin; s < S.slot_end; ++s) {
+            acc += p.part[(size_t)s * COLS + col];
+            if (!PASS_B) any |= p.part_any[(size_t)s * COLS + col];
+        }
+        const int row = S.row;
+        const double deg = (double)(p.rp[row + 1] - p.rp[row]);
+        const size_t idx = (size_t)row * COLS + col;
+        if (!PASS_B) {
+            p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * acc;
+            if (any) r[RED_NP] += deg;
+        } else {
+            epilogue_b<VT>(p.OUT, p.ACC, idx, acc, p.inv_ws_row[row], rule, cs.convert, kss, kpi, ws_src, alpha,
+                           deg, r);
+        }
+    }
+    double* base = p.red + p.red_off;
+#pragma unroll
+    for (int k = 0; k < kNumRed; ++k)
+        block_column_sum<COLS>(r[k], sh, base + (size_t)k * COLS * p.n_part, p.n_part);
+}
+
+// ---------------------------------------------------------------------------
+// phase control (Algorithms 3 and 4), one block per source
+// ---------------------------------------------------------------------------
+__device__ void set_rules(ColState& s, int mode, int ra, int rb, int conv) {
+    s.mode = mode;
+    s.ruleA = ra;
+    s.ruleB = rb;
+    s.convert = conv;
+}
+
+// SS-Push returned: start PI-Push (Algorithm 5, line 3).
+__device__ void enter_pi(ColState& s, const double* R, double sum_r) {
+    s.np_ss = s.np;
+    s.sum_r_ss = sum_r;
+    s.gamma = R[RED_SUM_Y];     // Eq. (gamma): sum_x ws(x)/ws(u) r(x) = sum_x y(x)
+    s.np = 0.0;                 // Algorithm 4 repeats Algorithm 3 from its line 3 (n_p <- 0)
+    if (R[RED_CNT_PI] == 0.0) {
+        // the first selective iteration would push nothing and Eq. (fwd-eps)
+        // would hold: return pi_f from Eq. (fppr)
+        s.pi_sel_iters = 1;
+        s.pi_returned = 1;
+        set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, 1);
+    } else {
+        set_rules(s, MODE_PI_SEL, RULE_PI, RULE_PI, 0);
+    }
+}
+
+__device__ void control_update(ColState& s, const double* R, int32_t* n_active) {
+    const int m = s.mode;
+    if (m == MODE_DONE) return;
+    s.steps += 1;
+    const double sum_r = R[RED_SUM_R] * s.ws_src;     // sum_x r(x)
+    const double sum_y = R[RED_SUM_Y];                // sum_x r_f(x)
+    const bool ss_stop = (R[RED_CNT_SS] == 0.0) || (sum_r <= s.eps_b);
+    switch (m) {
+        case MODE_SS_SEL:
+            s.np += R[RED_NP];
+            s.ss_sel_iters += 1;
+            if (ss_stop) {
+                enter_pi(s, R, sum_r);
+            } else if (s.np >= s.two_e * (log(1.0 / sum_r) / s.ln_inv)) {      // Eq. (bwd-np)
+                s.ss_switched = 1;
+                set_rules(s, MODE_SS_SEQ, RULE_ALL, RULE_ALL, 0);
+            }
+            break;
+        case MODE_SS_SEQ:
+            s.np += R[RED_NP];
+            s.ss_seq_iters += 1;
+            if (ss_stop) enter_pi(s, R, sum_r);
+            break;
+        case MODE_PI_SEL:
+            s.np += R[RED_NP];
+            s.pi_sel_iters += 1;
+            if (R[RED_CNT_PI] == 0.0) {                                         // Eq. (fwd-eps)
+                s.np_pi = s.np;
+                s.pi_returned = 1;
+                set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, 1);
+            } else if (s.np >= s.two_e * (log(s.gamma / sum_y) / s.ln_inv)) {  // Eq. (fwd-np)
+                s.np_pi = s.np;
+                s.sum_rf = sum_y;
+                double tr = ceil(log(sum_y / s.eps_f) / s.ln_inv - 1.0);         // Eq. (t)
+                int t = tr > 0.0 ? (int)tr : 0;
+                s.t = t;
+                if (t == 0) {
+                    set_rules(s, MODE_FINAL, RULE_NONE, RULE_ALL, 1);
+                } else {
+                    s.t_rem = t;
+                    set_rules(s, MODE_POWER, RULE_ALL, RULE_ALL, 1);
+                }
+            }
+            break;
+        case MODE_POWER:
+            s.convert = 0;
+            s.t_rem -= 1;
+            if (s.t_rem == 0) set_rules(s, MODE_FINAL, RULE_NONE, RULE_ALL, 0);
+            break;
+        case MODE_FINAL:
+            set_rules(s, MODE_DONE, RULE_NONE, RULE_NONE, 0);
+            atomicSub(n_active, 1);
+            break;
+        default:
+            break;
+    }
+}
+
+template <int COLS>
+__global__ __launch_bounds__(256) void k_control(ColState* st, const double* red, int n_part, int32_t* n_active) {
+    __shared__ double sh[256];
+    __shared__ double R[kNumRed];
+    if (*n_active == 0) return;
+    const int col = blockIdx.x;
+    for (int k = 0; k < kNumRed; ++k) {
+        const double* src = red + ((size_t)k * COLS + col) * n_part;
+        double s = 0.0;
+        for (int i = threadIdx.x; i < n_part; i += 256) s += src[i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) R[k] = sh[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) control_update(st[col], R, n_active);
+}
+
+// ---------------------------------------------------------------------------
+// initialisation and output
+// ---------------------------------------------------------------------------
+template <typename VT>
+__global__ void k_fill(VT* a, size_t n, VT v) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) a[i] = v;
+}
+
+template <typename VT>
+__global__ void k_seed(VT* Y, const int32_t* rows, int ncols, int cols) {
+    int c = threadIdx.x;
+    if (c < ncols) Y[(size_t)rows[c] * cols + c] = VT(1);
+}
+
+// ACC[internal x][c] -> out[c][external x] (row-major), through an LDS tile.
+template <int COLS, typename VT>
+__global__ __launch_bounds__(256) void k_export_scores(const VT* ACC, const int32_t* perm, int32_t nu, int ncols,
+                                                       VT* out) {
+    __shared__ VT tile[64][COLS + (COLS == 1 ? 0 : 1)];
+    const int x0 = blockIdx.x * 64;
+    for (int idx = threadIdx.x; idx < 64 * COLS; idx += 256) {
+        int i = idx / COLS, c = idx % COLS;
+        int x = x0 + i;
+        tile[i][c] = x < nu ? ACC[(size_t)perm[x] * COLS + c] : VT(0);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * COLS; idx += 256) {
+        int c = idx / 64, i = idx % 64;
+        int x = x0 + i;
+        if (c < ncols && x < nu) out[(size_t)c * nu + x] = tile[i][c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename VT>
+static VT* as(void* p) { return reinterpret_cast<VT*>(p); }
+
+template <typename VT>
+static const VT* inv_ws_u_of(const Graph* g);
+template <>
+const float* inv_ws_u_of<float>(const Graph* g) { return g->inv_ws_u_f; }
+template <>
+const double* inv_ws_u_of<double>(const Graph* g) { return g->inv_ws_u_d; }
+template <typename VT>
+static const VT* inv_ws_v_of(const Graph* g);
+template <>
+const float* inv_ws_v_of<float>(const Graph* g) { return g->inv_ws_v_f; }
+template <>
+const double* inv_ws_v_of<double>(const Graph* g) { return g->inv_ws_v_d; }
+
+// Buffers of one dense residue block (the graph's workspace or a private one).
+struct Block {
+    void* Y;
+    void* ACC;
+    void* Q;
+    void* partA;
+    int32_t* partA_any;
+    void* partB;
+    double* red;
+    ColState* st;
+    int32_t* n_active;
+    int32_t* h_active;
+};
+
+static void prof_begin(Graph* g, hipStream_t s, int kind, double bytes, hipEvent_t* ev) {
+    if (!g->prof_on) return;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    hipEventRecord(a, s);
+    ev[0] = a;
+    ev[1] = b;
+    g->prof_kind.push_back(kind);
+    g->prof_b.push_back(bytes);
+}
+static void prof_end(Graph* g, hipStream_t s, hipEvent_t* ev) {
+    if (!g->prof_on || ev[1] == nullptr) return;
+    hipEventRecord(ev[1], s);
+    g->prof_ev.push_back(ev[0]);
+    g->prof_ev.push_back(ev[1]);
+}
+
+// Algorithmic bytes of one launch: adjacency once, each dense vector once.
+template <typename VT, typename WT>
+static double pass_bytes(const Graph* g, int cols, bool pass_b) {
+    const double nnz = (double)g->ne;
+    const double nu = (double)(g->nu - g->info.isolated_u), nv = (double)(g->nv - g->info.isolated_v);
+    const double adj = nnz * (4.0 + sizeof(WT));
+    if (!pass_b) {   // rows V: read rp_v, inv_ws_v, Y and inv_ws_u once, write Q
+        return adj + nv * 8.0 + nv * sizeof(VT) + nu * cols * sizeof(VT) + nu * sizeof(VT) + nv * cols * sizeof(VT);
+    }
+    // rows U: read rp_u, inv_ws_u, Q once; read and write Y and ACC
+    return adj + nu * 8.0 + nu * sizeof(VT) + nv * cols * sizeof(VT) + 4.0 * nu * cols * sizeof(VT);
+}
+
+template <int COLS, typename VT, typename WT>
+static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipStream_t s) {
+    const WT* wu = reinterpret_cast<const WT*>(g->w_u);
+    const WT* wv = reinterpret_cast<const WT*>(g->w_v);
+    PassArgs<VT, WT> A;
+    A.tiles = g->tiles_v.tiles;
+    A.n_tiles = g->tiles_v.n_tiles;
+    A.rp = g->rp_v;
+    A.ci = g->ci_v;
+    A.w = wv;
+    A.inv_ws_row = inv_ws_v_of<VT>(g);
+    A.inv_ws_col = inv_ws_u_of<VT>(g);
+    A.X = as<VT>(b.Y);
+    A.OUT = as<VT>(b.Q);
+    A.ACC = nullptr;
+    A.part = as<VT>(b.partA);
+    A.part_any = b.partA_any;
+    A.st = b.st;
+    A.n_active = b.n_active;
+    A.red = b.red;
+    A.n_part = G.n_part;
+    PassArgs<VT, WT> B = A;
+    B.tiles = g->tiles_u.tiles;
+    B.n_tiles = g->tiles_u.n_tiles;
+    B.rp = g->rp_u;
+    B.ci = g->ci_u;
+    B.w = wu;
+    B.inv_ws_row = inv_ws_u_of<VT>(g);
+    B.inv_ws_col = inv_ws_v_of<VT>(g);
+    B.X = as<VT>(b.Q);
+    B.OUT = as<VT>(b.Y);
+    B.ACC = as<VT>(b.ACC);
+    B.part = as<VT>(b.partB);
+    B.part_any = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    prof_begin(g, s, 0, pass_bytes<VT, WT>(g, COLS, false), ev);
+    A.red_off = G.offA;
+    hipLaunchKernelGGL((k_pass<COLS, VT, WT, false>), dim3(G.blkA), dim3(kPassThreads), 0, s, A);
+    prof_end(g, s, ev);
+    // the fix-ups always run: their blocks also write their reduction slots
+    A.red_off = G.offFA;
+    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFA), dim3(kPassThreads), 0, s, A,
+                       g->tiles_v.split, g->tiles_v.n_split);
+    ev[0] = ev[1] = nullptr;
+    prof_begin(g, s, 1, pass_bytes<VT, WT>(g, COLS, true), ev);
+    B.red_off = G.offB;
+    hipLaunchKernelGGL((k_pass<COLS, VT, WT, true>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
+    prof_end(g, s, ev);
+    B.red_off = G.offFB;
+    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
+                       g->tiles_u.split, g->tiles_u.n_split);
+    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(256), 0, s, b.st, b.red, G.n_part, b.n_active);
+    BHPP_HIP(hipGetLastError());
+    return BHPP_OK;
+}
+
+constexpr int kStepsPerChunk = 8;
+constexpr int kMaxSteps = 4000;   // a query needs O(log 1/eps) sweeps; this only stops runaways
+
+// Run every source of the block to completion. The phase of each source
+// lives on the device; the host only polls the count of unfinished sources
+// once per chunk of sweeps (and keeps one chunk in flight while it waits).
+template <int COLS, typename VT, typename WT>
+static bhpp_status run_block(Graph* g, const Block& b, hipStream_t s, int* steps_out) {
+    const Geometry G = geometry(g);
+    hipEvent_t evs[2];
+    BHPP_HIP(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
+    BHPP_HIP(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
+    int32_t* h = b.h_active;   // two pinned slots
+    int steps = 0, chunk = 0;
+    bhpp_status rc = BHPP_OK;
+    bool pending = false;
+    for (;;) {
+        for (int i = 0; i < kStepsPerChunk; ++i) {
+            rc = launch_step<COLS, VT, WT>(g, b, G, s);
+            if (rc) break;
+        }
+        if (rc) break;
+        steps += kStepsPerChunk;
+        const int slot = chunk & 1;
+        if (hipMemcpyAsync(&h[slot], b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(evs[slot], s) != hipSuccess) {
+            rc = BHPP_DEVICE_ERROR;
+            break;
+        }
+        if (pending) {   // wait for the previous chunk's count
+            if (hipEventSynchronize(evs[slot ^ 1]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
+            if (h[slot ^ 1] == 0) break;
+        }
+        pending = true;
+        ++chunk;
+        if (steps > kMaxSteps) { rc = BHPP_NO_CONVERGENCE; break; }
+    }
+    if (rc == BHPP_OK || rc == BHPP_NO_CONVERGENCE) {
+        if (hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    }
+    hipEventDestroy(evs[0]);
+    hipEventDestroy(evs[1]);
+    if (steps_out) *steps_out = steps;
+    return rc;
+}
+
+static void init_state(ColState& c, double alpha, double ws_src, double eps, double eps_b_ratio, double lambda,
+                       int64_t ne) {
+    memset(&c, 0, sizeof(c));
+    c.alpha = alpha;
+    c.ws_src = ws_src;
+    c.eps = eps;
+    c.eps_b = eps * eps_b_ratio;
+    c.eps_f = eps - c.eps_b;                 // Algorithm 5, line 2
+    c.k_ss = ws_src > 0 ? c.eps_b / ws_src : 0.0;
+    c.k_pi = c.eps_f / lambda;
+    c.two_e = 2.0 * (double)ne;
+    c.ln_inv = log(1.0 / (1.0 - alpha));
+    c.mode = MODE_SS_SEL;                    // Algorithm 3 starts with selective pushes
+    c.ruleA = c.ruleB = RULE_SS;
+    c.convert = 0;
+}
+
+static void done_state(ColState& c) {
+    memset(&c, 0, sizeof(c));
+    c.mode = MODE_DONE;
+    c.alpha = 0.5;
+    c.k_ss = c.k_pi = 1e300;
+}
+
+template <int COLS, typename VT, typename WT>
+static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const double* eps, double alpha,
+                            double lambda, void* scores_out, hipStream_t s, std::vector<ColState>& hs,
+                            std::vector<int>& steps) {
+    Workspace& w = g->ws;
+    Block b{w.Y, w.ACC, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    hs.assign(COLS, ColState{});
+    std::vector<int32_t> rows(COLS, 0);
+    for (int c = 0; c < COLS; ++c) {
+        if (c < ncols) {
+            const int32_t u = src_ext[c];
+            init_state(hs[c], alpha, g->h_ws_u[u], eps[c], g->info.eps_b_ratio, lambda, g->ne);
+            rows[c] = g->h_perm_u[u];
+        } else {
+            done_state(hs[c]);
+        }
+    }
+    const size_t nU = (size_t)g->nu * COLS;
+    int32_t* d_rows = reinterpret_cast<int32_t*>(w.red);   // borrow: red is rewritten by every pass
+    BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * COLS, hipMemcpyHostToDevice, s));
+    int32_t act = ncols;
+    BHPP_HIP(hipMemcpyAsync(w.n_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_fill<VT>, dim3(2048), dim3(256), 0, s, as<VT>(w.Y), nU, VT(0));
+    hipLaunchKernelGGL(k_fill<VT>, dim3(2048), dim3(256), 0, s, as<VT>(w.ACC), nU, VT(0));
+    hipLaunchKernelGGL(k_seed<VT>, dim3(1), dim3(64), 0, s, as<VT>(w.Y), d_rows, ncols, COLS);
+    BHPP_HIP(hipGetLastError());
+    BHPP_HIP(hipStreamSynchronize(s));   // d_rows is borrowed from red
+    int nsteps = 0;
+    bhpp_status rc = run_block<COLS, VT, WT>(g, b, s, &nsteps);
+    if (rc) return rc;
+    BHPP_HIP(hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost));
+    if (scores_out) {
+        hipLaunchKernelGGL((k_export_scores<COLS, VT>), dim3((g->nu + 63) / 64), dim3(256), 0, s, as<VT>(w.ACC),
+                           g->perm_u, g->nu, ncols, as<VT>(scores_out));
+        BHPP_HIP(hipGetLastError());
+    }
+    steps.push_back(nsteps);
+    return BHPP_OK;
+}
+
+template <typename VT, typename WT>
+static bhpp_status run_tile_dispatch(Graph* g, int ncols, const int32_t* src, const double* eps, double alpha,
+                                     double lambda, void* scores, hipStream_t s, std::vector<ColState>& hs,
+                                     std::vector<int>& steps) {
+    const int cols = next_pow2(ncols);
+    switch (cols) {
+        case 1: return run_tile<1, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 2: return run_tile<2, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 4: return run_tile<4, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 8: return run_tile<8, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 16: return run_tile<16, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 32: return run_tile<32, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 64: return run_tile<64, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        default: return BHPP_INVALID_ARG;
+    }
+}
+
+bhpp_status ensure_workspace(Graph* g, int cols) {
+    Workspace& w = g->ws;
+    const Geometry G = geometry(g);
+    if (w.cols >= cols && w.n_part >= G.n_part) return BHPP_OK;
+    // free and reallocate at the larger size
+    hipFree(w.Y); hipFree(w.ACC); hipFree(w.Q); hipFree(w.partA); hipFree(w.partA_any); hipFree(w.partB);
+    hipFree(w.red); hipFree(w.st); hipFree(w.n_active); hipFree(w.scores);
+    if (w.h_active) hipHostFree(w.h_active);
+    w = Workspace{};
+    const size_t e = (size_t)g->elem;
+    const size_t c = (size_t)cols;
+    auto alloc = [&](void** p, size_t bytes) -> bool {
+        if (bytes == 0) bytes = 256;
+        w.bytes += bytes;
+        return hipMalloc(p, bytes) == hipSuccess;
+    };
+    bool ok = alloc(&w.Y, (size_t)g->nu * c * e) && alloc(&w.ACC, (size_t)g->nu * c * e) &&
+              alloc(&w.Q, (size_t)g->nv * c * e) && alloc(&w.partA, (size_t)g->tiles_v.n_slots * c * e) &&
+              alloc((void**)&w.partA_any, (size_t)g->tiles_v.n_slots * c * 4) &&
+              alloc(&w.partB, (size_t)g->tiles_u.n_slots * c * e) &&
+              alloc((void**)&w.red, (size_t)kNumRed * c * G.n_part * 8 + 64 * 4) &&
+              alloc((void**)&w.st, sizeof(ColState) * c) && alloc((void**)&w.n_active, 64) &&
+              alloc(&w.scores, (size_t)g->nu * c * e);
+    if (ok) ok = hipHostMalloc((void**)&w.h_active, 64) == hipSuccess;
+    if (!ok) {
+        hipFree(w.Y); hipFree(w.ACC); hipFree(w.Q); hipFree(w.partA); hipFree(w.partA_any); hipFree(w.partB);
+        hipFree(w.red); hipFree(w.st); hipFree(w.n_active); hipFree(w.scores);
+        if (w.h_active) hipHostFree(w.h_active);
+        w = Workspace{};
+        (void)hipGetLastError();
+        return BHPP_OUT_OF_MEMORY;
+    }
+    w.cols = cols;
+    w.elem = g->elem;
+    w.n_part = G.n_part;
+    return BHPP_OK;
+}
+
+bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const double* eps, double alpha,
+                        double lambda, void* scores_out, int32_t k, int32_t exclude_self, int32_t* topk_ids,
+                        void* topk_vals, bhpp_query_stats* stats, hipStream_t s) {
+    const int per = kMaxCols;
+    for (int base = 0; base < n; base += per) {
+        const int nc = n - base < per ? n - base : per;
+        bhpp_status rc = ensure_workspace(g, next_pow2(nc));
+        if (rc) return rc;
+        std::vector<ColState> hs;
+        std::vector<int> steps;
+        void* scores = scores_out ? (void*)((char*)scores_out + (size_t)base * g->nu * g->elem)
+                                  : (k > 0 ? g->ws.scores : nullptr);
+        if (g->dtype == BHPP_DTYPE_F64)
+            rc = run_tile_dispatch<double, double>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs,
+                                                   steps);
+        else
+            rc = run_tile_dispatch<float, float>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs,
+                                                 steps);
+        if (rc) return rc;
+        if (k > 0) {
+            std::vector<int32_t> ex(nc, -1);
+            if (exclude_self)
+                for (int c = 0; c < nc; ++c) ex[c] = src_ext[base + c];
+            int32_t* d_ex = reinterpret_cast<int32_t*>(g->ws.red);
+            BHPP_HIP(hipMemcpyAsync(d_ex, ex.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
+            rc = topk_rows(scores, nc, g->nu, k, d_ex, g->dtype, topk_ids + (size_t)base * k,
+                           (char*)topk_vals + (size_t)base * k * g->elem, s);
+            if (rc) return rc;
+            BHPP_HIP(hipStreamSynchronize(s));   // d_ex is borrowed from red
+        }
+        if (stats) {
+            for (int c = 0; c < nc; ++c) {
+                const ColState& cs = hs[c];
+                bhpp_query_stats& q = stats[base + c];
+                q.ss_sel_iters = cs.ss_sel_iters;
+                q.ss_seq_iters = cs.ss_seq_iters;
+                q.pi_sel_iters = cs.pi_sel_iters;
+                q.t = cs.t;
+                q.ss_switched = cs.ss_switched;
+                q.pi_returned = cs.pi_returned;
+                q.steps = cs.steps;
+                q.reserved = 0;
+                q.np_ss = cs.np_ss;
+                q.np_pi = cs.np_pi;
+                q.gamma = cs.gamma;
+                q.sum_r_ss = cs.sum_r_ss;
+                q.sum_rf = cs.sum_rf;
+            }
+        }
+    }
+    return BHPP_OK;
+}
+
+// Lemma 4: rho = PowerIteration(e = 1, tau) computed in FP64 with one column
+// in a private workspace; lambda = min(max rho + |U| (1-alpha)^(tau+1),
+// max ws / min ws).
+template <typename WT>
+static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t s, double* out) {
+    const Geometry G = geometry(g);
+    Block b{};
+    size_t nU = (size_t)g->nu, nV = (size_t)g->nv;
+    auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
+    bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.Q, nV * 8) &&
+              A(&b.partA, (size_t)g->tiles_v.n_slots * 8) && A((void**)&b.partA_any, (size_t)g->tiles_v.n_slots * 4) &&
+              A(&b.partB, (size_t)g->tiles_u.n_slots * 8) && A((void**)&b.red, (size_t)kNumRed * G.n_part * 8) &&
+              A((void**)&b.st, sizeof(ColState)) && A((void**)&b.n_active, 64) &&
+              hipHostMalloc((void**)&b.h_active, 64) == hipSuccess;
+    bhpp_status rc = ok ? BHPP_OK : BHPP_OUT_OF_MEMORY;
+    const bool saved_prof = g->prof_on;
+    g->prof_on = false;
+    if (rc == BHPP_OK) {
+        ColState c;
+        memset(&c, 0, sizeof(c));
+        c.alpha = alpha;
+        c.k_ss = c.k_pi = 1e300;
+        c.ln_inv = log(1.0 / (1.0 - alpha));
+        if (tau > 0) {
+            c.t_rem = tau;
+            c.mode = MODE_POWER;
+            c.ruleA = c.ruleB = RULE_ALL;
+        } else {
+            c.mode = MODE_FINAL;
+            c.ruleA = RULE_NONE;
+            c.ruleB = RULE_ALL;
+        }
+        int32_t one = 1;
+        if (hipMemcpyAsync(b.st, &c, sizeof(c), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(b.n_active, &one, 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = BHPP_DEVICE_ERROR;
+        hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, as<double>(b.Y), nU, 1.0);
+        hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, as<double>(b.ACC), nU, 0.0);
+        if (rc == BHPP_OK) rc = run_block<1, double, WT>(g, b, s, nullptr);
+        if (rc == BHPP_OK) {
+            std::vector<double> rho(nU);
+            if (hipMemcpy(rho.data(), b.ACC, nU * 8, hipMemcpyDeviceToHost) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+            double rmax = 0.0;
+            for (double v : rho) rmax = v > rmax ? v : rmax;
+            const double a = rmax + (double)g->nu * pow(1.0 - alpha, (double)tau + 1.0);
+            const double bnd = g->info.ws_u_max / g->info.ws_u_min;
+            *out = a < bnd ? a : bnd;
+        }
+    }
+    g->prof_on = saved_prof;
+    hipFree(b.Y); hipFree(b.ACC); hipFree(b.Q); hipFree(b.partA); hipFree(b.partA_any); hipFree(b.partB);
+    hipFree(b.red); hipFree(b.st); hipFree(b.n_active);
+    if (b.h_active) hipHostFree(b.h_active);
+    return rc;
+}
+
+bhpp_status compute_lambda(Graph* g, double alpha, int32_t tau, hipStream_t s, double* lambda_out) {
+    if (g->dtype == BHPP_DTYPE_F64) return lambda_impl<double>(g, alpha, tau, s, lambda_out);
+    return lambda_impl<float>(g, alpha, tau, s, lambda_out);
+}
+
+}  // namespace bhpp

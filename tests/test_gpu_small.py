@@ -1,0 +1,175 @@
+"""GPU parity on the 2k x 3k, 20k-edge graph (FP64) and small FP32 graphs.
+
+Reference values come only from the FP64 oracle (dense exact solve, truncated
+series, O-method) on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bh():
+    import paper_2312_06724_amd as bh
+    return bh
+
+
+@pytest.fixture(scope="module")
+def small(small_graph, bh):
+    s = small_graph
+    el = s["el"]
+    print(f"[gpu] building small graph {el.n_u}x{el.n_v} {el.n_e} edges (f64)", flush=True)
+    G = bh.Graph.from_edges(el, alpha=0.15, dtype="f64", keep_external=True)
+    return dict(s, G=G)
+
+
+def test_graph_index_bit_exact(small):
+    ex = {k: v.cpu().numpy() for k, v in small["G"].export().items()}
+    ref = small["g"].export()
+    for k in ("rp_u", "ci_u", "rp_v", "ci_v"):
+        assert np.array_equal(ex[k], ref[k]), k
+    for k in ("w_u", "w_v", "ws_u", "ws_v"):
+        assert np.array_equal(ex[k], ref[k]), k   # FP64 sums in the same order
+
+
+def test_graph_info_and_lambda(small):
+    inf = small["G"].info()
+    g = small["g"]
+    assert inf["n_edges"] == g.n_e
+    assert inf["tau"] == g.default_tau(0.15)
+    lam_ref = g.lambda_(0.15)
+    assert abs(inf["lambda"] - lam_ref) <= 1e-9 * lam_ref
+    assert abs(inf["eps_b_ratio"] - g.eps_b(1.0)) <= 1e-15
+    assert inf["isolated_u"] == int((g.ws_u == 0).sum())
+    # Lemma 4 against the dense solve
+    assert inf["lambda"] >= small["Pi"].sum(0).max() - 1e-9
+
+
+def test_single_queries_theorem3_and_oracle(small):
+    G, Pi, g = small["G"], small["Pi"], small["g"]
+    eps = 1e-7
+    for u in small["sources"]:
+        u = int(u)
+        print(f"[gpu] single query u={u}", flush=True)
+        b, st = G.query(u, eps)
+        b = b.cpu().numpy()
+        beta = Pi[u, :] + Pi[:, u]
+        d = beta - b
+        assert d.min() >= -1e-10 and d.max() <= eps + 1e-10, (u, d.min(), d.max())
+        ref, _, _, st_ref = g.approx_bhpp(u, 0.15, eps)
+        assert np.abs(ref - b).max() <= eps
+        # same algorithm, same FP64 arithmetic up to summation order
+        assert st["t"] == st_ref["t"] and st["ss_switched"] == st_ref["ss_switched"], (st, st_ref)
+
+
+def test_batch_equals_single_and_topk_bit_exact(small):
+    G, Pi = small["G"], small["Pi"]
+    src = small["sources"]
+    eps, k = 1e-7, 50
+    print(f"[gpu] batch of {len(src)} sources, top-{k}", flush=True)
+    out = G.query_batch(src, eps, k=k, exclude_self=True)
+    S = out["scores"].cpu().numpy()
+    ids = out["ids"].cpu().numpy()
+    vals = out["vals"].cpu().numpy()
+    for i, u in enumerate(src):
+        u = int(u)
+        one = G.query(u, eps)[0].cpu().numpy()
+        assert np.abs(one - S[i]).max() <= 1e-12
+        beta = Pi[u, :] + Pi[:, u]
+        d = beta - S[i]
+        assert d.min() >= -1e-10 and d.max() <= eps + 1e-10
+        rid, rval = oracle.topk_bruteforce(S[i], k, exclude=u)
+        assert np.array_equal(ids[i], rid)
+        assert np.array_equal(vals[i], rval)
+        # against the exact scores: identical sets unless the k-th gap is within eps
+        eid, ev = oracle.topk_bruteforce(beta, k + 1, exclude=u)
+        if ev[k - 1] - ev[k] > eps + 1e-9:
+            assert set(ids[i]) == set(eid[:k])
+
+
+def test_mixed_eps_in_one_batch(small):
+    G, Pi = small["G"], small["Pi"]
+    src = small["sources"][:6]
+    eps = np.array([1e-2, 1e-3, 1e-4, 1e-5, 1e-6, 1e-7])
+    S = G.query_batch(src, eps)["scores"].cpu().numpy()
+    for i, u in enumerate(src):
+        u = int(u)
+        d = (Pi[u, :] + Pi[:, u]) - S[i]
+        assert d.min() >= -1e-10 and d.max() <= eps[i] + 1e-10
+
+
+def test_error_codes(small, bh):
+    G, g = small["G"], small["g"]
+    iso = int(np.nonzero(g.ws_u == 0)[0][0])
+    with pytest.raises(bh.BhppError) as e:
+        G.query(iso, 1e-6)
+    assert e.value.code == -3
+    with pytest.raises(bh.BhppError) as e:
+        G.query(g.n_u, 1e-6)
+    assert e.value.code == -2
+    with pytest.raises(bh.BhppError) as e:
+        G.query(int(small["sources"][0]), 0.0)
+    assert e.value.code == -1
+    with pytest.raises(bh.BhppError) as e:
+        G.query_batch(small["sources"][:2], 1e-6, k=g.n_u)
+    assert e.value.code == -1
+
+
+def test_build_rejects_bad_input(bh):
+    eu = np.array([0, 1], np.int32)
+    ev = np.array([0, 1], np.int32)
+    with pytest.raises(bh.BhppError) as e:
+        bh.Graph(2, 2, eu, ev, np.array([1.0, -1.0]))
+    assert e.value.code == -4
+    with pytest.raises(bh.BhppError) as e:
+        bh.Graph(2, 2, eu, np.array([0, 2], np.int32), np.array([1.0, 1.0]))
+    assert e.value.code == -2
+
+
+def test_closed_form_graphs(bh):
+    import pins_lib
+    for name, mk in pins_lib.CLOSED_FORMS.items():
+        (nu, nv, eu, ev, w), Pi = mk()
+        for dt in ("f64", "f32"):
+            G = bh.Graph(nu, nv, eu, ev, w, dtype=dt)
+            S = G.query_batch(np.arange(nu), 1e-6)["scores"].cpu().numpy()
+            for u in range(nu):
+                d = (Pi[u, :] + Pi[:, u]) - S[u]
+                tol = 1e-10 if dt == "f64" else 2e-6
+                assert d.min() >= -tol and d.max() <= 1e-6 + tol, (name, dt, u)
+
+
+def test_duplicate_edges_merged(bh):
+    eu = np.array([1, 0, 1, 1, 0], np.int32)
+    ev = np.array([2, 0, 2, 0, 0], np.int32)
+    w = np.array([0.1, 2.0, 0.2, 5.0, 3.0])
+    G = bh.Graph(2, 3, eu, ev, w, dtype="f64", keep_external=True)
+    ex = {k: v.cpu().numpy() for k, v in G.export().items()}
+    ref = oracle.Graph(2, 3, eu, ev, w).export()
+    for k in ("rp_u", "ci_u", "w_u", "rp_v", "ci_v", "w_v", "ws_u", "ws_v"):
+        assert np.array_equal(ex[k], ref[k]), k
+
+
+@pytest.mark.parametrize("reorder", [True, False])
+def test_fp32_random_graph_batch(bh, reorder):
+    """FP32 values and accumulation; several tiles, split rows and a ragged
+    last source block (70 sources = 64 + 6)."""
+    el = synth.chung_lu(3000, 5000, 60000, 2.1, "lognormal", 77)
+    g = oracle.Graph.from_edges(el)
+    src = synth.sample_sources(el, 70, "uniform", 5)
+    G = bh.Graph.from_edges(el, dtype="f32", reorder=reorder)
+    eps = 1e-6
+    print(f"[gpu] fp32 random graph reorder={reorder}", flush=True)
+    out = G.query_batch(src, eps, k=20)
+    S = out["scores"].cpu().numpy().astype(np.float64)
+    ex = g.exact_beta_many(src, 0.15, tail=1e-12)
+    d = ex - S
+    assert d.min() >= -1e-6 and d.max() <= eps + 1e-6, (d.min(), d.max())
+    ids = out["ids"].cpu().numpy()
+    for i, u in enumerate(src):
+        rid, _ = oracle.topk_bruteforce(out["scores"][i].cpu().numpy(), 20, exclude=int(u))
+        assert np.array_equal(ids[i], rid)
