@@ -1,0 +1,188 @@
+"""Benchmark: approximate BHPP queries per second on one MI355X.
+
+Workload (one "step"): 64 query sources drawn uniformly from the non-isolated
+U nodes of a seeded Chung-Lu bipartite graph with |U| = 1M, |V| = 2M, 20M
+edges, degree exponent 2.1, lognormal(0,1) weights (a Last.fm-sized stand-in
+for the paper's datasets); alpha = 0.15, eps = 1e-6; each query returns
+beta'(u, x) for all x in U plus its top-100 (Algorithm 5, then top-k). The 64
+sources run together as 64 columns of one dense residue block, in FP32 with
+FP32 accumulation. Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line. Extra fields: the same graph queried one source at a
+time ("single_source_qps"), the roofline of the dominant kernel measured with
+HIP events on the query stream, and the FP64 CPU oracle timed on a bounded
+sample of the same queries.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_digest(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if the
+    counters were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    cur = source_digest(os.path.join(ROOT, "paper_2312_06724_amd", "csrc", "sweep.hip"))
+    ent = d.get(kernel)
+    if not ent or ent.get("sweep_hip_sha") != cur:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def cpu_baseline(el, sources, wl, n_threads):
+    import oracle
+    g = oracle.Graph.from_edges(el)
+    lam = g.lambda_(wl.alpha)
+    eps_b = g.eps_b(wl.eps)
+    sample = sources[:n_threads]
+    t0 = time.perf_counter()
+    _, st = g.approx_bhpp_many(sample, wl.alpha, wl.eps, eps_b, lam, nthreads=n_threads, keep=False)
+    dt = time.perf_counter() - t0
+    return dict(value=len(sample) / dt, unit="queries/s", cores=n_threads, kind="oracle",
+                sample=f"{len(sample)} of the {len(sources)} sources, one per thread, FP64 Approx-BHPP "
+                       f"(Algorithms 1-5), lambda and eps_b precomputed; {dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--single", type=int, default=8, help="sources timed one at a time")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (known-size kernel for scaling HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(sources shard across GPUs without communication; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2312_06724_amd as bh
+    import synth
+
+    wl = synth.MEDIUM
+    t0 = time.perf_counter()
+    el = wl.graph()
+    src = wl.sources(el)
+    log(f"graph {wl.name}: {el.n_e} edges generated in {time.perf_counter() - t0:.1f}s")
+    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
+    info = G.info()
+    log(f"built on GPU in {info['build_ms']:.1f} ms; lambda={info['lambda']:.3f} eps_b/eps={info['eps_b_ratio']:.4f}")
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written")
+        del a, b
+
+    def step():
+        return G.query_batch(src, wl.eps, k=wl.k, exclude_self=True, scores=True, stats=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    G.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = G.profile_read()
+    G.profile(False)
+    qps = wl.n_sources * args.steps / dt
+
+    stats = G.query_batch(src, wl.eps, k=0, scores=False, stats=True)["stats"]
+    sweeps = float(np.mean([s["steps"] for s in stats]))
+
+    # plain single-source path on the same graph
+    single_qps = None
+    if args.single > 0:
+        G.query(int(src[0]), wl.eps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for u in src[:args.single]:
+            G.query(int(u), wl.eps, with_stats=False)
+        torch.cuda.synchronize()
+        single_qps = args.single / (time.perf_counter() - t1)
+        log(f"single-source: {single_qps:.2f} q/s")
+
+    # roofline of the dominant kernel
+    names = ["V-side gather (k_gather64, SIDE_A)", "U-side gather (k_gather64)", "U-side update (k_update)"]
+    dom = int(np.argmax(prof["ms"]))
+    avg_ms = prof["ms"][dom] / max(1, prof["launches"][dom])
+    bytes_per_launch = prof["bytes"][dom] / max(1, prof["launches"][dom])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernel_id = ["gather_a", "gather_b", "update"][dom]
+    roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=stored_traffic(kernel_id),
+                    avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom],
+                    algorithmic_bytes_per_launch=int(bytes_per_launch),
+                    share_of_step=round(sum(prof["ms"]) / (dt * 1e3), 3),
+                    kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
+                                     gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
+                             for i, k in enumerate(["gather_a", "gather_b", "update"])})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        n = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(f"CPU oracle baseline on {n} threads ...")
+        cpu = cpu_baseline(el, src, wl, n)
+
+    out = {
+        "metric": "BHPP queries/s at eps=1e-6 (64 sources batched, top-100)",
+        "value": round(qps, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_u": el.n_u, "n_v": el.n_v, "n_edges": el.n_e,
+                   "sources_per_step": wl.n_sources, "source_sampling": "uniform non-isolated",
+                   "alpha": wl.alpha, "eps": wl.eps, "k": wl.k, "lambda": round(info["lambda"], 3)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "single_source_qps": round(single_qps, 3) if single_qps else None,
+        "mean_sweeps_per_query": sweeps,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -189,18 +189,18 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
                               void* hip_stream);
 
 /*
- * Device-time profile of the two gather kernels of the two-hop sweep (the
- * U->V half and the V->U half). While enabled, every launch of those kernels
- * on a query stream is bracketed by HIP events on that stream and the elapsed
- * times are accumulated; bhpp_profile_read synchronises and returns the
- * totals: ms[0], launches[0] for the V-side half, ms[1], launches[1] for the
- * U-side half, and the algorithmic bytes those launches moved in total
- * (bytes[0..1]: per launch, the adjacency read once plus each dense vector
- * read or written once). enable = 0 stops recording; enable = 1 also clears
- * the totals.
+ * Device-time profile of the sweep kernels. While enabled, every launch of the
+ * V-side gather (kind 0), the U-side gather (kind 1) and the U-side update
+ * (kind 2) on a query stream is bracketed by HIP events on that stream and the
+ * elapsed times are accumulated; bhpp_profile_read synchronises and returns,
+ * per kind, the total milliseconds, the number of launches and the
+ * algorithmic bytes those launches moved in total (per launch: the adjacency
+ * read once plus each dense vector read or written once). enable = 0 stops
+ * recording; enable = 1 also clears the totals. Errors: INVALID_ARG,
+ * DEVICE_ERROR.
  */
 bhpp_status bhpp_profile_enable(bhpp_graph* g, int32_t enable);
-bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[2], int64_t launches[2], double bytes[2]);
+bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[3], int64_t launches[3], double bytes[3]);
 
 /* Free the handle and all device memory it owns (NULL is ignored). The caller
    must make sure no work using it is still running. */

@@ -177,15 +177,17 @@ bhpp_status bhpp_profile_enable(bhpp_graph* h, int32_t enable) {
         g->prof_ev.clear();
         g->prof_kind.clear();
         g->prof_b.clear();
-        g->prof_ms[0] = g->prof_ms[1] = 0.0;
-        g->prof_n[0] = g->prof_n[1] = 0;
-        g->prof_bytes[0] = g->prof_bytes[1] = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            g->prof_ms[k] = 0.0;
+            g->prof_n[k] = 0;
+            g->prof_bytes[k] = 0.0;
+        }
     }
     g->prof_on = enable != 0;
     return BHPP_OK;
 }
 
-bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[2], int64_t launches[2], double bytes[2]) {
+bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[3], int64_t launches[3], double bytes[3]) {
     if (!h || !h->g || !ms || !launches || !bytes) return BHPP_INVALID_ARG;
     Graph* g = h->g;
     std::lock_guard<std::mutex> lock(g->mu);
@@ -206,7 +208,7 @@ bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[2], int64_t launches[2], 
     g->prof_ev.clear();
     g->prof_kind.clear();
     g->prof_b.clear();
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         ms[k] = g->prof_ms[k];
         launches[k] = g->prof_n[k];
         bytes[k] = g->prof_bytes[k];

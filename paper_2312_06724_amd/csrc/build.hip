@@ -135,6 +135,10 @@ __global__ void k_perm_from_keys(int32_t n, const uint64_t* keys, int32_t* iperm
     iperm[i] = x;
     perm[x] = i;
 }
+__global__ void k_degrees(int32_t n, const int64_t* rp, int32_t* deg) {
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < n) deg[x] = (int32_t)(rp[x + 1] - rp[x]);
+}
 // inverse weighted degree in internal order; 0 for isolated nodes
 template <typename VT>
 __global__ void k_inv_ws(int32_t n, const int32_t* iperm, const double* ws_ext, VT* out) {
@@ -171,6 +175,10 @@ bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, TileSet*
     };
     while (row < end) {
         const int64_t d = rp[row + 1] - rp[row];
+        if (d == 0) {   // rows without edges need no work and stay out of every tile
+            ++row;
+            continue;
+        }
         if (d > T) {
             SplitRow s{row, slot, 0, 0};
             for (int64_t e0 = rp[row]; e0 < rp[row + 1]; e0 += T) {
@@ -186,7 +194,7 @@ bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, TileSet*
         int64_t edges = 0, maxd = 0;
         while (row < end) {
             const int64_t dd = rp[row + 1] - rp[row];
-            if (dd > T) break;
+            if (dd == 0 || dd > T) break;
             if (row > start && (edges + dd > T || row - start >= 512)) break;
             edges += dd;
             maxd = std::max(maxd, dd);
@@ -215,7 +223,7 @@ void free_tiles(TileSet* ts) {
 
 void free_graph(Graph* g) {
     if (!g) return;
-    void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->inv_ws_u_f, g->inv_ws_v_f,
+    void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u,
                     g->inv_ws_u_d, g->inv_ws_v_d, g->perm_u, g->iperm_u, g->x_rp_u, g->x_ci_u, g->x_w_u,
                     g->x_rp_v, g->x_ci_v, g->x_w_v, g->x_ws_u, g->x_ws_v};
     for (void* p : ptrs) hipFree(p);
@@ -414,6 +422,8 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
         hipLaunchKernelGGL(k_cast<WT>, grid_for(m), dim3(256), 0, s, m, w_int_u, (WT*)g->w_u);
         hipLaunchKernelGGL(k_cast<WT>, grid_for(m), dim3(256), 0, s, m, w_int_v, (WT*)g->w_v);
     }
+    BHPP_HIP(hipMalloc((void**)&g->deg_u, sizeof(int32_t) * nu));
+    hipLaunchKernelGGL(k_degrees, grid_for(nu), dim3(256), 0, s, nu, g->rp_u, g->deg_u);
     BHPP_HIP(hipMalloc((void**)&g->inv_ws_u_d, sizeof(double) * nu));
     BHPP_HIP(hipMalloc((void**)&g->inv_ws_v_d, sizeof(double) * nv));
     hipLaunchKernelGGL(k_inv_ws<double>, grid_for(nu), dim3(256), 0, s, nu, g->iperm_u, ws_u, g->inv_ws_u_d);

@@ -115,6 +115,7 @@ struct Graph {
     int64_t* rp_v = nullptr; int32_t* ci_v = nullptr; void* w_v = nullptr;
     float* inv_ws_u_f = nullptr; float* inv_ws_v_f = nullptr;     // F32 graphs
     double* inv_ws_u_d = nullptr; double* inv_ws_v_d = nullptr;   // both dtypes
+    int32_t* deg_u = nullptr;    // degree of each internal U row
     int32_t* perm_u = nullptr;   // external U id -> internal
     int32_t* iperm_u = nullptr;  // internal -> external
     TileSet tiles_u, tiles_v;
@@ -134,9 +135,9 @@ struct Graph {
     bool sticky_error = false;
     // profiling of the sweep kernels
     bool prof_on = false;
-    double prof_ms[2] = {0, 0};
-    int64_t prof_n[2] = {0, 0};
-    double prof_bytes[2] = {0, 0};
+    double prof_ms[3] = {0, 0, 0};
+    int64_t prof_n[3] = {0, 0, 0};
+    double prof_bytes[3] = {0, 0, 0};
     std::vector<hipEvent_t> prof_ev;      // pairs, recorded on the query stream
     std::vector<int32_t> prof_kind;
     std::vector<double> prof_b;

@@ -15,15 +15,20 @@
 // (Algorithm 5). PowerIteration(y, t) (Algorithm 1) is t pushes of every node
 // followed by ACC += alpha y: alpha sum_{l<=t} (1-alpha)^l y P^l.
 //
-// One sweep is two gathers, each over one adjacency direction:
-//   pass A (rows v of W^T): Q(v) = (1-alpha)/ws(v) * sum_x w(x,v) y_S(x)/ws(x)
-//   pass B (rows x of W):   y(x) <- y(x) - y_S(x) + sum_v w(x,v) Q(v),
-//                           ACC(x) += alpha y_S(x), and the reductions that
-//                           the phase control needs (Red in common.h).
+// One sweep (one iteration of Algorithm 2's loop) is:
+//   gather A (rows v of W^T): Q(v) = (1-alpha)/ws(v) * sum_x w(x,v) y_S(x)/ws(x)
+//   gather B (rows x of W):   G(x) = sum_v w(x,v) Q(v)
+//   update (rows x of U):     y(x) <- y(x) - y_S(x) + G(x), ACC(x) += alpha y_S(x),
+//                             and the per-source reductions the phase control needs
+//   control (one block per source): the tests of Algorithms 3-4.
 // Up to 64 sources run together; source c of a block occupies column c of the
-// node-major arrays Y[n_u][C], ACC[n_u][C], Q[n_v][C] so one adjacency entry
-// feeds C lanes with one contiguous load.
+// node-major arrays Y[n_u][C], ACC[n_u][C], G[n_u][C], Q[n_v][C], so one
+// adjacency entry feeds C lanes with one contiguous load. The gathers contain
+// no loads besides the row gathers inside their inner loop (row metadata is
+// loaded per chunk of entries), so the row gathers stay in flight.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.h"
@@ -35,11 +40,12 @@ namespace bhpp {
 // ---------------------------------------------------------------------------
 constexpr int kWavesPerBlock = kPassThreads / kWave;
 constexpr int kMaxPassBlocks = 2048;
-constexpr int kMaxFixBlocks = 256;
+constexpr int kMaxFixBlocks = 1024;
+constexpr int kUpdateBlocks = 2048;
 
 struct Geometry {
-    int blkA, blkFA, blkB, blkFB;
-    int offA, offFA, offB, offFB, n_part;
+    int blkA, blkFA, blkB, blkFB, blkU;
+    int offA, offFA, offU, n_part;   // reduction slots: gather A, fix-up A, update
 };
 
 static Geometry geometry(const Graph* g) {
@@ -47,13 +53,13 @@ static Geometry geometry(const Graph* g) {
     auto clampi = [](long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); };
     G.blkA = clampi((g->tiles_v.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxPassBlocks);
     G.blkB = clampi((g->tiles_u.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxPassBlocks);
-    G.blkFA = clampi((g->tiles_v.n_split + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxFixBlocks);
-    G.blkFB = clampi((g->tiles_u.n_split + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxFixBlocks);
+    G.blkFA = clampi(g->tiles_v.n_split, 1, kMaxFixBlocks);
+    G.blkFB = clampi(g->tiles_u.n_split, 1, kMaxFixBlocks);
+    G.blkU = kUpdateBlocks;
     G.offA = 0;
     G.offFA = G.blkA;
-    G.offB = G.offFA + G.blkFA;
-    G.offFB = G.offB + G.blkB;
-    G.n_part = G.offFB + G.blkFB;
+    G.offU = G.offFA + G.blkFA;
+    G.n_part = G.offU + G.blkU;
     return G;
 }
 
@@ -66,10 +72,23 @@ __device__ __forceinline__ bool select_push(int rule, VT y, VT yw, VT kss, VT kp
     return rule == RULE_SS ? (yw > kss) : rule == RULE_PI ? (y > kpi) : rule == RULE_ALL ? (y > VT(0)) : false;
 }
 
+// Branch-free form of select_push for the inner loops: the rule of a lane
+// becomes (use y/ws(x) or y, threshold); RULE_NONE gets an infinite threshold.
+template <typename VT>
+struct PushTest {
+    bool by_ws;
+    VT thr;
+    __device__ __forceinline__ PushTest(int rule, VT kss, VT kpi) {
+        by_ws = rule == RULE_SS;
+        thr = rule == RULE_SS ? kss : rule == RULE_PI ? kpi : rule == RULE_ALL ? VT(0) : VT(INFINITY);
+    }
+    __device__ __forceinline__ bool operator()(VT y, VT yw) const { return (by_ws ? yw : y) > thr; }
+};
+
 // Sum `v` over the lanes of the block that serve the same column and store
-// it at out[col * n_part + blockIdx.x] (deterministic order).
+// it at out[col * n_part + slot] (fixed order, so results are deterministic).
 template <int COLS>
-__device__ __forceinline__ void block_column_sum(double v, double* sh, double* out, int n_part) {
+__device__ __forceinline__ void block_column_sum(double v, double* sh, double* out, int n_part, int slot) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
     for (int m = COLS; m < kWave; m <<= 1) v += __shfl_xor(v, m);
@@ -78,71 +97,64 @@ __device__ __forceinline__ void block_column_sum(double v, double* sh, double* o
     if ((int)threadIdx.x < COLS) {
         double s = 0.0;
         for (int w = 0; w < kWavesPerBlock; ++w) s += sh[w * kWave + threadIdx.x];
-        out[(size_t)threadIdx.x * n_part + blockIdx.x] = s;
+        out[(size_t)threadIdx.x * n_part + slot] = s;
     }
     __syncthreads();
 }
 
+// Broadcast lane j's value to the whole wavefront (j uniform).
+__device__ __forceinline__ int32_t rl(int32_t v, int j) { return __builtin_amdgcn_readlane(v, j); }
+__device__ __forceinline__ float rl(float v, int j) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j)); }
+__device__ __forceinline__ int64_t rl(int64_t v, int j) {
+    const int32_t lo = __builtin_amdgcn_readlane((int32_t)(v & 0xFFFFFFFF), j);
+    const int32_t hi = __builtin_amdgcn_readlane((int32_t)(v >> 32), j);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double rl(double v, int j) { return __longlong_as_double(rl((int64_t)__double_as_longlong(v), j)); }
+
+template <typename T>
+__device__ __forceinline__ T ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_nt(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
 template <typename VT, typename WT>
-struct PassArgs {
+struct GatherArgs {
     const Tile* tiles;
     int n_tiles;
     const int64_t* rp;
     const int32_t* ci;
     const WT* w;
-    const VT* inv_ws_row;   // 1/ws of the row side
-    const VT* inv_ws_col;   // 1/ws of the neighbour side
-    const VT* X;            // gathered vector (pass A: Y over U, pass B: Q over V)
-    VT* OUT;                // pass A: Q; pass B: Y (updated in place)
-    VT* ACC;                // pass B only
-    VT* part;               // split-row partial sums
-    int32_t* part_any;
+    const VT* inv_ws_row;   // 1/ws of the row side (gather A: V)
+    const VT* inv_ws_col;   // 1/ws of the neighbour side (gather A: U)
+    const VT* X;            // gathered vector: gather A Y (over U), gather B Q (over V)
+    VT* OUT;                // gather A: Q, gather B: G
+    VT* part;               // split-row partial sums [slots][COLS]
+    int32_t* part_any;      // gather A: whether any neighbour was pushed
     const ColState* st;
     const int32_t* n_active;
     double* red;            // [kNumRed][COLS][n_part]
     int n_part;
-    int red_off;
+    int red_slot;           // first reduction slot of this launch
+    int nt_stream;          // stream adjacency and row outputs past the caches
 };
 
-// Epilogue of pass B for row x and one column: apply the push of x decided by
-// ruleB, add the gathered inflow g, and accumulate the reductions.
-template <typename VT>
-__device__ __forceinline__ void epilogue_b(VT* Y, VT* ACC, size_t idx, VT g, VT iw, int ruleB, int convert,
-                                           VT kss, VT kpi, VT ws_src, VT alpha, double deg, double (&r)[kNumRed]) {
-    VT y = Y[idx];
-    VT yw = y * iw;
-    bool sel = select_push<VT>(ruleB, y, yw, kss, kpi);
-    VT s = sel ? y : VT(0);
-    VT a = ACC[idx];
-    if (convert) a = a * (VT(1) + ws_src * iw);   // Eq. (fppr) + pi_b: ACC -> beta' part
-    a += alpha * s;
-    VT yn = (y - s) + g;
-    Y[idx] = yn;
-    ACC[idx] = a;
-    VT tn = yn * iw;
-    if (sel) r[RED_NP] += deg;
-    r[RED_CNT_SS] += (tn > kss) ? 1.0 : 0.0;
-    r[RED_SUM_R] += (double)tn;
-    r[RED_CNT_PI] += (yn > kpi) ? 1.0 : 0.0;
-    r[RED_SUM_Y] += (double)yn;
-}
-
 // ---------------------------------------------------------------------------
-// pass A / pass B: one wavefront per tile, lanes = (row group, edge slot, column)
+// Gathers for 1..32 sources: a wavefront takes a tile; lanes are (row group,
+// edge slot, column); rows of a tile have similar degree (degree order), so
+// the edge slots per row follow the tile's largest degree.
 // ---------------------------------------------------------------------------
-template <int COLS, typename VT, typename WT, bool PASS_B>
-__global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs<VT, WT> p) {
+template <int COLS, typename VT, typename WT, bool SIDE_A>
+__global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
     __shared__ double sh[kPassThreads];
     if (*p.n_active == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int col = lane & (COLS - 1);
     const ColState& cs = p.st[col];
-    const int rule = PASS_B ? cs.ruleB : cs.ruleA;
-    const int convert = cs.convert;
-    const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
-    const VT one_minus_alpha = VT(1) - alpha;
-    double r[kNumRed] = {0, 0, 0, 0, 0};
+    const int rule = cs.ruleA;
+    const PushTest<VT> test(rule, (VT)cs.k_ss, (VT)cs.k_pi);
+    const VT one_minus_alpha = VT(1) - (VT)cs.alpha;
+    double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
         const Tile T = p.tiles[t];
@@ -164,89 +176,252 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(PassArgs<VT, WT> p) {
             }
             VT acc = VT(0);
             int any = 0;
-            if (PASS_B || rule != RULE_NONE) {
+            if (!SIDE_A || rule != RULE_NONE) {
 #pragma unroll 4
                 for (int64_t e = e0 + slot; e < e1; e += epar) {
                     const int32_t x = p.ci[e];
                     const VT ww = (VT)p.w[e];
                     const VT v = p.X[(size_t)x * COLS + col];
-                    if (PASS_B) {
+                    if (!SIDE_A) {
                         acc += ww * v;
                     } else {
                         const VT vw = v * p.inv_ws_col[x];
-                        if (select_push<VT>(rule, v, vw, kss, kpi)) {
-                            acc += ww * vw;
-                            any = 1;
-                        }
+                        acc += test(v, vw) ? ww * vw : VT(0);
                     }
                 }
             }
+            // a pushed entry adds a positive term, so acc > 0 iff some neighbour was pushed
+            if (SIDE_A) any = acc > VT(0) ? 1 : 0;
 #pragma unroll
             for (int m = COLS; m < kWave; m <<= 1) {
                 if (m < gl) {
                     acc += __shfl_xor(acc, m);
-                    if (!PASS_B) any |= __shfl_xor(any, m);
+                    if (SIDE_A) any |= __shfl_xor(any, m);
                 }
             }
             if (slot == 0 && valid) {
                 const size_t idx = (size_t)row * COLS + col;
                 if (T.slot >= 0) {
                     p.part[(size_t)T.slot * COLS + col] = acc;
-                    if (!PASS_B) p.part_any[(size_t)T.slot * COLS + col] = any;
-                } else if (!PASS_B) {
+                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = any;
+                } else if (SIDE_A) {
                     p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * acc;
-                    if (any) r[RED_NP] += (double)(e1 - e0);
+                    if (any) np += (double)(e1 - e0);
                 } else {
-                    epilogue_b<VT>(p.OUT, p.ACC, idx, acc, p.inv_ws_row[row], rule, convert, kss, kpi, ws_src,
-                                   alpha, (double)(e1 - e0), r);
+                    p.OUT[idx] = acc;
                 }
             }
         }
     }
-    double* base = p.red + p.red_off;
-#pragma unroll
-    for (int k = 0; k < kNumRed; ++k)
-        block_column_sum<COLS>(r[k], sh, base + (size_t)k * COLS * p.n_part, p.n_part);
+    if (SIDE_A) block_column_sum<COLS>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
+                                       p.red_slot + blockIdx.x);
 }
 
-// Fix-up of split rows: add the pieces in slot order, then the same epilogue.
-template <int COLS, typename VT, typename WT, bool PASS_B>
-__global__ __launch_bounds__(kPassThreads) void k_fixup(PassArgs<VT, WT> p, const SplitRow* split, int n_split) {
+// ---------------------------------------------------------------------------
+// Gather for 64 sources: one lane per source, one row at a time. Per chunk of
+// 64 adjacency entries the wavefront loads, one entry or row per lane, the
+// neighbour ids, weights, the end offsets of the next 64 rows and their 1/ws;
+// it then keeps INF row gathers in flight, taking each entry's neighbour id
+// from its lane with readlane. A row whose last entry is reached is flushed
+// with stores only. Tiles hold no empty rows.
+// ---------------------------------------------------------------------------
+template <typename VT, typename WT, bool SIDE_A, int INF>
+__global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p) {
+    constexpr int COLS = 64;
     __shared__ double sh[kPassThreads];
     if (*p.n_active == 0) return;
+    const bool ns = p.nt_stream != 0;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
-    const int col = lane & (COLS - 1);
+    const int col = lane;
     const ColState& cs = p.st[col];
-    const int rule = PASS_B ? cs.ruleB : cs.ruleA;
-    const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
-    const VT one_minus_alpha = VT(1) - alpha;
-    double r[kNumRed] = {0, 0, 0, 0, 0};
+    const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
+    const VT one_minus_alpha = VT(1) - (VT)cs.alpha;
+    double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
-    for (int i = blockIdx.x * kWavesPerBlock + wid; i < n_split; i += n_waves) {
-        const SplitRow S = split[i];
-        if (lane >= COLS) continue;
+    for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
+        const Tile T = p.tiles[t];
+        const bool split = T.slot >= 0;
+        int row = T.row_begin;
+        int64_t rbeg = T.e_begin;
         VT acc = VT(0);
-        int any = 0;
-        for (int s = S.slot_begin; s < S.slot_end; ++s) {
-            acc += p.part[(size_t)s * COLS + col];
-            if (!PASS_B) any |= p.part_any[(size_t)s * COLS + col];
-        }
-        const int row = S.row;
-        const double deg = (double)(p.rp[row + 1] - p.rp[row]);
-        const size_t idx = (size_t)row * COLS + col;
-        if (!PASS_B) {
-            p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * acc;
-            if (any) r[RED_NP] += deg;
-        } else {
-            epilogue_b<VT>(p.OUT, p.ACC, idx, acc, p.inv_ws_row[row], rule, cs.convert, kss, kpi, ws_src, alpha,
-                           deg, r);
+        for (int64_t cb = T.e_begin; cb < T.e_end; cb += kWave) {
+            const int n = (int)min((int64_t)kWave, T.e_end - cb);
+            // chunk metadata: entries cb.., rows row..row+63
+            const int32_t lx = lane < n ? (ns ? ld_nt(&p.ci[cb + lane]) : p.ci[cb + lane]) : 0;
+            const VT lw = lane < n ? (VT)(ns ? ld_nt(&p.w[cb + lane]) : p.w[cb + lane]) : VT(0);
+            const int mbase = row;
+            const int mr = mbase + lane;
+            const int64_t m_end = split ? T.e_end : (mr < T.row_end ? p.rp[mr + 1] : T.e_end);
+            const VT m_iw = (SIDE_A && !split && mr < T.row_end) ? p.inv_ws_row[mr] : VT(0);
+            const VT liw = SIDE_A ? p.inv_ws_col[lx] : VT(0);
+            // row ends relative to the chunk start (> 64: not in this chunk)
+            const int m_rel = (int)min(m_end - cb, (int64_t)(1 << 30));
+            int rend = rl(m_rel, 0);
+            for (int j0 = 0; j0 < n; j0 += INF) {
+                VT v[INF];
+#pragma unroll
+                for (int jj = 0; jj < INF; ++jj) {
+                    const int j = j0 + jj;
+                    v[jj] = j < n ? p.X[(size_t)rl(lx, j) * COLS + col] : VT(0);
+                }
+#pragma unroll
+                for (int jj = 0; jj < INF; ++jj) {
+                    const int j = j0 + jj;
+                    if (j < n) {
+                        const VT wj = rl(lw, j);
+                        if (!SIDE_A) {
+                            acc += wj * v[jj];
+                        } else {
+                            const VT vw = v[jj] * rl(liw, j);
+                            acc += test(v[jj], vw) ? wj * vw : VT(0);
+                        }
+                        if (j + 1 == rend) {                 // last entry of the row: flush
+                            const size_t idx = (size_t)row * COLS + col;
+                            if (split) {
+                                p.part[(size_t)T.slot * COLS + col] = acc;
+                                if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc > VT(0) ? 1 : 0;
+                            } else if (SIDE_A) {
+                                const VT q = one_minus_alpha * rl(m_iw, row - mbase) * acc;
+                                if (ns) st_nt(&p.OUT[idx], q); else p.OUT[idx] = q;
+                                // a pushed entry adds a positive term: acc > 0 iff the row is active
+                                const int64_t rend_abs = cb + rend;
+                                if (acc > VT(0)) np += (double)(rend_abs - rbeg);
+                                rbeg = rend_abs;
+                            } else {
+                                if (ns) st_nt(&p.OUT[idx], acc); else p.OUT[idx] = acc;
+                            }
+                            acc = VT(0);
+                            ++row;
+                            rend = row - mbase < kWave ? rl(m_rel, row - mbase) : (1 << 30);
+                        }
+                    }
+                }
+            }
         }
     }
-    double* base = p.red + p.red_off;
+    if (SIDE_A) block_column_sum<COLS>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
+                                       p.red_slot + blockIdx.x);
+}
+
+// Fix-up of split rows, one block per row: thread (sl, col) adds the pieces
+// sl, sl + L, sl + 2L, ... (L = threads / COLS) in order, the block then adds
+// the L partial sums in a fixed tree, and writes the row like the gather.
+template <int COLS, typename VT, typename WT, bool SIDE_A>
+__global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, const SplitRow* split, int n_split) {
+    __shared__ double sh[kPassThreads];
+    __shared__ VT sv[kPassThreads];
+    __shared__ int32_t sa[kPassThreads];
+    if (*p.n_active == 0) return;
+    constexpr int L = kPassThreads / COLS;
+    const int tid = threadIdx.x;
+    const int col = tid & (COLS - 1);
+    const int sl = tid / COLS;
+    const VT one_minus_alpha = VT(1) - (VT)p.st[col].alpha;
+    double np = 0.0;
+    for (int i = blockIdx.x; i < n_split; i += gridDim.x) {
+        const SplitRow S = split[i];
+        VT a0 = VT(0), a1 = VT(0), a2 = VT(0), a3 = VT(0);
+        int any = 0;
+        int s = S.slot_begin + sl;
+        for (; s + 3 * L < S.slot_end; s += 4 * L) {   // four independent loads in flight
+            a0 += p.part[(size_t)s * COLS + col];
+            a1 += p.part[(size_t)(s + L) * COLS + col];
+            a2 += p.part[(size_t)(s + 2 * L) * COLS + col];
+            a3 += p.part[(size_t)(s + 3 * L) * COLS + col];
+            if (SIDE_A)
+                any |= p.part_any[(size_t)s * COLS + col] | p.part_any[(size_t)(s + L) * COLS + col] |
+                       p.part_any[(size_t)(s + 2 * L) * COLS + col] | p.part_any[(size_t)(s + 3 * L) * COLS + col];
+        }
+        for (; s < S.slot_end; s += L) {
+            a0 += p.part[(size_t)s * COLS + col];
+            if (SIDE_A) any |= p.part_any[(size_t)s * COLS + col];
+        }
+        sv[tid] = (a0 + a1) + (a2 + a3);
+        sa[tid] = any;
+        __syncthreads();
+        for (int h = L / 2; h > 0; h >>= 1) {
+            if (sl < h) {
+                sv[tid] += sv[tid + h * COLS];
+                sa[tid] |= sa[tid + h * COLS];
+            }
+            __syncthreads();
+        }
+        if (sl == 0) {
+            const int row = S.row;
+            const size_t idx = (size_t)row * COLS + col;
+            if (SIDE_A) {
+                p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * sv[tid];
+                if (sa[tid]) np += (double)(p.rp[row + 1] - p.rp[row]);
+            } else {
+                p.OUT[idx] = sv[tid];
+            }
+        }
+        __syncthreads();
+    }
+    if (SIDE_A) block_column_sum<COLS>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
+                                       p.red_slot + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Update of U rows: apply the push of x decided by ruleB, add the inflow G,
+// convert ACC when the control asks for it, and reduce per source.
+// ---------------------------------------------------------------------------
+template <int COLS, typename VT>
+__global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT* __restrict__ ACC,
+                                                        const VT* __restrict__ G, const VT* __restrict__ inv_ws,
+                                                        const int32_t* __restrict__ deg, int32_t n_rows,
+                                                        const ColState* st, const int32_t* n_active, double* red,
+                                                        int n_part, int red_slot) {
+    __shared__ double sh[kPassThreads];
+    if (*n_active == 0) return;
+    const int col = threadIdx.x & (COLS - 1);
+    const ColState& cs = st[col];
+    const PushTest<VT> test(cs.ruleB, (VT)cs.k_ss, (VT)cs.k_pi);
+    const int convert = cs.convert;
+    const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
+    double r[kNumRed] = {0, 0, 0, 0, 0};
+    const size_t n = (size_t)n_rows * COLS;
+    const size_t stride = (size_t)gridDim.x * kPassThreads;   // a multiple of COLS: the column stays fixed
+    constexpr int U = 4;
+    for (size_t i0 = (size_t)blockIdx.x * kPassThreads + threadIdx.x; i0 < n; i0 += U * stride) {
+        VT y[U], a[U], g[U], iw[U];
+        int32_t d[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const size_t i = i0 + k * stride;
+            const bool in = i < n;
+            const int32_t x = in ? (int32_t)(i / COLS) : 0;
+            d[k] = in ? deg[x] : 0;
+            iw[k] = in ? inv_ws[x] : VT(0);
+            y[k] = in ? Y[i] : VT(0);
+            a[k] = in ? ACC[i] : VT(0);
+            g[k] = in ? G[i] : VT(0);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            if (d[k] == 0) continue;                          // isolated or past the end: untouched
+            const size_t i = i0 + k * stride;
+            const VT yw = y[k] * iw[k];
+            const bool sel = test(y[k], yw);
+            const VT s = sel ? y[k] : VT(0);
+            VT acc = a[k];
+            if (convert) acc = acc * (VT(1) + ws_src * iw[k]);   // Eq. (fppr) + pi_b: ACC -> beta' part
+            acc += alpha * s;
+            const VT yn = (y[k] - s) + g[k];
+            Y[i] = yn;
+            ACC[i] = acc;
+            const VT tn = yn * iw[k];
+            r[RED_NP] += sel ? (double)d[k] : 0.0;
+            r[RED_CNT_SS] += (tn > kss) ? 1.0 : 0.0;
+            r[RED_SUM_R] += (double)tn;
+            r[RED_CNT_PI] += (yn > kpi) ? 1.0 : 0.0;
+            r[RED_SUM_Y] += (double)yn;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < kNumRed; ++k)
-        block_column_sum<COLS>(r[k], sh, base + (size_t)k * COLS * p.n_part, p.n_part);
+        block_column_sum<COLS>(r[k], sh, red + (size_t)k * COLS * n_part, n_part, red_slot + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,8 +484,8 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
             } else if (s.np >= s.two_e * (log(s.gamma / sum_y) / s.ln_inv)) {  // Eq. (fwd-np)
                 s.np_pi = s.np;
                 s.sum_rf = sum_y;
-                double tr = ceil(log(sum_y / s.eps_f) / s.ln_inv - 1.0);         // Eq. (t)
-                int t = tr > 0.0 ? (int)tr : 0;
+                const double tr = ceil(log(sum_y / s.eps_f) / s.ln_inv - 1.0);   // Eq. (t)
+                const int t = tr > 0.0 ? (int)tr : 0;
                 s.t = t;
                 if (t == 0) {
                     set_rules(s, MODE_FINAL, RULE_NONE, RULE_ALL, 1);
@@ -334,8 +509,11 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
     }
 }
 
+// Reduction slots [0, off_u) carry only n_p (gather A and its fix-up);
+// [off_u, n_part) carry all reductions (update).
 template <int COLS>
-__global__ __launch_bounds__(256) void k_control(ColState* st, const double* red, int n_part, int32_t* n_active) {
+__global__ __launch_bounds__(256) void k_control(ColState* st, const double* red, int n_part, int off_u,
+                                                 int32_t* n_active) {
     __shared__ double sh[256];
     __shared__ double R[kNumRed];
     if (*n_active == 0) return;
@@ -343,7 +521,7 @@ __global__ __launch_bounds__(256) void k_control(ColState* st, const double* red
     for (int k = 0; k < kNumRed; ++k) {
         const double* src = red + ((size_t)k * COLS + col) * n_part;
         double s = 0.0;
-        for (int i = threadIdx.x; i < n_part; i += 256) s += src[i];
+        for (int i = (k == RED_NP ? 0 : off_u) + threadIdx.x; i < n_part; i += 256) s += src[i];
         sh[threadIdx.x] = s;
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -414,6 +592,7 @@ const double* inv_ws_v_of<double>(const Graph* g) { return g->inv_ws_v_d; }
 struct Block {
     void* Y;
     void* ACC;
+    void* G;
     void* Q;
     void* partA;
     int32_t* partA_any;
@@ -424,10 +603,44 @@ struct Block {
     int32_t* h_active;
 };
 
+// Launch knobs of the 64-column gather, from BHPP_TUNE="inflight=16,nt=1"
+// (defaults below). They pick between equivalent schedules; results do not change.
+struct Tune {
+    int inflight = 8;
+    int nt = 0;
+};
+static const Tune& tune() {
+    static Tune t = [] {
+        Tune x;
+        if (const char* e = getenv("BHPP_TUNE")) {
+            int v;
+            const char* q;
+            if ((q = strstr(e, "inflight=")) && sscanf(q, "inflight=%d", &v) == 1) x.inflight = v;
+            if ((q = strstr(e, "nt=")) && sscanf(q, "nt=%d", &v) == 1) x.nt = v;
+        }
+        return x;
+    }();
+    return t;
+}
+
+template <typename VT, typename WT, bool SIDE_A>
+static void launch_gather64(int blocks, hipStream_t s, const GatherArgs<VT, WT>& a) {
+    switch (tune().inflight) {
+        case 8: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 8>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+        case 32: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 32>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 16>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+    }
+}
+
 static void prof_begin(Graph* g, hipStream_t s, int kind, double bytes, hipEvent_t* ev) {
+    ev[0] = ev[1] = nullptr;
     if (!g->prof_on) return;
     hipEvent_t a, b;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    if (hipEventCreate(&b) != hipSuccess) {
+        hipEventDestroy(a);
+        return;
+    }
     hipEventRecord(a, s);
     ev[0] = a;
     ev[1] = b;
@@ -435,78 +648,87 @@ static void prof_begin(Graph* g, hipStream_t s, int kind, double bytes, hipEvent
     g->prof_b.push_back(bytes);
 }
 static void prof_end(Graph* g, hipStream_t s, hipEvent_t* ev) {
-    if (!g->prof_on || ev[1] == nullptr) return;
+    if (ev[1] == nullptr) return;
     hipEventRecord(ev[1], s);
     g->prof_ev.push_back(ev[0]);
     g->prof_ev.push_back(ev[1]);
 }
 
 // Algorithmic bytes of one launch: adjacency once, each dense vector once.
+// kind 0: gather A (rows V), 1: gather B (rows U), 2: update (rows U).
 template <typename VT, typename WT>
-static double pass_bytes(const Graph* g, int cols, bool pass_b) {
+static double launch_bytes(const Graph* g, int cols, int kind) {
     const double nnz = (double)g->ne;
     const double nu = (double)(g->nu - g->info.isolated_u), nv = (double)(g->nv - g->info.isolated_v);
     const double adj = nnz * (4.0 + sizeof(WT));
-    if (!pass_b) {   // rows V: read rp_v, inv_ws_v, Y and inv_ws_u once, write Q
-        return adj + nv * 8.0 + nv * sizeof(VT) + nu * cols * sizeof(VT) + nu * sizeof(VT) + nv * cols * sizeof(VT);
-    }
-    // rows U: read rp_u, inv_ws_u, Q once; read and write Y and ACC
-    return adj + nu * 8.0 + nu * sizeof(VT) + nv * cols * sizeof(VT) + 4.0 * nu * cols * sizeof(VT);
+    const double vt = sizeof(VT);
+    if (kind == 0)   // rp_v, 1/ws_v; read Y and 1/ws_u once; write Q
+        return adj + nv * 8.0 + nv * vt + nu * cols * vt + nu * vt + nv * cols * vt;
+    if (kind == 1)   // rp_u; read Q once; write G
+        return adj + nu * 8.0 + nv * cols * vt + nu * cols * vt;
+    // update: rp_u, 1/ws_u; read Y, ACC, G; write Y, ACC
+    return nu * 8.0 + nu * vt + 5.0 * nu * cols * vt;
 }
 
 template <int COLS, typename VT, typename WT>
 static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipStream_t s) {
-    const WT* wu = reinterpret_cast<const WT*>(g->w_u);
-    const WT* wv = reinterpret_cast<const WT*>(g->w_v);
-    PassArgs<VT, WT> A;
+    GatherArgs<VT, WT> A;
     A.tiles = g->tiles_v.tiles;
     A.n_tiles = g->tiles_v.n_tiles;
     A.rp = g->rp_v;
     A.ci = g->ci_v;
-    A.w = wv;
+    A.w = reinterpret_cast<const WT*>(g->w_v);
     A.inv_ws_row = inv_ws_v_of<VT>(g);
     A.inv_ws_col = inv_ws_u_of<VT>(g);
     A.X = as<VT>(b.Y);
     A.OUT = as<VT>(b.Q);
-    A.ACC = nullptr;
     A.part = as<VT>(b.partA);
     A.part_any = b.partA_any;
     A.st = b.st;
     A.n_active = b.n_active;
     A.red = b.red;
     A.n_part = G.n_part;
-    PassArgs<VT, WT> B = A;
+    A.nt_stream = tune().nt;
+    GatherArgs<VT, WT> B = A;
     B.tiles = g->tiles_u.tiles;
     B.n_tiles = g->tiles_u.n_tiles;
     B.rp = g->rp_u;
     B.ci = g->ci_u;
-    B.w = wu;
+    B.w = reinterpret_cast<const WT*>(g->w_u);
     B.inv_ws_row = inv_ws_u_of<VT>(g);
     B.inv_ws_col = inv_ws_v_of<VT>(g);
     B.X = as<VT>(b.Q);
-    B.OUT = as<VT>(b.Y);
-    B.ACC = as<VT>(b.ACC);
+    B.OUT = as<VT>(b.G);
     B.part = as<VT>(b.partB);
     B.part_any = nullptr;
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipEvent_t ev[2];
 
-    prof_begin(g, s, 0, pass_bytes<VT, WT>(g, COLS, false), ev);
-    A.red_off = G.offA;
-    hipLaunchKernelGGL((k_pass<COLS, VT, WT, false>), dim3(G.blkA), dim3(kPassThreads), 0, s, A);
+    prof_begin(g, s, 0, launch_bytes<VT, WT>(g, COLS, 0), ev);
+    A.red_slot = G.offA;
+    if (COLS == 64)
+        launch_gather64<VT, WT, true>(G.blkA, s, A);
+    else
+        hipLaunchKernelGGL((k_gather<COLS, VT, WT, true>), dim3(G.blkA), dim3(kPassThreads), 0, s, A);
     prof_end(g, s, ev);
-    // the fix-ups always run: their blocks also write their reduction slots
-    A.red_off = G.offFA;
-    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFA), dim3(kPassThreads), 0, s, A,
+    // the fix-up always runs: its blocks also write their reduction slots
+    A.red_slot = G.offFA;
+    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kPassThreads), 0, s, A,
                        g->tiles_v.split, g->tiles_v.n_split);
-    ev[0] = ev[1] = nullptr;
-    prof_begin(g, s, 1, pass_bytes<VT, WT>(g, COLS, true), ev);
-    B.red_off = G.offB;
-    hipLaunchKernelGGL((k_pass<COLS, VT, WT, true>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
+    prof_begin(g, s, 1, launch_bytes<VT, WT>(g, COLS, 1), ev);
+    B.red_slot = 0;
+    if (COLS == 64)
+        launch_gather64<VT, WT, false>(G.blkB, s, B);
+    else
+        hipLaunchKernelGGL((k_gather<COLS, VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
     prof_end(g, s, ev);
-    B.red_off = G.offFB;
-    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
-                       g->tiles_u.split, g->tiles_u.n_split);
-    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(256), 0, s, b.st, b.red, G.n_part, b.n_active);
+    if (g->tiles_u.n_split > 0)
+        hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
+                           g->tiles_u.split, g->tiles_u.n_split);
+    prof_begin(g, s, 2, launch_bytes<VT, WT>(g, COLS, 2), ev);
+    hipLaunchKernelGGL((k_update<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.ACC),
+                       as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part, G.offU);
+    prof_end(g, s, ev);
+    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(256), 0, s, b.st, b.red, G.n_part, G.offU, b.n_active);
     BHPP_HIP(hipGetLastError());
     return BHPP_OK;
 }
@@ -583,10 +805,9 @@ static void done_state(ColState& c) {
 
 template <int COLS, typename VT, typename WT>
 static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const double* eps, double alpha,
-                            double lambda, void* scores_out, hipStream_t s, std::vector<ColState>& hs,
-                            std::vector<int>& steps) {
+                            double lambda, void* scores_out, hipStream_t s, std::vector<ColState>& hs) {
     Workspace& w = g->ws;
-    Block b{w.Y, w.ACC, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    Block b{w.Y, w.ACC, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
     hs.assign(COLS, ColState{});
     std::vector<int32_t> rows(COLS, 0);
     for (int c = 0; c < COLS; ++c) {
@@ -599,7 +820,7 @@ static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const d
         }
     }
     const size_t nU = (size_t)g->nu * COLS;
-    int32_t* d_rows = reinterpret_cast<int32_t*>(w.red);   // borrow: red is rewritten by every pass
+    int32_t* d_rows = reinterpret_cast<int32_t*>(w.red);   // borrow: red is rewritten by every sweep
     BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
     BHPP_HIP(hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * COLS, hipMemcpyHostToDevice, s));
     int32_t act = ncols;
@@ -609,8 +830,7 @@ static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const d
     hipLaunchKernelGGL(k_seed<VT>, dim3(1), dim3(64), 0, s, as<VT>(w.Y), d_rows, ncols, COLS);
     BHPP_HIP(hipGetLastError());
     BHPP_HIP(hipStreamSynchronize(s));   // d_rows is borrowed from red
-    int nsteps = 0;
-    bhpp_status rc = run_block<COLS, VT, WT>(g, b, s, &nsteps);
+    bhpp_status rc = run_block<COLS, VT, WT>(g, b, s, nullptr);
     if (rc) return rc;
     BHPP_HIP(hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost));
     if (scores_out) {
@@ -618,36 +838,39 @@ static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const d
                            g->perm_u, g->nu, ncols, as<VT>(scores_out));
         BHPP_HIP(hipGetLastError());
     }
-    steps.push_back(nsteps);
     return BHPP_OK;
 }
 
 template <typename VT, typename WT>
 static bhpp_status run_tile_dispatch(Graph* g, int ncols, const int32_t* src, const double* eps, double alpha,
-                                     double lambda, void* scores, hipStream_t s, std::vector<ColState>& hs,
-                                     std::vector<int>& steps) {
+                                     double lambda, void* scores, hipStream_t s, std::vector<ColState>& hs) {
     const int cols = next_pow2(ncols);
     switch (cols) {
-        case 1: return run_tile<1, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
-        case 2: return run_tile<2, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
-        case 4: return run_tile<4, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
-        case 8: return run_tile<8, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
-        case 16: return run_tile<16, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
-        case 32: return run_tile<32, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
-        case 64: return run_tile<64, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs, steps);
+        case 1: return run_tile<1, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 2: return run_tile<2, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 4: return run_tile<4, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 8: return run_tile<8, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 16: return run_tile<16, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 32: return run_tile<32, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 64: return run_tile<64, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
         default: return BHPP_INVALID_ARG;
     }
 }
 
+static void free_workspace(Workspace& w) {
+    void* ptrs[] = {w.Y, w.ACC, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores};
+    for (void* p : ptrs) hipFree(p);
+    if (w.h_active) hipHostFree(w.h_active);
+    w = Workspace{};
+}
+
+// Workspace of the query blocks. w.scores doubles as G during the sweeps and
+// as the row-major score scratch of the top-k afterwards.
 bhpp_status ensure_workspace(Graph* g, int cols) {
     Workspace& w = g->ws;
     const Geometry G = geometry(g);
     if (w.cols >= cols && w.n_part >= G.n_part) return BHPP_OK;
-    // free and reallocate at the larger size
-    hipFree(w.Y); hipFree(w.ACC); hipFree(w.Q); hipFree(w.partA); hipFree(w.partA_any); hipFree(w.partB);
-    hipFree(w.red); hipFree(w.st); hipFree(w.n_active); hipFree(w.scores);
-    if (w.h_active) hipHostFree(w.h_active);
-    w = Workspace{};
+    free_workspace(w);
     const size_t e = (size_t)g->elem;
     const size_t c = (size_t)cols;
     auto alloc = [&](void** p, size_t bytes) -> bool {
@@ -664,10 +887,7 @@ bhpp_status ensure_workspace(Graph* g, int cols) {
               alloc(&w.scores, (size_t)g->nu * c * e);
     if (ok) ok = hipHostMalloc((void**)&w.h_active, 64) == hipSuccess;
     if (!ok) {
-        hipFree(w.Y); hipFree(w.ACC); hipFree(w.Q); hipFree(w.partA); hipFree(w.partA_any); hipFree(w.partB);
-        hipFree(w.red); hipFree(w.st); hipFree(w.n_active); hipFree(w.scores);
-        if (w.h_active) hipHostFree(w.h_active);
-        w = Workspace{};
+        free_workspace(w);
         (void)hipGetLastError();
         return BHPP_OUT_OF_MEMORY;
     }
@@ -686,15 +906,12 @@ bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const doubl
         bhpp_status rc = ensure_workspace(g, next_pow2(nc));
         if (rc) return rc;
         std::vector<ColState> hs;
-        std::vector<int> steps;
         void* scores = scores_out ? (void*)((char*)scores_out + (size_t)base * g->nu * g->elem)
                                   : (k > 0 ? g->ws.scores : nullptr);
         if (g->dtype == BHPP_DTYPE_F64)
-            rc = run_tile_dispatch<double, double>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs,
-                                                   steps);
+            rc = run_tile_dispatch<double, double>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs);
         else
-            rc = run_tile_dispatch<float, float>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs,
-                                                 steps);
+            rc = run_tile_dispatch<float, float>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs);
         if (rc) return rc;
         if (k > 0) {
             std::vector<int32_t> ex(nc, -1);
@@ -737,9 +954,9 @@ template <typename WT>
 static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t s, double* out) {
     const Geometry G = geometry(g);
     Block b{};
-    size_t nU = (size_t)g->nu, nV = (size_t)g->nv;
+    const size_t nU = (size_t)g->nu, nV = (size_t)g->nv;
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
-    bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.Q, nV * 8) &&
+    bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.G, nU * 8) && A(&b.Q, nV * 8) &&
               A(&b.partA, (size_t)g->tiles_v.n_slots * 8) && A((void**)&b.partA_any, (size_t)g->tiles_v.n_slots * 4) &&
               A(&b.partB, (size_t)g->tiles_u.n_slots * 8) && A((void**)&b.red, (size_t)kNumRed * G.n_part * 8) &&
               A((void**)&b.st, sizeof(ColState)) && A((void**)&b.n_active, 64) &&
@@ -780,8 +997,8 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
         }
     }
     g->prof_on = saved_prof;
-    hipFree(b.Y); hipFree(b.ACC); hipFree(b.Q); hipFree(b.partA); hipFree(b.partA_any); hipFree(b.partB);
-    hipFree(b.red); hipFree(b.st); hipFree(b.n_active);
+    void* ptrs[] = {b.Y, b.ACC, b.G, b.Q, b.partA, b.partA_any, b.partB, b.red, b.st, b.n_active};
+    for (void* p : ptrs) hipFree(p);
     if (b.h_active) hipHostFree(b.h_active);
     return rc;
 }
