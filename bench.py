@@ -139,12 +139,13 @@ def main():
         log(f"single-source: {single_qps:.2f} q/s")
 
     # roofline of the dominant kernel
-    names = ["V-side gather (k_gather64, SIDE_A)", "U-side gather (k_gather64)", "U-side update (k_update)"]
+    names = ["V-side gather (k_gather64, SIDE_A)", "U-side gather (k_gather64)", "U-side update (k_update)",
+             "push selection (k_select)"]
     dom = int(np.argmax(prof["ms"]))
     avg_ms = prof["ms"][dom] / max(1, prof["launches"][dom])
     bytes_per_launch = prof["bytes"][dom] / max(1, prof["launches"][dom])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kernel_id = ["gather_a", "gather_b", "update"][dom]
+    kernel_id = ["gather_a", "gather_b", "update", "select"][dom]
     roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=stored_traffic(kernel_id),
                     avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom],
@@ -152,7 +153,7 @@ def main():
                     share_of_step=round(sum(prof["ms"]) / (dt * 1e3), 3),
                     kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
                                      gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
-                             for i, k in enumerate(["gather_a", "gather_b", "update"])})
+                             for i, k in enumerate(["gather_a", "gather_b", "update", "select"])})
 
     cpu = None
     if not args.no_cpu_baseline:

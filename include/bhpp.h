@@ -190,8 +190,9 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
 
 /*
  * Device-time profile of the sweep kernels. While enabled, every launch of the
- * V-side gather (kind 0), the U-side gather (kind 1) and the U-side update
- * (kind 2) on a query stream is bracketed by HIP events on that stream and the
+ * V-side gather (kind 0), the U-side gather (kind 1), the U-side update
+ * (kind 2) and the push selection (kind 3) on a query stream is bracketed by
+ * HIP events on that stream and the
  * elapsed times are accumulated; bhpp_profile_read synchronises and returns,
  * per kind, the total milliseconds, the number of launches and the
  * algorithmic bytes those launches moved in total (per launch: the adjacency
@@ -200,7 +201,7 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
  * DEVICE_ERROR.
  */
 bhpp_status bhpp_profile_enable(bhpp_graph* g, int32_t enable);
-bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[3], int64_t launches[3], double bytes[3]);
+bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[4], int64_t launches[4], double bytes[4]);
 
 /* Free the handle and all device memory it owns (NULL is ignored). The caller
    must make sure no work using it is still running. */

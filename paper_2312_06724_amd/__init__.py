@@ -227,9 +227,9 @@ class Graph:
         _check(load_library().bhpp_profile_enable(self._h, 1 if enable else 0), "bhpp_profile_enable")
 
     def profile_read(self):
-        ms = (ctypes.c_double * 3)()
-        n = (ctypes.c_int64 * 3)()
-        b = (ctypes.c_double * 3)()
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        b = (ctypes.c_double * 4)()
         _check(load_library().bhpp_profile_read(self._h, ms, n, b), "bhpp_profile_read")
         return dict(ms=list(ms), launches=list(n), bytes=list(b))
 

@@ -177,7 +177,7 @@ bhpp_status bhpp_profile_enable(bhpp_graph* h, int32_t enable) {
         g->prof_ev.clear();
         g->prof_kind.clear();
         g->prof_b.clear();
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < 4; ++k) {
             g->prof_ms[k] = 0.0;
             g->prof_n[k] = 0;
             g->prof_bytes[k] = 0.0;
@@ -187,7 +187,7 @@ bhpp_status bhpp_profile_enable(bhpp_graph* h, int32_t enable) {
     return BHPP_OK;
 }
 
-bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[3], int64_t launches[3], double bytes[3]) {
+bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[4], int64_t launches[4], double bytes[4]) {
     if (!h || !h->g || !ms || !launches || !bytes) return BHPP_INVALID_ARG;
     Graph* g = h->g;
     std::lock_guard<std::mutex> lock(g->mu);
@@ -208,7 +208,7 @@ bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[3], int64_t launches[3], 
     g->prof_ev.clear();
     g->prof_kind.clear();
     g->prof_b.clear();
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ms[k] = g->prof_ms[k];
         launches[k] = g->prof_n[k];
         bytes[k] = g->prof_bytes[k];

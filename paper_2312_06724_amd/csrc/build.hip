@@ -111,6 +111,13 @@ __global__ void k_gather_f64(int64_t n, const int32_t* order, const double* in, 
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = in[order[i]];
 }
+// U rows store w(x,v)/ws(v): the U-side gather then needs no per-row scaling
+template <typename WT>
+__global__ void k_scale_by_col(int64_t n, const double* w, const int32_t* col, const int32_t* iperm_col,
+                               const double* ws_col_ext, WT* out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (WT)(w[i] / ws_col_ext[iperm_col[col[i]]]);
+}
 template <typename WT>
 __global__ void k_cast(int64_t n, const double* in, WT* out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -134,6 +141,13 @@ __global__ void k_perm_from_keys(int32_t n, const uint64_t* keys, int32_t* iperm
     const int32_t x = (int32_t)(keys[i] & 0xFFFFFFFFull);
     iperm[i] = x;
     perm[x] = i;
+}
+// bit e of bits is set iff adjacency entry e is the last entry of its row
+__global__ void k_end_bits(int32_t n, const int64_t* rp, unsigned long long* bits) {
+    int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n || rp[x + 1] == rp[x]) return;
+    const int64_t e = rp[x + 1] - 1;
+    atomicOr(&bits[e >> 6], 1ull << (e & 63));
 }
 __global__ void k_degrees(int32_t n, const int64_t* rp, int32_t* deg) {
     int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -223,7 +237,7 @@ void free_tiles(TileSet* ts) {
 
 void free_graph(Graph* g) {
     if (!g) return;
-    void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u,
+    void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u, g->end_bits_u, g->end_bits_v,
                     g->inv_ws_u_d, g->inv_ws_v_d, g->perm_u, g->iperm_u, g->x_rp_u, g->x_ci_u, g->x_w_u,
                     g->x_rp_v, g->x_ci_v, g->x_w_v, g->x_ws_u, g->x_ws_v};
     for (void* p : ptrs) hipFree(p);
@@ -419,8 +433,18 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
     rc = csr_from(tmp, m, iv, iu, w_of, nv, nu, nullptr, g->rp_v, g->ci_v, w_int_v, s);
     if (rc) return rc;
     if (m > 0) {
-        hipLaunchKernelGGL(k_cast<WT>, grid_for(m), dim3(256), 0, s, m, w_int_u, (WT*)g->w_u);
+        hipLaunchKernelGGL(k_scale_by_col<WT>, grid_for(m), dim3(256), 0, s, m, w_int_u, g->ci_u, iperm_v, ws_v,
+                           (WT*)g->w_u);
         hipLaunchKernelGGL(k_cast<WT>, grid_for(m), dim3(256), 0, s, m, w_int_v, (WT*)g->w_v);
+    }
+    {   // row-end bitmaps (one spare word so a reader may load word i+1)
+        const size_t words = (size_t)(m >> 6) + 2;
+        BHPP_HIP(hipMalloc((void**)&g->end_bits_u, 8 * words));
+        BHPP_HIP(hipMalloc((void**)&g->end_bits_v, 8 * words));
+        BHPP_HIP(hipMemsetAsync(g->end_bits_u, 0, 8 * words, s));
+        BHPP_HIP(hipMemsetAsync(g->end_bits_v, 0, 8 * words, s));
+        hipLaunchKernelGGL(k_end_bits, grid_for(nu), dim3(256), 0, s, nu, g->rp_u, (unsigned long long*)g->end_bits_u);
+        hipLaunchKernelGGL(k_end_bits, grid_for(nv), dim3(256), 0, s, nv, g->rp_v, (unsigned long long*)g->end_bits_v);
     }
     BHPP_HIP(hipMalloc((void**)&g->deg_u, sizeof(int32_t) * nu));
     hipLaunchKernelGGL(k_degrees, grid_for(nu), dim3(256), 0, s, nu, g->rp_u, g->deg_u);

@@ -92,6 +92,7 @@ struct Workspace {
     int elem = 0;                // bytes per value
     void* Y = nullptr;           // [n_u][cols] forward residue y = (ws/ws(u)) r
     void* ACC = nullptr;         // [n_u][cols] push estimate, later beta'
+    void* S = nullptr;           // [n_u][cols] y/ws of the nodes pushed in the current sweep
     void* Q = nullptr;           // [n_v][cols] V-side residue of the current sweep
     void* partA = nullptr;       // [slots_v][cols] split-row partial sums
     int32_t* partA_any = nullptr;
@@ -111,11 +112,13 @@ struct Graph {
     int32_t dtype = BHPP_DTYPE_F32;
     int elem = 4;
     // internal (degree-ordered) adjacency
-    int64_t* rp_u = nullptr; int32_t* ci_u = nullptr; void* w_u = nullptr;
-    int64_t* rp_v = nullptr; int32_t* ci_v = nullptr; void* w_v = nullptr;
+    int64_t* rp_u = nullptr; int32_t* ci_u = nullptr; void* w_u = nullptr;   // w_u holds w(x,v)/ws(v)
+    int64_t* rp_v = nullptr; int32_t* ci_v = nullptr; void* w_v = nullptr;   // w_v holds w(x,v)
     float* inv_ws_u_f = nullptr; float* inv_ws_v_f = nullptr;     // F32 graphs
     double* inv_ws_u_d = nullptr; double* inv_ws_v_d = nullptr;   // both dtypes
     int32_t* deg_u = nullptr;    // degree of each internal U row
+    uint64_t* end_bits_u = nullptr;  // bit e set iff entry e of the U rows ends its row
+    uint64_t* end_bits_v = nullptr;
     int32_t* perm_u = nullptr;   // external U id -> internal
     int32_t* iperm_u = nullptr;  // internal -> external
     TileSet tiles_u, tiles_v;
@@ -135,9 +138,9 @@ struct Graph {
     bool sticky_error = false;
     // profiling of the sweep kernels
     bool prof_on = false;
-    double prof_ms[3] = {0, 0, 0};
-    int64_t prof_n[3] = {0, 0, 0};
-    double prof_bytes[3] = {0, 0, 0};
+    double prof_ms[4] = {0, 0, 0, 0};
+    int64_t prof_n[4] = {0, 0, 0, 0};
+    double prof_bytes[4] = {0, 0, 0, 0};
     std::vector<hipEvent_t> prof_ev;      // pairs, recorded on the query stream
     std::vector<int32_t> prof_kind;
     std::vector<double> prof_b;

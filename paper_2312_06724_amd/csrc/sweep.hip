@@ -123,14 +123,12 @@ struct GatherArgs {
     int n_tiles;
     const int64_t* rp;
     const int32_t* ci;
-    const WT* w;
-    const VT* inv_ws_row;   // 1/ws of the row side (gather A: V)
-    const VT* inv_ws_col;   // 1/ws of the neighbour side (gather A: U)
-    const VT* X;            // gathered vector: gather A Y (over U), gather B Q (over V)
+    const WT* w;            // gather A: w(x,v); gather B: w(x,v)/ws(v)
+    const VT* X;            // gathered vector: gather A S (over U), gather B Q (over V)
     VT* OUT;                // gather A: Q, gather B: G
     VT* part;               // split-row partial sums [slots][COLS]
     int32_t* part_any;      // gather A: whether any neighbour was pushed
-    const ColState* st;
+    const uint64_t* end_bits;  // bit e set iff entry e is the last of its row
     const int32_t* n_active;
     double* red;            // [kNumRed][COLS][n_part]
     int n_part;
@@ -138,8 +136,15 @@ struct GatherArgs {
     int nt_stream;          // stream adjacency and row outputs past the caches
 };
 
+// Gather A (rows v of W^T) forms Q(v) = sum_x w(x,v) S(x) with S(x) = y(x)/ws(x)
+// for the pushed x and 0 otherwise; gather B (rows x of W) forms
+// G(x) = sum_v w(x,v)/ws(v) Q(v); the update then adds (1-alpha) G(x). Both are
+// the same weighted gather; gather A also counts the push cost of the V side:
+// d(v) for every v with a pushed neighbour, i.e. Q(v) > 0 (each pushed
+// neighbour adds a positive term).
+
 // ---------------------------------------------------------------------------
-// Gathers for 1..32 sources: a wavefront takes a tile; lanes are (row group,
+// Gathers for 2..32 sources: a wavefront takes a tile; lanes are (row group,
 // edge slot, column); rows of a tile have similar degree (degree order), so
 // the edge slots per row follow the tile's largest degree.
 // ---------------------------------------------------------------------------
@@ -150,10 +155,6 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int col = lane & (COLS - 1);
-    const ColState& cs = p.st[col];
-    const int rule = cs.ruleA;
-    const PushTest<VT> test(rule, (VT)cs.k_ss, (VT)cs.k_pi);
-    const VT one_minus_alpha = VT(1) - (VT)cs.alpha;
     double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
@@ -175,40 +176,19 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
                 e1 = p.rp[row + 1];
             }
             VT acc = VT(0);
-            int any = 0;
-            if (!SIDE_A || rule != RULE_NONE) {
 #pragma unroll 4
-                for (int64_t e = e0 + slot; e < e1; e += epar) {
-                    const int32_t x = p.ci[e];
-                    const VT ww = (VT)p.w[e];
-                    const VT v = p.X[(size_t)x * COLS + col];
-                    if (!SIDE_A) {
-                        acc += ww * v;
-                    } else {
-                        const VT vw = v * p.inv_ws_col[x];
-                        acc += test(v, vw) ? ww * vw : VT(0);
-                    }
-                }
-            }
-            // a pushed entry adds a positive term, so acc > 0 iff some neighbour was pushed
-            if (SIDE_A) any = acc > VT(0) ? 1 : 0;
+            for (int64_t e = e0 + slot; e < e1; e += epar)
+                acc += (VT)p.w[e] * p.X[(size_t)p.ci[e] * COLS + col];
 #pragma unroll
-            for (int m = COLS; m < kWave; m <<= 1) {
-                if (m < gl) {
-                    acc += __shfl_xor(acc, m);
-                    if (SIDE_A) any |= __shfl_xor(any, m);
-                }
-            }
+            for (int m = COLS; m < kWave; m <<= 1)
+                if (m < gl) acc += __shfl_xor(acc, m);
             if (slot == 0 && valid) {
-                const size_t idx = (size_t)row * COLS + col;
                 if (T.slot >= 0) {
                     p.part[(size_t)T.slot * COLS + col] = acc;
-                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = any;
-                } else if (SIDE_A) {
-                    p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * acc;
-                    if (any) np += (double)(e1 - e0);
+                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc > VT(0) ? 1 : 0;
                 } else {
-                    p.OUT[idx] = acc;
+                    p.OUT[(size_t)row * COLS + col] = acc;
+                    if (SIDE_A && acc > VT(0)) np += (double)(e1 - e0);
                 }
             }
         }
@@ -220,10 +200,10 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
 // ---------------------------------------------------------------------------
 // Gather for 64 sources: one lane per source, one row at a time. Per chunk of
 // 64 adjacency entries the wavefront loads, one entry or row per lane, the
-// neighbour ids, weights, the end offsets of the next 64 rows and their 1/ws;
-// it then keeps INF row gathers in flight, taking each entry's neighbour id
-// from its lane with readlane. A row whose last entry is reached is flushed
-// with stores only. Tiles hold no empty rows.
+// neighbour ids, weights and the end offsets of the next 64 rows; it then
+// keeps INF row gathers in flight, taking each entry's neighbour id from its
+// lane with readlane. A row whose last entry is reached is flushed with a
+// store. Tiles hold no empty rows.
 // ---------------------------------------------------------------------------
 template <typename VT, typename WT, bool SIDE_A, int INF>
 __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p) {
@@ -234,9 +214,6 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int col = lane;
-    const ColState& cs = p.st[col];
-    const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
-    const VT one_minus_alpha = VT(1) - (VT)cs.alpha;
     double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
@@ -247,14 +224,11 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
         VT acc = VT(0);
         for (int64_t cb = T.e_begin; cb < T.e_end; cb += kWave) {
             const int n = (int)min((int64_t)kWave, T.e_end - cb);
-            // chunk metadata: entries cb.., rows row..row+63
             const int32_t lx = lane < n ? (ns ? ld_nt(&p.ci[cb + lane]) : p.ci[cb + lane]) : 0;
             const VT lw = lane < n ? (VT)(ns ? ld_nt(&p.w[cb + lane]) : p.w[cb + lane]) : VT(0);
             const int mbase = row;
             const int mr = mbase + lane;
             const int64_t m_end = split ? T.e_end : (mr < T.row_end ? p.rp[mr + 1] : T.e_end);
-            const VT m_iw = (SIDE_A && !split && mr < T.row_end) ? p.inv_ws_row[mr] : VT(0);
-            const VT liw = SIDE_A ? p.inv_ws_col[lx] : VT(0);
             // row ends relative to the chunk start (> 64: not in this chunk)
             const int m_rel = (int)min(m_end - cb, (int64_t)(1 << 30));
             int rend = rl(m_rel, 0);
@@ -269,27 +243,17 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
                 for (int jj = 0; jj < INF; ++jj) {
                     const int j = j0 + jj;
                     if (j < n) {
-                        const VT wj = rl(lw, j);
-                        if (!SIDE_A) {
-                            acc += wj * v[jj];
-                        } else {
-                            const VT vw = v[jj] * rl(liw, j);
-                            acc += test(v[jj], vw) ? wj * vw : VT(0);
-                        }
+                        acc += rl(lw, j) * v[jj];
                         if (j + 1 == rend) {                 // last entry of the row: flush
-                            const size_t idx = (size_t)row * COLS + col;
                             if (split) {
                                 p.part[(size_t)T.slot * COLS + col] = acc;
                                 if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc > VT(0) ? 1 : 0;
-                            } else if (SIDE_A) {
-                                const VT q = one_minus_alpha * rl(m_iw, row - mbase) * acc;
-                                if (ns) st_nt(&p.OUT[idx], q); else p.OUT[idx] = q;
-                                // a pushed entry adds a positive term: acc > 0 iff the row is active
-                                const int64_t rend_abs = cb + rend;
-                                if (acc > VT(0)) np += (double)(rend_abs - rbeg);
-                                rbeg = rend_abs;
                             } else {
+                                const size_t idx = (size_t)row * COLS + col;
                                 if (ns) st_nt(&p.OUT[idx], acc); else p.OUT[idx] = acc;
+                                const int64_t rend_abs = cb + rend;
+                                if (SIDE_A && acc > VT(0)) np += (double)(rend_abs - rbeg);
+                                rbeg = rend_abs;
                             }
                             acc = VT(0);
                             ++row;
@@ -302,6 +266,105 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     }
     if (SIDE_A) block_column_sum<COLS>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
                                        p.red_slot + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Gather for one source: lanes are adjacency entries. A wavefront walks its
+// tile in groups of UNR chunks of 64 entries (coalesced index and weight
+// loads, one gather per lane, all UNR chunks in flight); the row-end bitmap
+// gives the lanes that end a row, and a segmented inclusive scan across the
+// lanes (fixed order) sums each row. The row still open at the end of a chunk
+// carries its partial sum into the next one. Tiles hold no empty rows.
+// ---------------------------------------------------------------------------
+template <typename VT, typename WT, bool SIDE_A>
+__global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) {
+    constexpr int UNR = 4;
+    __shared__ double sh[kPassThreads];
+    if (*p.n_active == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const uint64_t lt_mask = lane ? (~0ull >> (kWave - lane)) : 0ull;   // lanes below this one
+    double np = 0.0;
+    const int n_waves = gridDim.x * kWavesPerBlock;
+    for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
+        const Tile T = p.tiles[t];
+        const bool split = T.slot >= 0;
+        int row = T.row_begin;
+        int64_t open_begin = T.e_begin;   // first entry of the row still open
+        VT carry = VT(0);                 // its partial sum (uniform)
+        VT part = VT(0);                  // split pieces: per-lane partial sums
+        for (int64_t cb0 = T.e_begin; cb0 < T.e_end; cb0 += (int64_t)kWave * UNR) {
+            int n[UNR];
+            int32_t x[UNR];
+            VT ww[UNR], v[UNR];
+            uint64_t mask[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                const int64_t cb = cb0 + (int64_t)u * kWave;
+                n[u] = (int)max((int64_t)0, min((int64_t)kWave, T.e_end - cb));
+                const bool valid = lane < n[u];
+                x[u] = valid ? p.ci[cb + lane] : 0;
+                ww[u] = valid ? (VT)p.w[cb + lane] : VT(0);
+                mask[u] = 0;
+                if (!split && n[u] > 0) {
+                    const int64_t wi = cb >> 6;
+                    const int bs = (int)(cb & 63);
+                    const uint64_t w0 = p.end_bits[wi];
+                    const uint64_t w1 = bs ? p.end_bits[wi + 1] : 0ull;
+                    uint64_t m = bs ? ((w0 >> bs) | (w1 << (64 - bs))) : w0;
+                    if (n[u] < kWave) m &= (1ull << n[u]) - 1ull;
+                    mask[u] = m;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) v[u] = lane < n[u] ? p.X[x[u]] : VT(0);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                if (n[u] == 0) break;
+                const VT term = ww[u] * v[u];
+                if (split) {
+                    part += term;
+                    continue;
+                }
+                const int64_t cb = cb0 + (int64_t)u * kWave;
+                const uint64_t before = mask[u] & lt_mask;
+                const int seg = __popcll(before);                           // rows ended before this lane
+                const int start = before ? kWave - __clzll(before) : 0;      // first lane of this lane's row
+                VT sum = term;
+#pragma unroll
+                for (int d = 1; d < kWave; d <<= 1) {
+                    const VT up = __shfl_up(sum, d);
+                    if (lane - d >= start) sum += up;
+                }
+                if (seg == 0) sum += carry;
+                if ((mask[u] >> lane) & 1ull) {
+                    p.OUT[(size_t)(row + seg)] = sum;
+                    if (SIDE_A && sum > VT(0)) {
+                        const int64_t beg = seg == 0 ? open_begin : cb + start;
+                        np += (double)(cb + lane + 1 - beg);
+                    }
+                }
+                const VT last = rl(sum, n[u] - 1);
+                if (mask[u]) {
+                    const int h = kWave - 1 - __clzll(mask[u]);              // last row end in the chunk
+                    open_begin = cb + h + 1;
+                    carry = h == n[u] - 1 ? VT(0) : last;
+                } else {
+                    carry = last;
+                }
+                row += __popcll(mask[u]);
+            }
+        }
+        if (split) {
+#pragma unroll
+            for (int m = 1; m < kWave; m <<= 1) part += __shfl_xor(part, m);
+            if (lane == 0) {
+                p.part[T.slot] = part;
+                if (SIDE_A) p.part_any[T.slot] = part > VT(0) ? 1 : 0;
+            }
+        }
+    }
+    if (SIDE_A) block_column_sum<1>(np, sh, p.red + (size_t)RED_NP * p.n_part, p.n_part, p.red_slot + blockIdx.x);
 }
 
 // Fix-up of split rows, one block per row: thread (sl, col) adds the pieces
@@ -317,7 +380,6 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
     const int tid = threadIdx.x;
     const int col = tid & (COLS - 1);
     const int sl = tid / COLS;
-    const VT one_minus_alpha = VT(1) - (VT)p.st[col].alpha;
     double np = 0.0;
     for (int i = blockIdx.x; i < n_split; i += gridDim.x) {
         const SplitRow S = split[i];
@@ -349,13 +411,8 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
         }
         if (sl == 0) {
             const int row = S.row;
-            const size_t idx = (size_t)row * COLS + col;
-            if (SIDE_A) {
-                p.OUT[idx] = one_minus_alpha * p.inv_ws_row[row] * sv[tid];
-                if (sa[tid]) np += (double)(p.rp[row + 1] - p.rp[row]);
-            } else {
-                p.OUT[idx] = sv[tid];
-            }
+            p.OUT[(size_t)row * COLS + col] = sv[tid];
+            if (SIDE_A && sa[tid]) np += (double)(p.rp[row + 1] - p.rp[row]);
         }
         __syncthreads();
     }
@@ -364,7 +421,39 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
 }
 
 // ---------------------------------------------------------------------------
-// Update of U rows: apply the push of x decided by ruleB, add the inflow G,
+// Select: S(x) = y(x)/ws(x) for every x the source pushes in this sweep
+// (its rule for the V-side half), else 0.
+// ---------------------------------------------------------------------------
+template <int COLS, typename VT>
+__global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ Y, VT* __restrict__ S,
+                                                        const VT* __restrict__ inv_ws, int32_t n_rows,
+                                                        const ColState* st, const int32_t* n_active) {
+    if (*n_active == 0) return;
+    const int col = threadIdx.x & (COLS - 1);
+    const ColState& cs = st[col];
+    const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
+    const size_t n = (size_t)n_rows * COLS;
+    const size_t stride = (size_t)gridDim.x * kPassThreads;
+    constexpr int U = 4;
+    for (size_t i0 = (size_t)blockIdx.x * kPassThreads + threadIdx.x; i0 < n; i0 += U * stride) {
+        VT y[U], iw[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const size_t i = i0 + k * stride;
+            y[k] = i < n ? Y[i] : VT(0);
+            iw[k] = i < n ? inv_ws[i / COLS] : VT(0);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const size_t i = i0 + k * stride;
+            const VT yw = y[k] * iw[k];
+            if (i < n) S[i] = test(y[k], yw) ? yw : VT(0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Update of U rows: apply the push of x decided by ruleB, add (1-alpha) G,
 // convert ACC when the control asks for it, and reduce per source.
 // ---------------------------------------------------------------------------
 template <int COLS, typename VT>
@@ -380,6 +469,7 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
     const PushTest<VT> test(cs.ruleB, (VT)cs.k_ss, (VT)cs.k_pi);
     const int convert = cs.convert;
     const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
+    const VT one_minus_alpha = VT(1) - alpha;
     double r[kNumRed] = {0, 0, 0, 0, 0};
     const size_t n = (size_t)n_rows * COLS;
     const size_t stride = (size_t)gridDim.x * kPassThreads;   // a multiple of COLS: the column stays fixed
@@ -408,7 +498,7 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
             VT acc = a[k];
             if (convert) acc = acc * (VT(1) + ws_src * iw[k]);   // Eq. (fppr) + pi_b: ACC -> beta' part
             acc += alpha * s;
-            const VT yn = (y[k] - s) + g[k];
+            const VT yn = (y[k] - s) + one_minus_alpha * g[k];
             Y[i] = yn;
             ACC[i] = acc;
             const VT tn = yn * iw[k];
@@ -592,6 +682,7 @@ const double* inv_ws_v_of<double>(const Graph* g) { return g->inv_ws_v_d; }
 struct Block {
     void* Y;
     void* ACC;
+    void* S;
     void* G;
     void* Q;
     void* partA;
@@ -655,19 +746,21 @@ static void prof_end(Graph* g, hipStream_t s, hipEvent_t* ev) {
 }
 
 // Algorithmic bytes of one launch: adjacency once, each dense vector once.
-// kind 0: gather A (rows V), 1: gather B (rows U), 2: update (rows U).
+// kind 0: gather A (rows V), 1: gather B (rows U), 2: update (rows U),
+// 3: select (rows U).
 template <typename VT, typename WT>
 static double launch_bytes(const Graph* g, int cols, int kind) {
     const double nnz = (double)g->ne;
     const double nu = (double)(g->nu - g->info.isolated_u), nv = (double)(g->nv - g->info.isolated_v);
     const double adj = nnz * (4.0 + sizeof(WT));
     const double vt = sizeof(VT);
-    if (kind == 0)   // rp_v, 1/ws_v; read Y and 1/ws_u once; write Q
-        return adj + nv * 8.0 + nv * vt + nu * cols * vt + nu * vt + nv * cols * vt;
+    if (kind == 0)   // rp_v; read S once; write Q
+        return adj + nv * 8.0 + nu * cols * vt + nv * cols * vt;
     if (kind == 1)   // rp_u; read Q once; write G
         return adj + nu * 8.0 + nv * cols * vt + nu * cols * vt;
-    // update: rp_u, 1/ws_u; read Y, ACC, G; write Y, ACC
-    return nu * 8.0 + nu * vt + 5.0 * nu * cols * vt;
+    if (kind == 2)   // degrees, 1/ws_u; read Y, ACC, G; write Y, ACC
+        return nu * 4.0 + nu * vt + 5.0 * nu * cols * vt;
+    return (double)g->nu * (vt + 2.0 * cols * vt);   // select: 1/ws_u, read Y, write S
 }
 
 template <int COLS, typename VT, typename WT>
@@ -678,13 +771,11 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     A.rp = g->rp_v;
     A.ci = g->ci_v;
     A.w = reinterpret_cast<const WT*>(g->w_v);
-    A.inv_ws_row = inv_ws_v_of<VT>(g);
-    A.inv_ws_col = inv_ws_u_of<VT>(g);
-    A.X = as<VT>(b.Y);
+    A.X = as<VT>(b.S);
     A.OUT = as<VT>(b.Q);
     A.part = as<VT>(b.partA);
     A.part_any = b.partA_any;
-    A.st = b.st;
+    A.end_bits = g->end_bits_v;
     A.n_active = b.n_active;
     A.red = b.red;
     A.n_part = G.n_part;
@@ -695,18 +786,23 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     B.rp = g->rp_u;
     B.ci = g->ci_u;
     B.w = reinterpret_cast<const WT*>(g->w_u);
-    B.inv_ws_row = inv_ws_u_of<VT>(g);
-    B.inv_ws_col = inv_ws_v_of<VT>(g);
     B.X = as<VT>(b.Q);
     B.OUT = as<VT>(b.G);
     B.part = as<VT>(b.partB);
     B.part_any = nullptr;
+    B.end_bits = g->end_bits_u;
     hipEvent_t ev[2];
 
+    prof_begin(g, s, 3, launch_bytes<VT, WT>(g, COLS, 3), ev);
+    hipLaunchKernelGGL((k_select<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.S),
+                       inv_ws_u_of<VT>(g), g->nu, b.st, b.n_active);
+    prof_end(g, s, ev);
     prof_begin(g, s, 0, launch_bytes<VT, WT>(g, COLS, 0), ev);
     A.red_slot = G.offA;
     if (COLS == 64)
         launch_gather64<VT, WT, true>(G.blkA, s, A);
+    else if (COLS == 1)
+        hipLaunchKernelGGL((k_gather1<VT, WT, true>), dim3(G.blkA), dim3(kPassThreads), 0, s, A);
     else
         hipLaunchKernelGGL((k_gather<COLS, VT, WT, true>), dim3(G.blkA), dim3(kPassThreads), 0, s, A);
     prof_end(g, s, ev);
@@ -718,6 +814,8 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     B.red_slot = 0;
     if (COLS == 64)
         launch_gather64<VT, WT, false>(G.blkB, s, B);
+    else if (COLS == 1)
+        hipLaunchKernelGGL((k_gather1<VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
     else
         hipLaunchKernelGGL((k_gather<COLS, VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
     prof_end(g, s, ev);
@@ -807,7 +905,7 @@ template <int COLS, typename VT, typename WT>
 static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const double* eps, double alpha,
                             double lambda, void* scores_out, hipStream_t s, std::vector<ColState>& hs) {
     Workspace& w = g->ws;
-    Block b{w.Y, w.ACC, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
     hs.assign(COLS, ColState{});
     std::vector<int32_t> rows(COLS, 0);
     for (int c = 0; c < COLS; ++c) {
@@ -858,7 +956,7 @@ static bhpp_status run_tile_dispatch(Graph* g, int ncols, const int32_t* src, co
 }
 
 static void free_workspace(Workspace& w) {
-    void* ptrs[] = {w.Y, w.ACC, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores};
+    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores};
     for (void* p : ptrs) hipFree(p);
     if (w.h_active) hipHostFree(w.h_active);
     w = Workspace{};
@@ -879,6 +977,7 @@ bhpp_status ensure_workspace(Graph* g, int cols) {
         return hipMalloc(p, bytes) == hipSuccess;
     };
     bool ok = alloc(&w.Y, (size_t)g->nu * c * e) && alloc(&w.ACC, (size_t)g->nu * c * e) &&
+              alloc(&w.S, (size_t)g->nu * c * e) &&
               alloc(&w.Q, (size_t)g->nv * c * e) && alloc(&w.partA, (size_t)g->tiles_v.n_slots * c * e) &&
               alloc((void**)&w.partA_any, (size_t)g->tiles_v.n_slots * c * 4) &&
               alloc(&w.partB, (size_t)g->tiles_u.n_slots * c * e) &&
@@ -956,7 +1055,7 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
     Block b{};
     const size_t nU = (size_t)g->nu, nV = (size_t)g->nv;
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
-    bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.G, nU * 8) && A(&b.Q, nV * 8) &&
+    bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.S, nU * 8) && A(&b.G, nU * 8) && A(&b.Q, nV * 8) &&
               A(&b.partA, (size_t)g->tiles_v.n_slots * 8) && A((void**)&b.partA_any, (size_t)g->tiles_v.n_slots * 4) &&
               A(&b.partB, (size_t)g->tiles_u.n_slots * 8) && A((void**)&b.red, (size_t)kNumRed * G.n_part * 8) &&
               A((void**)&b.st, sizeof(ColState)) && A((void**)&b.n_active, 64) &&
@@ -997,7 +1096,7 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
         }
     }
     g->prof_on = saved_prof;
-    void* ptrs[] = {b.Y, b.ACC, b.G, b.Q, b.partA, b.partA_any, b.partB, b.red, b.st, b.n_active};
+    void* ptrs[] = {b.Y, b.ACC, b.S, b.G, b.Q, b.partA, b.partA_any, b.partB, b.red, b.st, b.n_active};
     for (void* p : ptrs) hipFree(p);
     if (b.h_active) hipHostFree(b.h_active);
     return rc;
