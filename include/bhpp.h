@@ -138,11 +138,14 @@ bhpp_status bhpp_query(bhpp_graph* g, int32_t source, double alpha, double eps,
 /*
  * n_src independent queries executed together: up to 64 sources share every
  * two-hop sweep as columns of one dense residue block, each source with its
- * own phase, thresholds and stopping point.
+ * own phase, thresholds and stopping point. With more than 64 sources the
+ * block is fed from a queue: as sources finish, their results are written out
+ * and the next sources take their columns, so sources of very different cost
+ * share the sweeps without waiting for each other.
  *   sources      host int32[n_src]
  *   eps          host double[n_src] (per-source error threshold) or NULL to use eps_all
  *   scores_out   device [n_src][n_u] row-major of the graph dtype, or NULL
- *   k            top-k size, 0 to skip top-k, else 1 <= k <= n_u - (exclude_self != 0)
+ *   k            top-k size, 0 to skip top-k, else 1 <= k <= min(4096, n_u - (exclude_self != 0))
  *   exclude_self nonzero: the source itself is left out of its own top-k
  *   topk_ids     device int32[n_src][k] (required if k > 0)
  *   topk_vals    device [n_src][k] of the graph dtype (required if k > 0)
@@ -202,6 +205,25 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
  */
 bhpp_status bhpp_profile_enable(bhpp_graph* g, int32_t enable);
 bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[4], int64_t launches[4], double bytes[4]);
+
+/*
+ * Launch settings of the sweep kernels: config[0] entries per work tile (rows
+ * longer than this are split into pieces), config[1] row gathers kept in
+ * flight per wavefront in the 64-source gather (4, 8 or 16), config[2] 1 to
+ * stream adjacency loads and row outputs past the caches, config[3] 1 to
+ * replay each chunk of sweeps as a captured HIP graph. Results do not depend
+ * on them, only the time does.
+ *
+ * bhpp_autotune times a few sweeps of a 64-source block for each candidate
+ * (tile sizes 256/512/1024, 4/8/16 gathers in flight, streaming off/on) on
+ * hip_stream's device, keeps the fastest and writes it to config_out (host).
+ * It synchronises hip_stream. bhpp_set_launch_config applies a setting saved
+ * earlier (e.g. a cache keyed by the graph); bhpp_get_launch_config reads the
+ * current one. Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE_ERROR.
+ */
+bhpp_status bhpp_autotune(bhpp_graph* g, void* hip_stream, int32_t config_out[4]);
+bhpp_status bhpp_set_launch_config(bhpp_graph* g, const int32_t config[4]);
+bhpp_status bhpp_get_launch_config(const bhpp_graph* g, int32_t config_out[4]);
 
 /* Free the handle and all device memory it owns (NULL is ignored). The caller
    must make sure no work using it is still running. */

@@ -29,8 +29,8 @@ BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER = 1, 2
 
 # names exported by include/bhpp.h
 EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
-            "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_free_graph",
-            "bhpp_status_string"]
+            "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_autotune",
+            "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_free_graph", "bhpp_status_string"]
 
 
 class BhppError(RuntimeError):
@@ -99,6 +99,12 @@ def load_library():
     L.bhpp_profile_enable.argtypes = [P, I32]
     L.bhpp_profile_read.restype = I32
     L.bhpp_profile_read.argtypes = [P, P, P, P]
+    L.bhpp_autotune.restype = I32
+    L.bhpp_autotune.argtypes = [P, P, P]
+    L.bhpp_set_launch_config.restype = I32
+    L.bhpp_set_launch_config.argtypes = [P, P]
+    L.bhpp_get_launch_config.restype = I32
+    L.bhpp_get_launch_config.argtypes = [P, P]
     L.bhpp_free_graph.restype = None
     L.bhpp_free_graph.argtypes = [P]
     L.bhpp_status_string.restype = ctypes.c_char_p
@@ -222,6 +228,45 @@ class Graph:
             ctypes.cast(st, ctypes.c_void_p) if stats else None, _stream())
         _check(rc, "bhpp_query_batch")
         return dict(scores=sc, ids=ids, vals=vals, stats=[st[i].as_dict() for i in range(n)] if stats else None)
+
+    def autotune(self, cache_path=None):
+        """Pick the fastest launch setting for this graph (bhpp_autotune) and
+        remember it in a JSON cache keyed by the graph's shape, so later builds
+        of the same graph can reuse it with apply_cached_config()."""
+        import json
+        cfg = (ctypes.c_int32 * 4)()
+        _check(load_library().bhpp_autotune(self._h, _stream(), cfg), "bhpp_autotune")
+        out = dict(tile_edges=cfg[0], inflight=cfg[1], nt_stream=cfg[2], graphs=cfg[3])
+        if cache_path:
+            data = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
+            data[self.cache_key()] = out
+            tmp = cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache_path)
+        return out
+
+    def cache_key(self):
+        inf = self.info()
+        return f"{inf['n_u']}x{inf['n_v']}x{inf['n_edges']}:{self.dtype}"
+
+    def apply_cached_config(self, cache_path):
+        import json
+        if not os.path.exists(cache_path):
+            return None
+        ent = json.load(open(cache_path)).get(self.cache_key())
+        if ent:
+            self.set_launch_config(ent)
+        return ent
+
+    def set_launch_config(self, cfg):
+        arr = (ctypes.c_int32 * 4)(cfg["tile_edges"], cfg["inflight"], cfg["nt_stream"], cfg["graphs"])
+        _check(load_library().bhpp_set_launch_config(self._h, arr), "bhpp_set_launch_config")
+
+    def launch_config(self):
+        cfg = (ctypes.c_int32 * 4)()
+        _check(load_library().bhpp_get_launch_config(self._h, cfg), "bhpp_get_launch_config")
+        return dict(tile_edges=cfg[0], inflight=cfg[1], nt_stream=cfg[2], graphs=cfg[3])
 
     def profile(self, enable):
         _check(load_library().bhpp_profile_enable(self._h, 1 if enable else 0), "bhpp_profile_enable")

@@ -216,6 +216,44 @@ bhpp_status bhpp_profile_read(bhpp_graph* h, double ms[4], int64_t launches[4], 
     return BHPP_OK;
 }
 
+bhpp_status bhpp_autotune(bhpp_graph* h, void* hip_stream, int32_t config_out[4]) {
+    if (!h || !h->g || !config_out) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        int cfg[4];
+        bhpp_status rc = bhpp::autotune(g, stream_of(hip_stream), cfg);
+        if (rc == BHPP_OK)
+            for (int i = 0; i < 4; ++i) config_out[i] = cfg[i];
+        return sticky(g, rc);
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_set_launch_config(bhpp_graph* h, const int32_t config[4]) {
+    if (!h || !h->g || !config) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        int cfg[4] = {config[0], config[1], config[2], config[3]};
+        return sticky(g, bhpp::set_launch_config(g, cfg));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_get_launch_config(const bhpp_graph* h, int32_t config_out[4]) {
+    if (!h || !h->g || !config_out) return BHPP_INVALID_ARG;
+    const Graph* g = h->g;
+    config_out[0] = g->tile_edges;
+    config_out[1] = g->inflight;
+    config_out[2] = g->nt_stream;
+    config_out[3] = g->use_graphs;
+    return BHPP_OK;
+}
+
 void bhpp_free_graph(bhpp_graph* h) {
     if (!h) return;
     if (h->g) {

@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.h"
@@ -174,14 +176,14 @@ static int bits_for(uint64_t maxval) {
 // work tiles (host): rows grouped so each tile covers about kTileEdges
 // adjacency entries; rows longer than that are split into pieces.
 // ---------------------------------------------------------------------------
-bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, TileSet* ts) {
+bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts) {
     std::vector<Tile> tiles;
     std::vector<SplitRow> split;
     int32_t slot = 0;
     int32_t end = n_rows;
     while (end > 0 && rp[end] == rp[end - 1]) --end;   // isolated suffix (degree order) needs no work
     int32_t row = 0;
-    const int64_t T = kTileEdges;
+    const int64_t T = tile_edges;
     auto log2ceil = [](int64_t d) {
         int l = 0;
         while ((1LL << l) < d && l < 6) ++l;
@@ -243,11 +245,9 @@ void free_graph(Graph* g) {
     for (void* p : ptrs) hipFree(p);
     free_tiles(&g->tiles_u);
     free_tiles(&g->tiles_v);
-    Workspace& w = g->ws;
-    void* wp[] = {w.Y, w.ACC, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores};
-    for (void* p : wp) hipFree(p);
-    if (w.h_active) hipHostFree(w.h_active);
+    free_workspace(g->ws);
     for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
+    if (g->work) hipStreamDestroy(g->work);
     delete g;
 }
 
@@ -494,10 +494,12 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
     BHPP_HIP(hipMemcpyAsync(h_rp_u.data(), g->rp_u, sizeof(int64_t) * ((size_t)nu + 1), hipMemcpyDeviceToHost, s));
     BHPP_HIP(hipMemcpyAsync(h_rp_v.data(), g->rp_v, sizeof(int64_t) * ((size_t)nv + 1), hipMemcpyDeviceToHost, s));
     BHPP_HIP(hipStreamSynchronize(s));
-    rc = build_tiles(h_rp_u, nu, &g->tiles_u);
+    rc = build_tiles(h_rp_u, nu, g->tile_edges, &g->tiles_u);
     if (rc) return rc;
-    rc = build_tiles(h_rp_v, nv, &g->tiles_v);
+    rc = build_tiles(h_rp_v, nv, g->tile_edges, &g->tiles_v);
     if (rc) return rc;
+    g->h_rp_u = std::move(h_rp_u);
+    g->h_rp_v = std::move(h_rp_v);
 
     bhpp_graph_summary& I = g->info;
     I.n_u = nu;
@@ -557,6 +559,16 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
                         const void* ew, const bhpp_graph_opts& opts, hipStream_t s, Graph** out) {
     Graph* g = new (std::nothrow) Graph();
     if (!g) return BHPP_OUT_OF_MEMORY;
+    // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1"
+    if (const char* e = getenv("BHPP_TUNE")) {
+        int v;
+        const char* q;
+        if ((q = strstr(e, "tile=")) && sscanf(q, "tile=%d", &v) == 1 && v >= 64) g->tile_edges = v;
+        if ((q = strstr(e, "inflight=")) && sscanf(q, "inflight=%d", &v) == 1 && (v == 4 || v == 8 || v == 16))
+            g->inflight = v;
+        if ((q = strstr(e, "nt=")) && sscanf(q, "nt=%d", &v) == 1) g->nt_stream = v ? 1 : 0;
+        if ((q = strstr(e, "graphs=")) && sscanf(q, "graphs=%d", &v) == 1) g->use_graphs = v ? 1 : 0;
+    }
     g->nu = n_u;
     g->nv = n_v;
     g->dtype = opts.dtype;

@@ -17,6 +17,7 @@ constexpr int kTileEdges = 512;      // target adjacency entries per work tile
 constexpr int kMaxCols = 64;         // sources per dense residue block (one per lane)
 constexpr int kPassThreads = 256;    // threads per block of the sweep kernels
 constexpr int kNumRed = 5;           // per-source reductions after a step (see Red)
+constexpr int kTopkTmpK = 4096;      // largest k of the batched top-k
 
 // A unit of work for one wavefront: either a run of whole rows whose degrees
 // are similar (rows are numbered by decreasing degree) or one piece of a row
@@ -85,6 +86,12 @@ struct ColState {
     // statistics
     int32_t ss_sel_iters, ss_seq_iters, pi_sel_iters, t, ss_switched, pi_returned;
     double np_ss, np_pi, sum_r_ss, sum_rf;
+    // scheduling: a column reused for a new query keeps the old query's Y and
+    // ACC until its first sweep, which reads them as y = e_src and ACC = 0
+    int32_t fresh;
+    int32_t src_row;     // internal id of the source
+    int32_t qid;         // index of the query in the caller's arrays, -1 if none
+    int32_t pad;
 };
 
 struct Workspace {
@@ -102,8 +109,13 @@ struct Workspace {
     ColState* st = nullptr;      // [cols]
     int32_t* n_active = nullptr; // device counter of unfinished sources
     int32_t* h_active = nullptr; // pinned host mirror
-    void* scores = nullptr;      // [cols][n_u] row-major scratch for top-k
+    void* scores = nullptr;      // [cols][n_u]: G during sweeps, row-major score scratch for top-k
+    int32_t* ids_tmp = nullptr;  // [cols][kTopkTmpK] top-k scratch
+    void* vals_tmp = nullptr;
+    int32_t* ex_tmp = nullptr;   // [cols] excluded id per exported row
     size_t bytes = 0;
+    // sweep chunks captured as HIP graphs (one per column count), replayed per chunk
+    hipGraphExec_t chunk_exec[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 struct Graph {
@@ -129,12 +141,19 @@ struct Graph {
     // host copies
     std::vector<double> h_ws_u;       // external order, FP64
     std::vector<int32_t> h_perm_u;    // external -> internal
+    std::vector<int64_t> h_rp_u, h_rp_v;   // internal row offsets (tiles are rebuilt from them)
     bhpp_graph_summary info{};
     std::map<double, double> lambda_cache;   // alpha -> lambda
     int32_t tau = 0;
     // runtime
     std::mutex mu;
     Workspace ws;
+    hipStream_t work = nullptr;      // the library's own stream (capturable), joined to the caller's
+    // launch settings chosen by the autotuner (or defaults / BHPP_TUNE)
+    int tile_edges = kTileEdges;
+    int inflight = 8;
+    int nt_stream = 0;
+    int use_graphs = 1;
     bool sticky_error = false;
     // profiling of the sweep kernels
     bool prof_on = false;
@@ -163,8 +182,11 @@ bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const doubl
                         int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, hipStream_t s);
 bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
                       int32_t dtype, int32_t* ids_out, void* vals_out, hipStream_t s);
-bhpp_status ensure_workspace(Graph* g, int cols);
-bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, TileSet* ts);
+bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s);
+bhpp_status set_launch_config(Graph* g, const int* cfg);
+bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts);
+void free_workspace(Workspace& w);
+bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg);
 void free_tiles(TileSet* ts);
 
 inline int next_pow2(int x) {

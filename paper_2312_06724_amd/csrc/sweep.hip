@@ -432,6 +432,8 @@ __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ 
     const int col = threadIdx.x & (COLS - 1);
     const ColState& cs = st[col];
     const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
+    const bool fresh = cs.fresh != 0;
+    const int32_t src_row = cs.src_row;
     const size_t n = (size_t)n_rows * COLS;
     const size_t stride = (size_t)gridDim.x * kPassThreads;
     constexpr int U = 4;
@@ -440,8 +442,9 @@ __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ 
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const size_t i = i0 + k * stride;
-            y[k] = i < n ? Y[i] : VT(0);
-            iw[k] = i < n ? inv_ws[i / COLS] : VT(0);
+            const int32_t x = (int32_t)(i / COLS);
+            y[k] = i < n ? (fresh ? (x == src_row ? VT(1) : VT(0)) : Y[i]) : VT(0);   // new query: y = e_src
+            iw[k] = i < n ? inv_ws[x] : VT(0);
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -470,6 +473,8 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
     const int convert = cs.convert;
     const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
     const VT one_minus_alpha = VT(1) - alpha;
+    const bool fresh = cs.fresh != 0;
+    const int32_t src_row = cs.src_row;
     double r[kNumRed] = {0, 0, 0, 0, 0};
     const size_t n = (size_t)n_rows * COLS;
     const size_t stride = (size_t)gridDim.x * kPassThreads;   // a multiple of COLS: the column stays fixed
@@ -484,8 +489,8 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
             const int32_t x = in ? (int32_t)(i / COLS) : 0;
             d[k] = in ? deg[x] : 0;
             iw[k] = in ? inv_ws[x] : VT(0);
-            y[k] = in ? Y[i] : VT(0);
-            a[k] = in ? ACC[i] : VT(0);
+            y[k] = in ? (fresh ? (x == src_row ? VT(1) : VT(0)) : Y[i]) : VT(0);   // new query: y = e_src
+            a[k] = (in && !fresh) ? ACC[i] : VT(0);                                  // and ACC = 0
             g[k] = in ? G[i] : VT(0);
         }
 #pragma unroll
@@ -542,6 +547,7 @@ __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
 }
 
 __device__ void control_update(ColState& s, const double* R, int32_t* n_active) {
+    s.fresh = 0;   // after its first sweep a column holds its own query's Y and ACC
     const int m = s.mode;
     if (m == MODE_DONE) return;
     s.steps += 1;
@@ -640,22 +646,27 @@ __global__ void k_seed(VT* Y, const int32_t* rows, int ncols, int cols) {
     if (c < ncols) Y[(size_t)rows[c] * cols + c] = VT(1);
 }
 
-// ACC[internal x][c] -> out[c][external x] (row-major), through an LDS tile.
+// Finished columns cols[0..m) of ACC (internal node order) -> out[j][external x]
+// (row-major, one row per finished query), through an LDS tile: reads and
+// writes are both coalesced.
+// Isolated nodes score 0; their rows of ACC are never written by the sweeps
+// (and may hold another block width's data), so they are not read.
 template <int COLS, typename VT>
-__global__ __launch_bounds__(256) void k_export_scores(const VT* ACC, const int32_t* perm, int32_t nu, int ncols,
-                                                       VT* out) {
+__global__ __launch_bounds__(256) void k_extract(const VT* ACC, const int32_t* perm, const int32_t* deg, int32_t nu,
+                                                 const int32_t* cols, int m, VT* out) {
     __shared__ VT tile[64][COLS + (COLS == 1 ? 0 : 1)];
     const int x0 = blockIdx.x * 64;
     for (int idx = threadIdx.x; idx < 64 * COLS; idx += 256) {
-        int i = idx / COLS, c = idx % COLS;
-        int x = x0 + i;
-        tile[i][c] = x < nu ? ACC[(size_t)perm[x] * COLS + c] : VT(0);
+        const int i = idx / COLS, c = idx % COLS;
+        const int x = x0 + i;
+        const int32_t xi = x < nu ? perm[x] : 0;
+        tile[i][c] = (x < nu && deg[xi] > 0) ? ACC[(size_t)xi * COLS + c] : VT(0);
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < 64 * COLS; idx += 256) {
-        int c = idx / 64, i = idx % 64;
-        int x = x0 + i;
-        if (c < ncols && x < nu) out[(size_t)c * nu + x] = tile[i][c];
+    for (int idx = threadIdx.x; idx < 64 * m; idx += 256) {
+        const int j = idx / 64, i = idx % 64;
+        const int x = x0 + i;
+        if (x < nu) out[(size_t)j * nu + x] = tile[i][cols[j]];
     }
 }
 
@@ -694,32 +705,12 @@ struct Block {
     int32_t* h_active;
 };
 
-// Launch knobs of the 64-column gather, from BHPP_TUNE="inflight=16,nt=1"
-// (defaults below). They pick between equivalent schedules; results do not change.
-struct Tune {
-    int inflight = 8;
-    int nt = 0;
-};
-static const Tune& tune() {
-    static Tune t = [] {
-        Tune x;
-        if (const char* e = getenv("BHPP_TUNE")) {
-            int v;
-            const char* q;
-            if ((q = strstr(e, "inflight=")) && sscanf(q, "inflight=%d", &v) == 1) x.inflight = v;
-            if ((q = strstr(e, "nt=")) && sscanf(q, "nt=%d", &v) == 1) x.nt = v;
-        }
-        return x;
-    }();
-    return t;
-}
-
 template <typename VT, typename WT, bool SIDE_A>
-static void launch_gather64(int blocks, hipStream_t s, const GatherArgs<VT, WT>& a) {
-    switch (tune().inflight) {
-        case 8: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 8>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
-        case 32: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 32>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 16>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+static void launch_gather64(int inflight, int blocks, hipStream_t s, const GatherArgs<VT, WT>& a) {
+    switch (inflight) {
+        case 4: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 4>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+        case 16: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 16>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+        default: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 8>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
     }
 }
 
@@ -779,7 +770,7 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     A.n_active = b.n_active;
     A.red = b.red;
     A.n_part = G.n_part;
-    A.nt_stream = tune().nt;
+    A.nt_stream = g->nt_stream;
     GatherArgs<VT, WT> B = A;
     B.tiles = g->tiles_u.tiles;
     B.n_tiles = g->tiles_u.n_tiles;
@@ -800,7 +791,7 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     prof_begin(g, s, 0, launch_bytes<VT, WT>(g, COLS, 0), ev);
     A.red_slot = G.offA;
     if (COLS == 64)
-        launch_gather64<VT, WT, true>(G.blkA, s, A);
+        launch_gather64<VT, WT, true>(g->inflight, G.blkA, s, A);
     else if (COLS == 1)
         hipLaunchKernelGGL((k_gather1<VT, WT, true>), dim3(G.blkA), dim3(kPassThreads), 0, s, A);
     else
@@ -813,7 +804,7 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     prof_begin(g, s, 1, launch_bytes<VT, WT>(g, COLS, 1), ev);
     B.red_slot = 0;
     if (COLS == 64)
-        launch_gather64<VT, WT, false>(G.blkB, s, B);
+        launch_gather64<VT, WT, false>(g->inflight, G.blkB, s, B);
     else if (COLS == 1)
         hipLaunchKernelGGL((k_gather1<VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
     else
@@ -832,49 +823,56 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
 }
 
 constexpr int kStepsPerChunk = 8;
-constexpr int kMaxSteps = 4000;   // a query needs O(log 1/eps) sweeps; this only stops runaways
+constexpr int kMaxSteps = 4000;   // sweeps without a finished query; a query needs O(log 1/eps)
 
-// Run every source of the block to completion. The phase of each source
-// lives on the device; the host only polls the count of unfinished sources
-// once per chunk of sweeps (and keeps one chunk in flight while it waits).
+// One chunk of kStepsPerChunk sweeps. Unless the kernels are being profiled,
+// the chunk is captured once as a HIP graph (all state lives in device
+// memory, so every replay continues where the last one stopped) and replayed.
 template <int COLS, typename VT, typename WT>
-static bhpp_status run_block(Graph* g, const Block& b, hipStream_t s, int* steps_out) {
+static bhpp_status launch_chunk(Graph* g, const Block& b, const Geometry& G, hipStream_t s, hipGraphExec_t* cache) {
+    if (cache && g->use_graphs && !g->prof_on) {
+        if (*cache == nullptr) {
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return BHPP_DEVICE_ERROR;
+            bhpp_status rc = BHPP_OK;
+            for (int i = 0; i < kStepsPerChunk && rc == BHPP_OK; ++i) rc = launch_step<COLS, VT, WT>(g, b, G, s);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &graph);
+            if (rc != BHPP_OK || e != hipSuccess || graph == nullptr) {
+                if (graph) hipGraphDestroy(graph);
+                (void)hipGetLastError();
+                return rc != BHPP_OK ? rc : BHPP_DEVICE_ERROR;
+            }
+            const hipError_t e2 = hipGraphInstantiate(cache, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e2 != hipSuccess) {
+                *cache = nullptr;
+                return BHPP_DEVICE_ERROR;
+            }
+        }
+        BHPP_HIP(hipGraphLaunch(*cache, s));
+        return BHPP_OK;
+    }
+    for (int i = 0; i < kStepsPerChunk; ++i) {
+        const bhpp_status rc = launch_step<COLS, VT, WT>(g, b, G, s);
+        if (rc) return rc;
+    }
+    return BHPP_OK;
+}
+
+// Run the block until no source is active (no refill): used for lambda.
+template <int COLS, typename VT, typename WT>
+static bhpp_status run_plain(Graph* g, const Block& b, hipStream_t s) {
     const Geometry G = geometry(g);
-    hipEvent_t evs[2];
-    BHPP_HIP(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
-    BHPP_HIP(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
-    int32_t* h = b.h_active;   // two pinned slots
-    int steps = 0, chunk = 0;
-    bhpp_status rc = BHPP_OK;
-    bool pending = false;
+    int steps = 0;
     for (;;) {
-        for (int i = 0; i < kStepsPerChunk; ++i) {
-            rc = launch_step<COLS, VT, WT>(g, b, G, s);
-            if (rc) break;
-        }
-        if (rc) break;
+        bhpp_status rc = launch_chunk<COLS, VT, WT>(g, b, G, s, nullptr);
+        if (rc) return rc;
         steps += kStepsPerChunk;
-        const int slot = chunk & 1;
-        if (hipMemcpyAsync(&h[slot], b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipEventRecord(evs[slot], s) != hipSuccess) {
-            rc = BHPP_DEVICE_ERROR;
-            break;
-        }
-        if (pending) {   // wait for the previous chunk's count
-            if (hipEventSynchronize(evs[slot ^ 1]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
-            if (h[slot ^ 1] == 0) break;
-        }
-        pending = true;
-        ++chunk;
-        if (steps > kMaxSteps) { rc = BHPP_NO_CONVERGENCE; break; }
+        BHPP_HIP(hipMemcpyAsync(b.h_active, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BHPP_HIP(hipStreamSynchronize(s));
+        if (b.h_active[0] == 0) return BHPP_OK;
+        if (steps > kMaxSteps) return BHPP_NO_CONVERGENCE;
     }
-    if (rc == BHPP_OK || rc == BHPP_NO_CONVERGENCE) {
-        if (hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
-    }
-    hipEventDestroy(evs[0]);
-    hipEventDestroy(evs[1]);
-    if (steps_out) *steps_out = steps;
-    return rc;
 }
 
 static void init_state(ColState& c, double alpha, double ws_src, double eps, double eps_b_ratio, double lambda,
@@ -892,6 +890,7 @@ static void init_state(ColState& c, double alpha, double ws_src, double eps, dou
     c.mode = MODE_SS_SEL;                    // Algorithm 3 starts with selective pushes
     c.ruleA = c.ruleB = RULE_SS;
     c.convert = 0;
+    c.qid = -1;
 }
 
 static void done_state(ColState& c) {
@@ -899,72 +898,191 @@ static void done_state(ColState& c) {
     c.mode = MODE_DONE;
     c.alpha = 0.5;
     c.k_ss = c.k_pi = 1e300;
+    c.qid = -1;
 }
 
+static void fill_stats(const ColState& cs, bhpp_query_stats& q) {
+    q.ss_sel_iters = cs.ss_sel_iters;
+    q.ss_seq_iters = cs.ss_seq_iters;
+    q.pi_sel_iters = cs.pi_sel_iters;
+    q.t = cs.t;
+    q.ss_switched = cs.ss_switched;
+    q.pi_returned = cs.pi_returned;
+    q.steps = cs.steps;
+    q.reserved = 0;
+    q.np_ss = cs.np_ss;
+    q.np_pi = cs.np_pi;
+    q.gamma = cs.gamma;
+    q.sum_r_ss = cs.sum_r_ss;
+    q.sum_rf = cs.sum_rf;
+}
+
+static int log2i(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+// Queries are fed to a block of COLS columns from a queue. When enough
+// columns have finished (or the queue is empty and all have), their beta'
+// rows are extracted, their top-k computed, and the free columns take the
+// next queries; a reused column needs no reset pass (ColState::fresh).
 template <int COLS, typename VT, typename WT>
-static bhpp_status run_tile(Graph* g, int ncols, const int32_t* src_ext, const double* eps, double alpha,
-                            double lambda, void* scores_out, hipStream_t s, std::vector<ColState>& hs) {
+static bhpp_status run_sched(Graph* g, int n, const int32_t* src_ext, const double* eps, double alpha,
+                             double lambda, void* scores_out, int k, int exclude_self, int32_t* ids_out,
+                             void* vals_out, bhpp_query_stats* stats, hipStream_t s) {
     Workspace& w = g->ws;
-    Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
-    hs.assign(COLS, ColState{});
-    std::vector<int32_t> rows(COLS, 0);
-    for (int c = 0; c < COLS; ++c) {
-        if (c < ncols) {
-            const int32_t u = src_ext[c];
-            init_state(hs[c], alpha, g->h_ws_u[u], eps[c], g->info.eps_b_ratio, lambda, g->ne);
-            rows[c] = g->h_perm_u[u];
-        } else {
-            done_state(hs[c]);
-        }
-    }
-    const size_t nU = (size_t)g->nu * COLS;
-    int32_t* d_rows = reinterpret_cast<int32_t*>(w.red);   // borrow: red is rewritten by every sweep
-    BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
-    BHPP_HIP(hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * COLS, hipMemcpyHostToDevice, s));
-    int32_t act = ncols;
-    BHPP_HIP(hipMemcpyAsync(w.n_active, &act, sizeof(int32_t), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_fill<VT>, dim3(2048), dim3(256), 0, s, as<VT>(w.Y), nU, VT(0));
-    hipLaunchKernelGGL(k_fill<VT>, dim3(2048), dim3(256), 0, s, as<VT>(w.ACC), nU, VT(0));
-    hipLaunchKernelGGL(k_seed<VT>, dim3(1), dim3(64), 0, s, as<VT>(w.Y), d_rows, ncols, COLS);
-    BHPP_HIP(hipGetLastError());
-    BHPP_HIP(hipStreamSynchronize(s));   // d_rows is borrowed from red
-    bhpp_status rc = run_block<COLS, VT, WT>(g, b, s, nullptr);
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    const Geometry G = geometry(g);
+    const size_t nu = (size_t)g->nu, e = (size_t)g->elem;
+    std::vector<ColState> hs(COLS);
+    for (int c = 0; c < COLS; ++c) done_state(hs[c]);
+    int next = 0;
+    auto assign = [&](int c) {
+        const int q = next++;
+        const int32_t u = src_ext[q];
+        init_state(hs[c], alpha, g->h_ws_u[u], eps[q], g->info.eps_b_ratio, lambda, g->ne);
+        hs[c].fresh = 1;
+        hs[c].src_row = g->h_perm_u[u];
+        hs[c].qid = q;
+    };
+    for (int c = 0; c < COLS && next < n; ++c) assign(c);
+    auto upload = [&]() -> bhpp_status {
+        int32_t act = 0;
+        for (int c = 0; c < COLS; ++c) act += hs[c].mode != MODE_DONE ? 1 : 0;
+        w.h_active[2] = act;
+        BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
+        BHPP_HIP(hipMemcpyAsync(w.n_active, &w.h_active[2], sizeof(int32_t), hipMemcpyHostToDevice, s));
+        return BHPP_OK;
+    };
+    bhpp_status rc = upload();
     if (rc) return rc;
-    BHPP_HIP(hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost));
-    if (scores_out) {
-        hipLaunchKernelGGL((k_export_scores<COLS, VT>), dim3((g->nu + 63) / 64), dim3(256), 0, s, as<VT>(w.ACC),
-                           g->perm_u, g->nu, ncols, as<VT>(scores_out));
-        BHPP_HIP(hipGetLastError());
+    int live = 0;
+    for (int c = 0; c < COLS; ++c) live += hs[c].qid >= 0 ? 1 : 0;
+    const int R = COLS >= 8 ? COLS / 8 : 1;   // finished columns that trigger an export round
+    hipGraphExec_t* cache = &w.chunk_exec[log2i(COLS)];
+    hipEvent_t evs[2];
+    BHPP_HIP(hipEventCreateWithFlags(&evs[0], hipEventDisableTiming));
+    BHPP_HIP(hipEventCreateWithFlags(&evs[1], hipEventDisableTiming));
+    int chunk = 0, steps = 0;
+    bool pending = false;
+    std::vector<int32_t> cols, ex;
+    while (live > 0) {
+        rc = launch_chunk<COLS, VT, WT>(g, b, G, s, cache);
+        if (rc) break;
+        steps += kStepsPerChunk;
+        const int slot = chunk & 1;
+        if (hipMemcpyAsync(&w.h_active[slot], w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(evs[slot], s) != hipSuccess) {
+            rc = BHPP_DEVICE_ERROR;
+            break;
+        }
+        bool round = false;
+        if (pending) {   // the count after the previous chunk
+            if (hipEventSynchronize(evs[slot ^ 1]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
+            const int act = w.h_active[slot ^ 1];
+            const int done = live - act;
+            round = act == 0 || (next < n && done >= R);
+        }
+        pending = true;
+        ++chunk;
+        if (!round) {
+            if (steps > kMaxSteps) { rc = BHPP_NO_CONVERGENCE; break; }
+            continue;
+        }
+        // export round: wait for the chunk in flight, then read every column's state
+        if (hipStreamSynchronize(s) != hipSuccess ||
+            hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = BHPP_DEVICE_ERROR;
+            break;
+        }
+        cols.clear();
+        ex.clear();
+        for (int c = 0; c < COLS; ++c)
+            if (hs[c].qid >= 0 && hs[c].mode == MODE_DONE) {
+                cols.push_back(c);
+                ex.push_back(exclude_self ? src_ext[hs[c].qid] : -1);
+            }
+        const int m = (int)cols.size();
+        if (m > 0) {
+            int32_t* d_cols = w.ex_tmp;
+            int32_t* d_ex = w.ex_tmp + kMaxCols;
+            BHPP_HIP(hipMemcpyAsync(d_cols, cols.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+            BHPP_HIP(hipMemcpyAsync(d_ex, ex.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+            VT* rows = as<VT>(w.scores);   // [m][nu]; G is rewritten by the next sweep
+            hipLaunchKernelGGL((k_extract<COLS, VT>), dim3((g->nu + 63) / 64), dim3(256), 0, s, as<VT>(w.ACC),
+                               g->perm_u, g->deg_u, g->nu, d_cols, m, rows);
+            BHPP_HIP(hipGetLastError());
+            if (k > 0) {
+                rc = topk_rows(rows, m, g->nu, k, d_ex, g->dtype, w.ids_tmp, w.vals_tmp, s);
+                if (rc) break;
+            }
+            for (int j = 0; j < m; ++j) {
+                const int q = hs[cols[j]].qid;
+                if (scores_out)
+                    BHPP_HIP(hipMemcpyAsync((char*)scores_out + (size_t)q * nu * e, (char*)rows + (size_t)j * nu * e,
+                                            nu * e, hipMemcpyDeviceToDevice, s));
+                if (k > 0) {
+                    BHPP_HIP(hipMemcpyAsync(ids_out + (size_t)q * k, w.ids_tmp + (size_t)j * k, sizeof(int32_t) * k,
+                                            hipMemcpyDeviceToDevice, s));
+                    BHPP_HIP(hipMemcpyAsync((char*)vals_out + (size_t)q * k * e, (char*)w.vals_tmp + (size_t)j * k * e,
+                                            e * k, hipMemcpyDeviceToDevice, s));
+                }
+                if (stats) fill_stats(hs[cols[j]], stats[q]);
+                hs[cols[j]].qid = -1;
+                --live;
+                if (next < n) {
+                    assign(cols[j]);
+                    ++live;
+                }
+            }
+            rc = upload();
+            if (rc) break;
+            steps = 0;
+        }
+        pending = false;
+        chunk = 0;
     }
-    return BHPP_OK;
+    if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    hipEventDestroy(evs[0]);
+    hipEventDestroy(evs[1]);
+    return rc;
 }
 
 template <typename VT, typename WT>
-static bhpp_status run_tile_dispatch(Graph* g, int ncols, const int32_t* src, const double* eps, double alpha,
-                                     double lambda, void* scores, hipStream_t s, std::vector<ColState>& hs) {
-    const int cols = next_pow2(ncols);
+static bhpp_status run_sched_dispatch(Graph* g, int cols, int n, const int32_t* src, const double* eps, double alpha,
+                                      double lambda, void* scores, int k, int ex, int32_t* ids, void* vals,
+                                      bhpp_query_stats* st, hipStream_t s) {
     switch (cols) {
-        case 1: return run_tile<1, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
-        case 2: return run_tile<2, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
-        case 4: return run_tile<4, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
-        case 8: return run_tile<8, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
-        case 16: return run_tile<16, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
-        case 32: return run_tile<32, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
-        case 64: return run_tile<64, VT, WT>(g, ncols, src, eps, alpha, lambda, scores, s, hs);
+        case 1: return run_sched<1, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 2: return run_sched<2, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 4: return run_sched<4, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 8: return run_sched<8, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 16: return run_sched<16, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 32: return run_sched<32, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 64: return run_sched<64, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
         default: return BHPP_INVALID_ARG;
     }
 }
 
-static void free_workspace(Workspace& w) {
-    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores};
+void free_workspace(Workspace& w) {
+    for (hipGraphExec_t& x : w.chunk_exec)
+        if (x) {
+            hipGraphExecDestroy(x);
+            x = nullptr;
+        }
+    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores,
+                    w.ids_tmp, w.vals_tmp, w.ex_tmp};
     for (void* p : ptrs) hipFree(p);
     if (w.h_active) hipHostFree(w.h_active);
     w = Workspace{};
 }
 
-// Workspace of the query blocks. w.scores doubles as G during the sweeps and
-// as the row-major score scratch of the top-k afterwards.
-bhpp_status ensure_workspace(Graph* g, int cols) {
+// Workspace of the query block. w.scores doubles as G during the sweeps and
+// as the row-major score rows of finished queries between sweeps. Blocks of
+// fewer columns reuse the buffers with a smaller row stride; rows of isolated
+// nodes are never read (S and the update skip them, the extract writes 0).
+bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s) {
     Workspace& w = g->ws;
     const Geometry G = geometry(g);
     if (w.cols >= cols && w.n_part >= G.n_part) return BHPP_OK;
@@ -983,13 +1101,25 @@ bhpp_status ensure_workspace(Graph* g, int cols) {
               alloc(&w.partB, (size_t)g->tiles_u.n_slots * c * e) &&
               alloc((void**)&w.red, (size_t)kNumRed * c * G.n_part * 8 + 64 * 4) &&
               alloc((void**)&w.st, sizeof(ColState) * c) && alloc((void**)&w.n_active, 64) &&
-              alloc(&w.scores, (size_t)g->nu * c * e);
+              alloc(&w.scores, (size_t)g->nu * c * e) &&
+              alloc((void**)&w.ids_tmp, (size_t)kMaxCols * kTopkTmpK * 4) &&
+              alloc(&w.vals_tmp, (size_t)kMaxCols * kTopkTmpK * e) &&
+              alloc((void**)&w.ex_tmp, (size_t)2 * kMaxCols * 4);
     if (ok) ok = hipHostMalloc((void**)&w.h_active, 64) == hipSuccess;
     if (!ok) {
         free_workspace(w);
         (void)hipGetLastError();
         return BHPP_OUT_OF_MEMORY;
     }
+    const size_t nU = (size_t)g->nu * c;
+    if (e == 8) {
+        hipLaunchKernelGGL(k_fill<double>, dim3(2048), dim3(256), 0, s, as<double>(w.Y), nU, 0.0);
+        hipLaunchKernelGGL(k_fill<double>, dim3(2048), dim3(256), 0, s, as<double>(w.ACC), nU, 0.0);
+    } else {
+        hipLaunchKernelGGL(k_fill<float>, dim3(2048), dim3(256), 0, s, as<float>(w.Y), nU, 0.0f);
+        hipLaunchKernelGGL(k_fill<float>, dim3(2048), dim3(256), 0, s, as<float>(w.ACC), nU, 0.0f);
+    }
+    BHPP_HIP(hipGetLastError());
     w.cols = cols;
     w.elem = g->elem;
     w.n_part = G.n_part;
@@ -998,52 +1128,29 @@ bhpp_status ensure_workspace(Graph* g, int cols) {
 
 bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const double* eps, double alpha,
                         double lambda, void* scores_out, int32_t k, int32_t exclude_self, int32_t* topk_ids,
-                        void* topk_vals, bhpp_query_stats* stats, hipStream_t s) {
-    const int per = kMaxCols;
-    for (int base = 0; base < n; base += per) {
-        const int nc = n - base < per ? n - base : per;
-        bhpp_status rc = ensure_workspace(g, next_pow2(nc));
-        if (rc) return rc;
-        std::vector<ColState> hs;
-        void* scores = scores_out ? (void*)((char*)scores_out + (size_t)base * g->nu * g->elem)
-                                  : (k > 0 ? g->ws.scores : nullptr);
+                        void* topk_vals, bhpp_query_stats* stats, hipStream_t caller) {
+    if (k > kTopkTmpK) return BHPP_NOT_SUPPORTED;
+    if (!g->work) BHPP_HIP(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
+    hipStream_t s = g->work;
+    // the library's stream waits for the caller's prior work
+    hipEvent_t ev;
+    BHPP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    BHPP_HIP(hipEventRecord(ev, caller));
+    BHPP_HIP(hipStreamWaitEvent(s, ev, 0));
+    const int cols = next_pow2(n < kMaxCols ? n : kMaxCols);
+    bhpp_status rc = ensure_workspace(g, cols, s);
+    if (rc == BHPP_OK) {
         if (g->dtype == BHPP_DTYPE_F64)
-            rc = run_tile_dispatch<double, double>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs);
+            rc = run_sched_dispatch<double, double>(g, cols, n, src_ext, eps, alpha, lambda, scores_out, k,
+                                                    exclude_self, topk_ids, topk_vals, stats, s);
         else
-            rc = run_tile_dispatch<float, float>(g, nc, src_ext + base, eps + base, alpha, lambda, scores, s, hs);
-        if (rc) return rc;
-        if (k > 0) {
-            std::vector<int32_t> ex(nc, -1);
-            if (exclude_self)
-                for (int c = 0; c < nc; ++c) ex[c] = src_ext[base + c];
-            int32_t* d_ex = reinterpret_cast<int32_t*>(g->ws.red);
-            BHPP_HIP(hipMemcpyAsync(d_ex, ex.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, s));
-            rc = topk_rows(scores, nc, g->nu, k, d_ex, g->dtype, topk_ids + (size_t)base * k,
-                           (char*)topk_vals + (size_t)base * k * g->elem, s);
-            if (rc) return rc;
-            BHPP_HIP(hipStreamSynchronize(s));   // d_ex is borrowed from red
-        }
-        if (stats) {
-            for (int c = 0; c < nc; ++c) {
-                const ColState& cs = hs[c];
-                bhpp_query_stats& q = stats[base + c];
-                q.ss_sel_iters = cs.ss_sel_iters;
-                q.ss_seq_iters = cs.ss_seq_iters;
-                q.pi_sel_iters = cs.pi_sel_iters;
-                q.t = cs.t;
-                q.ss_switched = cs.ss_switched;
-                q.pi_returned = cs.pi_returned;
-                q.steps = cs.steps;
-                q.reserved = 0;
-                q.np_ss = cs.np_ss;
-                q.np_pi = cs.np_pi;
-                q.gamma = cs.gamma;
-                q.sum_r_ss = cs.sum_r_ss;
-                q.sum_rf = cs.sum_rf;
-            }
-        }
+            rc = run_sched_dispatch<float, float>(g, cols, n, src_ext, eps, alpha, lambda, scores_out, k,
+                                                  exclude_self, topk_ids, topk_vals, stats, s);
     }
-    return BHPP_OK;
+    // and the caller's stream waits for the library's work
+    if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(caller, ev, 0) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    hipEventDestroy(ev);
+    return rc;
 }
 
 // Lemma 4: rho = PowerIteration(e = 1, tau) computed in FP64 with one column
@@ -1065,9 +1172,8 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
     g->prof_on = false;
     if (rc == BHPP_OK) {
         ColState c;
-        memset(&c, 0, sizeof(c));
+        done_state(c);
         c.alpha = alpha;
-        c.k_ss = c.k_pi = 1e300;
         c.ln_inv = log(1.0 / (1.0 - alpha));
         if (tau > 0) {
             c.t_rem = tau;
@@ -1084,7 +1190,7 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
             rc = BHPP_DEVICE_ERROR;
         hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, as<double>(b.Y), nU, 1.0);
         hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, as<double>(b.ACC), nU, 0.0);
-        if (rc == BHPP_OK) rc = run_block<1, double, WT>(g, b, s, nullptr);
+        if (rc == BHPP_OK) rc = run_plain<1, double, WT>(g, b, s);
         if (rc == BHPP_OK) {
             std::vector<double> rho(nU);
             if (hipMemcpy(rho.data(), b.ACC, nU * 8, hipMemcpyDeviceToHost) != hipSuccess) rc = BHPP_DEVICE_ERROR;
@@ -1105,6 +1211,115 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
 bhpp_status compute_lambda(Graph* g, double alpha, int32_t tau, hipStream_t s, double* lambda_out) {
     if (g->dtype == BHPP_DTYPE_F64) return lambda_impl<double>(g, alpha, tau, s, lambda_out);
     return lambda_impl<float>(g, alpha, tau, s, lambda_out);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times sweeps of a 64-column block in PowerIteration mode for each
+// candidate launch setting (work-tile size, row gathers in flight, streaming
+// loads, graph replay) and keeps the fastest. The results do not depend on
+// the setting; only the time does.
+// ---------------------------------------------------------------------------
+template <typename VT, typename WT>
+static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out) {
+    const int COLS_T = 64;
+    bhpp_status rc = ensure_workspace(g, COLS_T, s);
+    if (rc) return rc;
+    Workspace& w = g->ws;
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    const Geometry G = geometry(g);
+    std::vector<ColState> hs(COLS_T);
+    for (int c = 0; c < COLS_T; ++c) {
+        done_state(hs[c]);
+        hs[c].alpha = g->info.alpha;
+        hs[c].mode = MODE_POWER;
+        hs[c].ruleA = hs[c].ruleB = RULE_ALL;
+        hs[c].t_rem = 1 << 20;               // never finishes within the timing
+        hs[c].fresh = 1;
+        hs[c].src_row = c % g->nu;           // hubs first in internal order
+    }
+    int32_t act = COLS_T;
+    BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS_T, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.n_active, &act, 4, hipMemcpyHostToDevice, s));
+    hipGraphExec_t* cache = &w.chunk_exec[log2i(COLS_T)];
+    rc = launch_chunk<COLS_T, VT, WT>(g, b, G, s, cache);   // warm-up (and capture)
+    if (rc) return rc;
+    hipEvent_t e0, e1;
+    BHPP_HIP(hipEventCreate(&e0));
+    BHPP_HIP(hipEventCreate(&e1));
+    BHPP_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps && rc == BHPP_OK; ++r) rc = launch_chunk<COLS_T, VT, WT>(g, b, G, s, cache);
+    BHPP_HIP(hipEventRecord(e1, s));
+    BHPP_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *ms_out = ms / (float)(reps * kStepsPerChunk);
+    // leave the block inactive
+    done_state(hs[0]);
+    for (int c = 0; c < COLS_T; ++c) done_state(hs[c]);
+    act = 0;
+    BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS_T, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.n_active, &act, 4, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
+static bhpp_status apply_setting(Graph* g, int tile_edges, int inflight, int nt, int graphs) {
+    for (hipGraphExec_t& x : g->ws.chunk_exec)
+        if (x) {
+            hipGraphExecDestroy(x);
+            x = nullptr;
+        }
+    if (tile_edges != g->tile_edges) {
+        free_tiles(&g->tiles_u);
+        free_tiles(&g->tiles_v);
+        g->tile_edges = tile_edges;
+        bhpp_status rc = build_tiles(g->h_rp_u, g->nu, tile_edges, &g->tiles_u);
+        if (rc) return rc;
+        rc = build_tiles(g->h_rp_v, g->nv, tile_edges, &g->tiles_v);
+        if (rc) return rc;
+        free_workspace(g->ws);   // slot counts changed
+    }
+    g->inflight = inflight;
+    g->nt_stream = nt;
+    g->use_graphs = graphs;
+    return BHPP_OK;
+}
+
+bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg) {
+    if (!g->work) BHPP_HIP(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
+    hipStream_t ws = g->work;
+    BHPP_HIP(hipStreamSynchronize(s));
+    const int tiles[] = {256, 512, 1024};
+    const int infl[] = {4, 8, 16};
+    int best[4] = {g->tile_edges, g->inflight, g->nt_stream, g->use_graphs};
+    float best_ms = 1e30f;
+    for (int te : tiles)
+        for (int inf : infl)
+            for (int nt = 0; nt < 2; ++nt) {
+                bhpp_status rc = apply_setting(g, te, inf, nt, 1);
+                if (rc) return rc;
+                float ms = 0.f;
+                rc = g->dtype == BHPP_DTYPE_F64 ? time_setting<double, double>(g, ws, 2, &ms)
+                                                : time_setting<float, float>(g, ws, 2, &ms);
+                if (rc) return rc;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best[0] = te;
+                    best[1] = inf;
+                    best[2] = nt;
+                    best[3] = 1;
+                }
+            }
+    bhpp_status rc = apply_setting(g, best[0], best[1], best[2], best[3]);
+    for (int i = 0; i < 4; ++i) out_cfg[i] = best[i];
+    return rc;
+}
+
+bhpp_status set_launch_config(Graph* g, const int* cfg) {
+    if (cfg[0] < 64 || cfg[0] > 1 << 16 || (cfg[1] != 4 && cfg[1] != 8 && cfg[1] != 16)) return BHPP_INVALID_ARG;
+    return apply_setting(g, cfg[0], cfg[1], cfg[2] ? 1 : 0, cfg[3] ? 1 : 0);
 }
 
 }  // namespace bhpp

@@ -1,0 +1,73 @@
+"""Queue-fed query blocks (many uneven sources), graph replay and launch settings."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2312_06724_amd as bh
+    el = synth.chung_lu(20000, 40000, 300000, 2.1, "lognormal", 31)
+    src = synth.sample_sources(el, 200, "degree", 8)       # uneven: hubs and tail nodes
+    rng = np.random.default_rng(4)
+    eps = rng.choice([1e-4, 1e-5, 1e-6], size=src.size)
+    print(f"[gpu] graph 20k x 40k, 300k edges; {src.size} degree-proportional sources", flush=True)
+    G = bh.Graph.from_edges(el, dtype="f32")
+    g = oracle.Graph.from_edges(el)
+    return dict(bh=bh, el=el, src=src, eps=eps, G=G, g=g)
+
+
+def test_many_uneven_sources_against_exact(setup):
+    s = setup
+    out = s["G"].query_batch(s["src"], s["eps"], k=20)
+    S = out["scores"].double().cpu().numpy()
+    ex = s["g"].exact_beta_many(s["src"], 0.15, tail=1e-11, nthreads=16)
+    d = ex - S
+    tol = 1e-6
+    assert d.min() >= -tol, d.min()
+    assert np.all(d.max(axis=1) <= s["eps"] + tol), (d.max(axis=1) - s["eps"]).max()
+    ids = out["ids"].cpu().numpy()
+    Sf = out["scores"].cpu().numpy()
+    for i, u in enumerate(s["src"]):
+        rid, _ = oracle.topk_bruteforce(Sf[i], 20, exclude=int(u))
+        assert np.array_equal(ids[i], rid)
+    st = out["stats"]
+    steps = np.array([x["steps"] for x in st])
+    assert steps.min() > 0 and steps.max() > steps.min()    # uneven work per source
+
+
+def test_alone_and_in_mix_identical(setup):
+    """A query's result does not depend on the other queries sharing its block
+    (same block width: 64 columns), nor on its column or its position."""
+    s = setup
+    src, eps = s["src"], s["eps"]
+    a = s["G"].query_batch(src, eps, k=10)
+    perm = np.random.default_rng(9).permutation(src.size)
+    b = s["G"].query_batch(src[perm], eps[perm], k=10)
+    Sa, Sb = a["scores"].cpu().numpy(), b["scores"].cpu().numpy()
+    assert np.array_equal(Sa[perm], Sb)
+    assert np.array_equal(a["ids"].cpu().numpy()[perm], b["ids"].cpu().numpy())
+    # one query with 63 others vs with 63 different others
+    c = s["G"].query_batch(np.concatenate([src[:1], src[100:163]]), np.concatenate([eps[:1], eps[100:163]]))
+    assert np.array_equal(c["scores"][0].cpu().numpy(), Sa[0])
+
+
+def test_launch_settings_do_not_change_results(setup):
+    s = setup
+    G = s["G"]
+    src, eps = s["src"][:70], s["eps"][:70]
+    base = G.query_batch(src, eps)["scores"].cpu().numpy()
+    cfg0 = G.launch_config()
+    for te, inf, nt, gr in [(256, 4, 0, 0), (1024, 16, 1, 1), (512, 8, 0, 1)]:
+        G.set_launch_config(dict(tile_edges=te, inflight=inf, nt_stream=nt, graphs=gr))
+        S = G.query_batch(src, eps)["scores"].cpu().numpy()
+        assert np.abs(S - base).max() <= 1e-6
+    best = G.autotune()
+    assert best["tile_edges"] in (256, 512, 1024) and best["inflight"] in (4, 8, 16)
+    S = G.query_batch(src, eps)["scores"].cpu().numpy()
+    assert np.abs(S - base).max() <= 1e-6
+    G.set_launch_config(cfg0)
