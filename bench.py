@@ -65,6 +65,43 @@ def cpu_baseline(el, sources, wl, n_threads):
                        f"(Algorithms 1-5), lambda and eps_b precomputed; {dt:.1f} s wall")
 
 
+def run_large(bh, torch, np):
+    """1024 degree-proportional sources on the 5M x 10M, 100M-edge graph, one
+    timed pass through the queue-fed 64-column block (top-100 each)."""
+    import synth
+    wl = synth.LARGE
+    t0 = time.perf_counter()
+    el = wl.graph()
+    src = wl.sources(el)
+    log(f"large graph {wl.name} generated in {time.perf_counter() - t0:.1f}s")
+    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
+    del el
+    info = G.info()
+    cfg = G.autotune()
+    log(f"large: built in {info['build_ms']:.0f} ms, lambda={info['lambda']:.1f}, autotuned {cfg}")
+    G.query_batch(src[:64], wl.eps, k=wl.k, scores=False, stats=False)   # warm-up (graph capture)
+    torch.cuda.synchronize()
+    G.profile(True)
+    t0 = time.perf_counter()
+    out = G.query_batch(src, wl.eps, k=wl.k, scores=False, stats=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = G.profile_read()
+    G.profile(False)
+    steps = np.array([s["steps"] for s in out["stats"]])
+    dom = int(np.argmax(prof["ms"]))
+    avg = prof["ms"][dom] / max(1, prof["launches"][dom])
+    ach = prof["bytes"][dom] / max(1, prof["launches"][dom]) / (avg * 1e-3) / 1e9
+    res = dict(workload=wl.name, sources=int(src.size), source_sampling="degree-proportional",
+               queries_per_s=round(src.size / dt, 3), wall_s=round(dt, 3), launch_config=cfg,
+               sweeps_per_query=dict(min=int(steps.min()), median=float(np.median(steps)), max=int(steps.max())),
+               roofline=dict(kernel=["gather_a", "gather_b", "update", "select"][dom], avg_launch_ms=round(avg, 4),
+                             achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4)))
+    log(f"large: {res['queries_per_s']} q/s")
+    G.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +110,8 @@ def main():
     ap.add_argument("--single", type=int, default=8, help="sources timed one at a time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--large", action="store_true",
+                    help="also run the 100M-edge workload: 1024 degree-proportional sources in one queue-fed block")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device-to-device copy first (known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
@@ -155,6 +194,8 @@ def main():
                                      gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
                              for i, k in enumerate(["gather_a", "gather_b", "update", "select"])})
 
+    large = run_large(bh, torch, np) if args.large else None
+
     cpu = None
     if not args.no_cpu_baseline:
         n = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -180,6 +221,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "single_source_qps": round(single_qps, 3) if single_qps else None,
+        "large": large,
         "mean_sweeps_per_query": sweeps,
     }
     print(json.dumps(out), flush=True)
