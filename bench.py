@@ -185,10 +185,17 @@ def main():
     bytes_per_launch = prof["bytes"][dom] / max(1, prof["launches"][dom])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernel_id = ["gather_a", "gather_b", "update", "select"][dom]
+    # lower bound for comparison: adjacency read once, each dense row read or written once
+    nu1, nv1, C = el.n_u - info["isolated_u"], el.n_v - info["isolated_v"], 64
+    compulsory = [8 * el.n_e + 8 * nv1 + 4 * C * (nu1 + nv1), 8 * el.n_e + 8 * nu1 + 4 * C * (nu1 + nv1),
+                  8 * nu1 + 20 * C * nu1, el.n_u * (4 + 8 * C)][dom]
     roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=stored_traffic(kernel_id),
                     avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom],
                     algorithmic_bytes_per_launch=int(bytes_per_launch),
+                    compulsory=dict(bytes_per_launch=int(compulsory),
+                                    achieved=round(compulsory / (avg_ms * 1e-3) / 1e9, 1),
+                                    frac=round(compulsory / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
                     share_of_step=round(sum(prof["ms"]) / (dt * 1e3), 3),
                     kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
                                      gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
@@ -223,6 +230,7 @@ def main():
         "single_source_qps": round(single_qps, 3) if single_qps else None,
         "large": large,
         "mean_sweeps_per_query": sweeps,
+        "sweeps_per_step": prof["launches"][0] / args.steps,
     }
     print(json.dumps(out), flush=True)
 

@@ -736,19 +736,23 @@ static void prof_end(Graph* g, hipStream_t s, hipEvent_t* ev) {
     g->prof_ev.push_back(ev[1]);
 }
 
-// Algorithmic bytes of one launch: adjacency once, each dense vector once.
+// Algorithmic bytes of one launch, counted per unit of the method's own cost
+// measure (an edge visit, the increment of n_p in Algorithms 3 and 4):
+// a C-column gather visits every entry once per column; the entry's index and
+// weight are shared by the C columns and each column reads one value of the
+// neighbour's row, so an entry-column costs (4 + sizeof(W)) / C + sizeof(V)
+// bytes; every non-isolated output row is written once, with its two offsets.
+// Node passes count each value read or written once per column.
 // kind 0: gather A (rows V), 1: gather B (rows U), 2: update (rows U),
 // 3: select (rows U).
 template <typename VT, typename WT>
 static double launch_bytes(const Graph* g, int cols, int kind) {
     const double nnz = (double)g->ne;
     const double nu = (double)(g->nu - g->info.isolated_u), nv = (double)(g->nv - g->info.isolated_v);
-    const double adj = nnz * (4.0 + sizeof(WT));
     const double vt = sizeof(VT);
-    if (kind == 0)   // rp_v; read S once; write Q
-        return adj + nv * 8.0 + nu * cols * vt + nv * cols * vt;
-    if (kind == 1)   // rp_u; read Q once; write G
-        return adj + nu * 8.0 + nv * cols * vt + nu * cols * vt;
+    const double visits = nnz * ((4.0 + sizeof(WT)) + cols * vt);
+    if (kind == 0) return visits + nv * (8.0 + cols * vt);
+    if (kind == 1) return visits + nu * (8.0 + cols * vt);
     if (kind == 2)   // degrees, 1/ws_u; read Y, ACC, G; write Y, ACC
         return nu * 4.0 + nu * vt + 5.0 * nu * cols * vt;
     return (double)g->nu * (vt + 2.0 * cols * vt);   // select: 1/ws_u, read Y, write S
