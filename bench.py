@@ -102,6 +102,65 @@ def run_large(bh, torch, np):
     return res
 
 
+def run_serving(bh, G, el, wl, rates, duration, np):
+    """Continuous batching on the resident graph: Poisson arrivals at each rate
+    for `duration` seconds, degree-proportional sources, eps uniform on
+    {1e-5, 1e-6, 1e-7}, top-k per request. Latency = arrival to result."""
+    import synth
+    S = bh.Server(G, k=wl.k)
+    # warm-up: capture the sweep chunk once
+    warm = synth.sample_sources(el, 4, "degree", 90)
+    for i, u in enumerate(warm):
+        S.submit(int(u), 1e-5, -1 - i)
+    while S.info()["completed"] < warm.size:
+        S.poll()
+    out = []
+    for j, rate in enumerate(rates):
+        rng = np.random.default_rng(1000 + j)
+        n = max(1, int(rate * duration))
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        src = synth.sample_sources(el, n, "degree", 2000 + j)
+        eps = rng.choice([1e-5, 1e-6, 1e-7], size=n)
+        lat = np.full(n, np.nan)
+        sweeps0 = S.info()["sweeps"]
+        t0 = time.perf_counter()
+        i = done = 0
+        cap = duration + 6.0                      # stop admitting results after this (overload)
+        while done < n:
+            now = time.perf_counter() - t0
+            while i < n and arr[i] <= now:
+                S.submit(int(src[i]), float(eps[i]), i)
+                i += 1
+            res = S.poll()
+            t = time.perf_counter() - t0
+            for tag, _, _ in res:
+                lat[tag] = t - arr[tag]
+                done += 1
+            if t > cap:
+                break
+            if not res and i < n:
+                inf = S.info()
+                if inf["running"] == 0 and inf["queued"] == 0:
+                    time.sleep(max(0.0, arr[i] - (time.perf_counter() - t0)))
+        wall = time.perf_counter() - t0
+        ok = lat[~np.isnan(lat)]
+        inf = S.info()
+        out.append(dict(offered_qps=rate, requests=n, completed=int(ok.size), wall_s=round(wall, 2),
+                        served_qps=round(ok.size / wall, 2),
+                        p50_ms=round(float(np.percentile(ok, 50)) * 1e3, 1) if ok.size else None,
+                        p99_ms=round(float(np.percentile(ok, 99)) * 1e3, 1) if ok.size else None,
+                        backlog=int(n - ok.size), sweeps=int(inf["sweeps"] - sweeps0)))
+        log(f"serve {rate} q/s: {out[-1]}")
+        if ok.size < n:   # overloaded: drop what is left before the next rate
+            S.close()
+            S = bh.Server(G, k=wl.k)
+    res = dict(width=S.width, k=wl.k, resident_bytes=int(S.info()["resident_bytes"]),
+               eps_mix=[1e-5, 1e-6, 1e-7], source_sampling="degree-proportional", duration_s=duration,
+               rates=out)
+    S.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +171,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--large", action="store_true",
                     help="also run the 100M-edge workload: 1024 degree-proportional sources in one queue-fed block")
+    ap.add_argument("--serve", default="150,250,2000",
+                    help="Poisson arrival rates (q/s) for the serving run; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device-to-device copy first (known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
@@ -201,6 +263,9 @@ def main():
                                      gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
                              for i, k in enumerate(["gather_a", "gather_b", "update", "select"])})
 
+    rates = [float(x) for x in args.serve.split(",") if x.strip()]
+    serving = run_serving(bh, G, el, wl, rates, args.serve_seconds, np) if rates else None
+
     large = run_large(bh, torch, np) if args.large else None
 
     cpu = None
@@ -228,6 +293,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "single_source_qps": round(single_qps, 3) if single_qps else None,
+        "serving": serving,
         "large": large,
         "mean_sweeps_per_query": sweeps,
         "sweeps_per_step": prof["launches"][0] / args.steps,

@@ -219,11 +219,60 @@ bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[4], int64_t launches[4], 
  * hip_stream's device, keeps the fastest and writes it to config_out (host).
  * It synchronises hip_stream. bhpp_set_launch_config applies a setting saved
  * earlier (e.g. a cache keyed by the graph); bhpp_get_launch_config reads the
- * current one. Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE_ERROR.
+ * current one. Errors: INVALID_ARG (also while a server of this graph
+ * exists: its captured sweeps refer to the current tiles), OUT_OF_MEMORY,
+ * DEVICE_ERROR.
  */
 bhpp_status bhpp_autotune(bhpp_graph* g, void* hip_stream, int32_t config_out[4]);
 bhpp_status bhpp_set_launch_config(bhpp_graph* g, const int32_t config[4]);
 bhpp_status bhpp_get_launch_config(const bhpp_graph* g, int32_t config_out[4]);
+
+/* ------------------------------------------------------------------------
+ * Serving (continuous batching). Requests are the queries of Definition 1
+ * (source u, error bound eps) answered by Algorithm 5 and reduced to their
+ * top-k; they arrive one at a time and leave when done.
+ *
+ * A server owns a resident query block of `width` columns on its own HIP
+ * stream: width is the largest power of two <= max_width (1..64) whose
+ * device workspace fits in mem_budget_bytes (<= 0: no cap); the workspace of
+ * width 64 on a 1M x 2M graph is about 1.6 GB in FP32. Admission: a request
+ * enters the block when a column is free, at the next poll.
+ *
+ * bhpp_server_submit queues a request (host call, no device work; source in
+ * caller ids, eps > 0, tag is returned with the result). It may run on
+ * another thread while a poll runs.
+ * bhpp_server_poll admits queued requests into free columns, runs one chunk
+ * of sweeps (8) and synchronises, then writes the requests that finished:
+ * n_out entries of tags_out[n], ids_out[n][k] and vals_out[n][k] (HOST
+ * memory, values in the graph's dtype, order as bhpp_topk) and, if not NULL,
+ * stats_out[n]. capacity (entries the outputs hold) must be >= width. With
+ * nothing queued or running it returns at once with n_out = 0.
+ * A request's result does not depend on the other requests in the block.
+ * Destroy every server of a graph before freeing the graph.
+ * Errors: INVALID_ARG, OUT_OF_RANGE, ISOLATED_SOURCE (submit checks the
+ * source), OUT_OF_MEMORY (create: the budget does not fit width 1),
+ * NO_CONVERGENCE, DEVICE_ERROR.
+ * ---------------------------------------------------------------------- */
+typedef struct bhpp_server bhpp_server;
+
+typedef struct {
+    int32_t width;          /* columns of the resident block */
+    int32_t k;
+    int64_t queued;         /* submitted, not yet admitted */
+    int64_t running;        /* admitted, not finished */
+    int64_t completed;
+    int64_t sweeps;         /* sweeps run by this server */
+    double resident_bytes;  /* device bytes of its workspace */
+    double lambda;          /* Lemma 4 bound used by its PI-Push thresholds */
+} bhpp_server_summary;
+
+bhpp_status bhpp_server_create(bhpp_graph* g, int32_t max_width, double mem_budget_bytes, double alpha,
+                               int32_t k, int32_t exclude_self, bhpp_server** out);
+bhpp_status bhpp_server_submit(bhpp_server* s, int32_t source, double eps, int64_t tag);
+bhpp_status bhpp_server_poll(bhpp_server* s, int32_t capacity, int64_t* tags_out, int32_t* ids_out,
+                             void* vals_out, bhpp_query_stats* stats_out, int32_t* n_out);
+bhpp_status bhpp_server_info(const bhpp_server* s, bhpp_server_summary* out);
+void bhpp_server_destroy(bhpp_server* s);
 
 /* Free the handle and all device memory it owns (NULL is ignored). The caller
    must make sure no work using it is still running. */

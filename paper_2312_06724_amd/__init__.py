@@ -30,7 +30,9 @@ BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER = 1, 2
 # names exported by include/bhpp.h
 EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
             "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_autotune",
-            "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_free_graph", "bhpp_status_string"]
+            "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_server_create", "bhpp_server_submit",
+            "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_free_graph",
+            "bhpp_status_string"]
 
 
 class BhppError(RuntimeError):
@@ -63,6 +65,17 @@ class GraphSummary(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("lambda_", ctypes.c_double), ("mu", ctypes.c_double),
                 ("eps_b_ratio", ctypes.c_double), ("ws_u_max", ctypes.c_double),
                 ("ws_u_min", ctypes.c_double), ("build_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["lambda"] = d.pop("lambda_")
+        return d
+
+
+class ServerSummary(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("k", ctypes.c_int32), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("completed", ctypes.c_int64), ("sweeps", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_double), ("lambda_", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -105,6 +118,16 @@ def load_library():
     L.bhpp_set_launch_config.argtypes = [P, P]
     L.bhpp_get_launch_config.restype = I32
     L.bhpp_get_launch_config.argtypes = [P, P]
+    L.bhpp_server_create.restype = I32
+    L.bhpp_server_create.argtypes = [P, I32, D, D, I32, I32, ctypes.POINTER(P)]
+    L.bhpp_server_submit.restype = I32
+    L.bhpp_server_submit.argtypes = [P, I32, D, I64]
+    L.bhpp_server_poll.restype = I32
+    L.bhpp_server_poll.argtypes = [P, I32, P, P, P, P, P]
+    L.bhpp_server_info.restype = I32
+    L.bhpp_server_info.argtypes = [P, ctypes.POINTER(ServerSummary)]
+    L.bhpp_server_destroy.restype = None
+    L.bhpp_server_destroy.argtypes = [P]
     L.bhpp_free_graph.restype = None
     L.bhpp_free_graph.argtypes = [P]
     L.bhpp_status_string.restype = ctypes.c_char_p
@@ -277,6 +300,60 @@ class Graph:
         b = (ctypes.c_double * 4)()
         _check(load_library().bhpp_profile_read(self._h, ms, n, b), "bhpp_profile_read")
         return dict(ms=list(ms), launches=list(n), bytes=list(b))
+
+
+class Server:
+    """A resident query block fed by a request queue (bhpp_server_*):
+    continuous batching of top-k queries on one graph."""
+
+    def __init__(self, graph, k=100, max_width=64, mem_budget_bytes=0.0, alpha=None, exclude_self=True):
+        _torch()
+        L = load_library()
+        h = ctypes.c_void_p()
+        rc = L.bhpp_server_create(graph._h, int(max_width), float(mem_budget_bytes), alpha or graph.alpha, int(k),
+                                  1 if exclude_self else 0, ctypes.byref(h))
+        _check(rc, "bhpp_server_create")
+        self._h = h
+        self.graph = graph          # keeps the graph alive while the server exists
+        self.k = int(k)
+        self.width = self.info()["width"]
+        self._vdt = np.float64 if graph.dtype == "f64" else np.float32
+        self._tags = np.empty(self.width, dtype=np.int64)
+        self._ids = np.empty((self.width, self.k), dtype=np.int32)
+        self._vals = np.empty((self.width, self.k), dtype=self._vdt)
+        self._st = (QueryStats * self.width)()
+
+    def submit(self, source, eps, tag):
+        _check(load_library().bhpp_server_submit(self._h, int(source), float(eps), int(tag)), "bhpp_server_submit")
+
+    def poll(self, stats=False):
+        """Run one chunk; returns [(tag, ids, vals[, stats])] of the finished requests."""
+        n = ctypes.c_int32()
+        rc = load_library().bhpp_server_poll(self._h, self.width, self._tags.ctypes.data, self._ids.ctypes.data,
+                                             self._vals.ctypes.data, ctypes.cast(self._st, ctypes.c_void_p),
+                                             ctypes.byref(n))
+        _check(rc, "bhpp_server_poll")
+        out = []
+        for j in range(n.value):
+            r = (int(self._tags[j]), self._ids[j].copy(), self._vals[j].copy())
+            out.append(r + (self._st[j].as_dict(),) if stats else r)
+        return out
+
+    def info(self):
+        s = ServerSummary()
+        _check(load_library().bhpp_server_info(self._h, ctypes.byref(s)), "bhpp_server_info")
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bhpp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def topk(scores, k, exclude=None):

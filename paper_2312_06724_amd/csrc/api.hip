@@ -13,6 +13,12 @@ struct bhpp_graph {
     Graph* g;
 };
 
+struct bhpp_server {
+    bhpp_graph* h;
+    bhpp::Server* sv;
+    int32_t width;
+};
+
 namespace {
 
 hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -222,6 +228,7 @@ bhpp_status bhpp_autotune(bhpp_graph* h, void* hip_stream, int32_t config_out[4]
     if (g->sticky_error) return BHPP_DEVICE_ERROR;
     try {
         std::lock_guard<std::mutex> lock(g->mu);
+        if (g->n_servers > 0) return BHPP_INVALID_ARG;
         int cfg[4];
         bhpp_status rc = bhpp::autotune(g, stream_of(hip_stream), cfg);
         if (rc == BHPP_OK)
@@ -237,6 +244,7 @@ bhpp_status bhpp_set_launch_config(bhpp_graph* h, const int32_t config[4]) {
     Graph* g = h->g;
     try {
         std::lock_guard<std::mutex> lock(g->mu);
+        if (g->n_servers > 0) return BHPP_INVALID_ARG;
         int cfg[4] = {config[0], config[1], config[2], config[3]};
         return sticky(g, bhpp::set_launch_config(g, cfg));
     } catch (...) {
@@ -252,6 +260,80 @@ bhpp_status bhpp_get_launch_config(const bhpp_graph* h, int32_t config_out[4]) {
     config_out[2] = g->nt_stream;
     config_out[3] = g->use_graphs;
     return BHPP_OK;
+}
+
+bhpp_status bhpp_server_create(bhpp_graph* h, int32_t max_width, double mem_budget_bytes, double alpha, int32_t k,
+                               int32_t exclude_self, bhpp_server** out) {
+    if (!out) return BHPP_INVALID_ARG;
+    *out = nullptr;
+    if (!h || !h->g || !valid_alpha(alpha) || max_width < 1 || max_width > 64) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    if (k < 1 || k > bhpp::kTopkTmpK || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
+    if (!(mem_budget_bytes <= 0.0 || std::isfinite(mem_budget_bytes))) return BHPP_INVALID_ARG;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        double lam = 0.0;
+        bhpp_status rc = lambda_for(g, alpha, nullptr, &lam);
+        if (rc) return sticky(g, rc);
+        bhpp::Server* sv = nullptr;
+        rc = bhpp::server_create(g, max_width, mem_budget_bytes, alpha, lam, k, exclude_self ? 1 : 0, &sv);
+        if (rc) return sticky(g, rc);
+        bhpp_server* s = new (std::nothrow) bhpp_server{h, sv, 0};
+        if (!s) {
+            bhpp::server_destroy(sv);
+            return BHPP_OUT_OF_MEMORY;
+        }
+        bhpp_server_summary i;
+        bhpp::server_info(sv, &i);
+        s->width = i.width;
+        *out = s;
+        return BHPP_OK;
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_server_submit(bhpp_server* s, int32_t source, double eps, int64_t tag) {
+    if (!s || !s->sv || !valid_eps(eps)) return BHPP_INVALID_ARG;
+    Graph* g = s->h->g;
+    if (source < 0 || source >= g->nu) return BHPP_OUT_OF_RANGE;
+    if (!(g->h_ws_u[source] > 0.0)) return BHPP_ISOLATED_SOURCE;
+    try {
+        return bhpp::server_submit(s->sv, source, eps, tag);
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_server_poll(bhpp_server* s, int32_t capacity, int64_t* tags_out, int32_t* ids_out, void* vals_out,
+                             bhpp_query_stats* stats_out, int32_t* n_out) {
+    if (!s || !s->sv || !n_out) return BHPP_INVALID_ARG;
+    *n_out = 0;
+    if (capacity < s->width || !tags_out || !ids_out || !vals_out) return BHPP_INVALID_ARG;
+    Graph* g = s->h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        return sticky(g, bhpp::server_poll(s->sv, tags_out, ids_out, vals_out, stats_out, n_out));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_server_info(const bhpp_server* s, bhpp_server_summary* out) {
+    if (!s || !s->sv || !out) return BHPP_INVALID_ARG;
+    bhpp::server_info(s->sv, out);
+    return BHPP_OK;
+}
+
+void bhpp_server_destroy(bhpp_server* s) {
+    if (!s) return;
+    if (s->sv) {
+        std::lock_guard<std::mutex> lock(s->h->g->mu);
+        bhpp::server_destroy(s->sv);
+    }
+    delete s;
 }
 
 void bhpp_free_graph(bhpp_graph* h) {

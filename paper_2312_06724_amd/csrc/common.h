@@ -155,6 +155,7 @@ struct Graph {
     int nt_stream = 0;
     int use_graphs = 1;
     bool sticky_error = false;
+    int n_servers = 0;               // live servers hold captured graphs of the tiles
     // profiling of the sweep kernels
     bool prof_on = false;
     double prof_ms[4] = {0, 0, 0, 0};
@@ -183,6 +184,15 @@ bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const doubl
 bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
                       int32_t dtype, int32_t* ids_out, void* vals_out, hipStream_t s);
 bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s);
+bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s);
+size_t workspace_bytes(const Graph* g, int cols);
+struct Server;
+bhpp_status server_create(Graph* g, int max_width, double mem_budget, double alpha, double lambda, int k, int excl,
+                          Server** out);
+bhpp_status server_submit(Server* sv, int32_t src, double eps, int64_t tag);
+bhpp_status server_poll(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st, int32_t* n_out);
+void server_info(Server* sv, bhpp_server_summary* out);
+void server_destroy(Server* sv);
 bhpp_status set_launch_config(Graph* g, const int* cfg);
 bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts);
 void free_workspace(Workspace& w);

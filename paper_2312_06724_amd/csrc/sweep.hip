@@ -31,6 +31,9 @@
 #include <cstdlib>
 #include <cstring>
 
+#include <deque>
+#include <new>
+
 #include "common.h"
 
 namespace bhpp {
@@ -1086,8 +1089,17 @@ void free_workspace(Workspace& w) {
 // as the row-major score rows of finished queries between sweeps. Blocks of
 // fewer columns reuse the buffers with a smaller row stride; rows of isolated
 // nodes are never read (S and the update skip them, the extract writes 0).
-bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s) {
-    Workspace& w = g->ws;
+size_t workspace_bytes(const Graph* g, int cols) {
+    const Geometry G = geometry(g);
+    const size_t e = (size_t)g->elem, c = (size_t)cols;
+    return (size_t)g->nu * c * e * 4 + (size_t)g->nv * c * e + (size_t)g->tiles_v.n_slots * c * (e + 4) +
+           (size_t)g->tiles_u.n_slots * c * e + (size_t)kNumRed * c * G.n_part * 8 + sizeof(ColState) * c +
+           (size_t)kMaxCols * kTopkTmpK * (4 + e) + 4096;
+}
+
+bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s) { return ensure_workspace(g, g->ws, cols, s); }
+
+bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
     const Geometry G = geometry(g);
     if (w.cols >= cols && w.n_part >= G.n_part) return BHPP_OK;
     free_workspace(w);
@@ -1324,6 +1336,209 @@ bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg) {
 bhpp_status set_launch_config(Graph* g, const int* cfg) {
     if (cfg[0] < 64 || cfg[0] > 1 << 16 || (cfg[1] != 4 && cfg[1] != 8 && cfg[1] != 16)) return BHPP_INVALID_ARG;
     return apply_setting(g, cfg[0], cfg[1], cfg[2] ? 1 : 0, cfg[3] ? 1 : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Serving: a resident query block fed by a request queue (continuous
+// batching). Each poll admits waiting requests into free columns, runs one
+// chunk of sweeps, and returns the top-k of every request that finished. The
+// block width is fixed at creation by the memory budget; a request is
+// admitted when a column is free. Columns are independent, so a request's
+// result does not depend on the requests it shares the block with.
+// ---------------------------------------------------------------------------
+struct Server {
+    Graph* g = nullptr;
+    Workspace ws;
+    int cols = 0, k = 0, excl = 0;
+    double alpha = 0.0, lambda = 0.0;
+    hipStream_t s = nullptr;
+    std::mutex qmu;                       // guards the queue (submit may run beside poll)
+    struct Req { int32_t src; double eps; int64_t tag; };
+    std::deque<Req> queue;
+    std::vector<ColState> hs;
+    std::vector<int64_t> tag;
+    std::vector<int32_t> src;
+    int32_t* h_ids = nullptr;             // pinned [cols][k]
+    void* h_vals = nullptr;
+    int64_t completed = 0, sweeps = 0, since_done = 0;
+    bool dirty = false;                   // host states changed since the last upload
+};
+
+static bhpp_status server_upload(Server* sv) {
+    int32_t act = 0;
+    for (const ColState& c : sv->hs) act += c.mode != MODE_DONE ? 1 : 0;
+    sv->ws.h_active[2] = act;
+    BHPP_HIP(hipMemcpyAsync(sv->ws.st, sv->hs.data(), sizeof(ColState) * sv->cols, hipMemcpyHostToDevice, sv->s));
+    BHPP_HIP(hipMemcpyAsync(sv->ws.n_active, &sv->ws.h_active[2], sizeof(int32_t), hipMemcpyHostToDevice, sv->s));
+    return BHPP_OK;
+}
+
+template <int COLS, typename VT, typename WT>
+static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st,
+                                    int32_t* n_out) {
+    Graph* g = sv->g;
+    Workspace& w = sv->ws;
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    const Geometry G = geometry(g);
+    hipStream_t s = sv->s;
+    *n_out = 0;
+    bool dirty = sv->dirty;
+    {
+        std::lock_guard<std::mutex> lock(sv->qmu);
+        for (int c = 0; c < COLS && !sv->queue.empty(); ++c) {
+            if (sv->hs[c].qid >= 0) continue;
+            const Server::Req r = sv->queue.front();
+            sv->queue.pop_front();
+            init_state(sv->hs[c], sv->alpha, g->h_ws_u[r.src], r.eps, g->info.eps_b_ratio, sv->lambda, g->ne);
+            sv->hs[c].fresh = 1;
+            sv->hs[c].src_row = g->h_perm_u[r.src];
+            sv->hs[c].qid = c;
+            sv->tag[c] = r.tag;
+            sv->src[c] = r.src;
+            dirty = true;
+        }
+    }
+    if (dirty) {
+        bhpp_status rc = server_upload(sv);
+        if (rc) return rc;
+        sv->dirty = false;
+    }
+    int live = 0;
+    for (int c = 0; c < COLS; ++c) live += sv->hs[c].qid >= 0 ? 1 : 0;
+    if (live == 0) return BHPP_OK;
+    bhpp_status rc = launch_chunk<COLS, VT, WT>(g, b, G, s, &w.chunk_exec[log2i(COLS)]);
+    if (rc) return rc;
+    sv->sweeps += kStepsPerChunk;
+    sv->since_done += kStepsPerChunk;
+    BHPP_HIP(hipStreamSynchronize(s));
+    BHPP_HIP(hipMemcpy(sv->hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost));
+    std::vector<int32_t> cols, ex;
+    for (int c = 0; c < COLS; ++c)
+        if (sv->hs[c].qid >= 0 && sv->hs[c].mode == MODE_DONE) {
+            cols.push_back(c);
+            ex.push_back(sv->excl ? sv->src[c] : -1);
+        }
+    const int m = (int)cols.size();
+    if (m == 0) return sv->since_done > kMaxSteps ? BHPP_NO_CONVERGENCE : BHPP_OK;
+    sv->since_done = 0;
+    const size_t nu = (size_t)g->nu, e = (size_t)g->elem, kk = (size_t)sv->k;
+    int32_t* d_cols = w.ex_tmp;
+    int32_t* d_ex = w.ex_tmp + kMaxCols;
+    BHPP_HIP(hipMemcpyAsync(d_cols, cols.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(d_ex, ex.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+    VT* rows = as<VT>(w.scores);
+    hipLaunchKernelGGL((k_extract<COLS, VT>), dim3((g->nu + 63) / 64), dim3(256), 0, s, as<VT>(w.ACC), g->perm_u,
+                       g->deg_u, g->nu, d_cols, m, rows);
+    BHPP_HIP(hipGetLastError());
+    rc = topk_rows(rows, m, g->nu, sv->k, d_ex, g->dtype, w.ids_tmp, w.vals_tmp, s);
+    if (rc) return rc;
+    BHPP_HIP(hipMemcpyAsync(sv->h_ids, w.ids_tmp, sizeof(int32_t) * kk * m, hipMemcpyDeviceToHost, s));
+    BHPP_HIP(hipMemcpyAsync(sv->h_vals, w.vals_tmp, e * kk * m, hipMemcpyDeviceToHost, s));
+    BHPP_HIP(hipStreamSynchronize(s));
+    (void)nu;
+    for (int j = 0; j < m; ++j) {
+        const int c = cols[j];
+        tags[j] = sv->tag[c];
+        memcpy(ids + (size_t)j * kk, sv->h_ids + (size_t)j * kk, sizeof(int32_t) * kk);
+        memcpy((char*)vals + (size_t)j * kk * e, (char*)sv->h_vals + (size_t)j * kk * e, e * kk);
+        if (st) fill_stats(sv->hs[c], st[j]);
+        sv->hs[c].qid = -1;
+    }
+    sv->dirty = true;   // freed columns: the device copy still names their request
+    sv->completed += m;
+    *n_out = m;
+    return BHPP_OK;
+}
+
+template <typename VT, typename WT>
+static bhpp_status server_poll_dispatch(Server* sv, int64_t* t, int32_t* i, void* v, bhpp_query_stats* st,
+                                        int32_t* n) {
+    switch (sv->cols) {
+        case 1: return server_poll_impl<1, VT, WT>(sv, t, i, v, st, n);
+        case 2: return server_poll_impl<2, VT, WT>(sv, t, i, v, st, n);
+        case 4: return server_poll_impl<4, VT, WT>(sv, t, i, v, st, n);
+        case 8: return server_poll_impl<8, VT, WT>(sv, t, i, v, st, n);
+        case 16: return server_poll_impl<16, VT, WT>(sv, t, i, v, st, n);
+        case 32: return server_poll_impl<32, VT, WT>(sv, t, i, v, st, n);
+        case 64: return server_poll_impl<64, VT, WT>(sv, t, i, v, st, n);
+        default: return BHPP_INVALID_ARG;
+    }
+}
+
+void server_destroy(Server* sv) {
+    if (!sv) return;
+    if (sv->s) hipStreamSynchronize(sv->s);
+    free_workspace(sv->ws);
+    if (sv->h_ids) hipHostFree(sv->h_ids);
+    if (sv->h_vals) hipHostFree(sv->h_vals);
+    if (sv->s) hipStreamDestroy(sv->s);
+    if (sv->g) sv->g->n_servers -= 1;
+    delete sv;
+}
+
+bhpp_status server_create(Graph* g, int max_width, double mem_budget, double alpha, double lambda, int k, int excl,
+                          Server** out) {
+    int cols = 1;
+    while (cols * 2 <= max_width && cols * 2 <= kMaxCols) cols *= 2;
+    if (mem_budget > 0.0)
+        while (cols > 1 && (double)workspace_bytes(g, cols) > mem_budget) cols /= 2;
+    if (mem_budget > 0.0 && (double)workspace_bytes(g, cols) > mem_budget) return BHPP_OUT_OF_MEMORY;
+    Server* sv = new (std::nothrow) Server();
+    if (!sv) return BHPP_OUT_OF_MEMORY;
+    sv->g = g;
+    g->n_servers += 1;
+    sv->cols = cols;
+    sv->k = k;
+    sv->excl = excl;
+    sv->alpha = alpha;
+    sv->lambda = lambda;
+    sv->hs.resize(cols);
+    for (ColState& c : sv->hs) done_state(c);
+    sv->tag.assign(cols, -1);
+    sv->src.assign(cols, -1);
+    bhpp_status rc = BHPP_OK;
+    if (hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    if (rc == BHPP_OK) rc = ensure_workspace(g, sv->ws, cols, sv->s);
+    if (rc == BHPP_OK && (hipHostMalloc((void**)&sv->h_ids, sizeof(int32_t) * (size_t)cols * k) != hipSuccess ||
+                          hipHostMalloc(&sv->h_vals, (size_t)g->elem * cols * k) != hipSuccess))
+        rc = BHPP_OUT_OF_MEMORY;
+    if (rc == BHPP_OK) rc = server_upload(sv);
+    if (rc == BHPP_OK && hipStreamSynchronize(sv->s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    if (rc) {
+        (void)hipGetLastError();
+        server_destroy(sv);
+        return rc;
+    }
+    *out = sv;
+    return BHPP_OK;
+}
+
+bhpp_status server_submit(Server* sv, int32_t src, double eps, int64_t tag) {
+    std::lock_guard<std::mutex> lock(sv->qmu);
+    sv->queue.push_back(Server::Req{src, eps, tag});
+    return BHPP_OK;
+}
+
+bhpp_status server_poll(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st, int32_t* n_out) {
+    if (sv->g->dtype == BHPP_DTYPE_F64) return server_poll_dispatch<double, double>(sv, tags, ids, vals, st, n_out);
+    return server_poll_dispatch<float, float>(sv, tags, ids, vals, st, n_out);
+}
+
+void server_info(Server* sv, bhpp_server_summary* o) {
+    memset(o, 0, sizeof(*o));
+    o->width = sv->cols;
+    o->k = sv->k;
+    {
+        std::lock_guard<std::mutex> lock(sv->qmu);
+        o->queued = (int64_t)sv->queue.size();
+    }
+    int64_t run = 0;
+    for (const ColState& c : sv->hs) run += c.qid >= 0 ? 1 : 0;
+    o->running = run;
+    o->completed = sv->completed;
+    o->sweeps = sv->sweeps;
+    o->resident_bytes = (double)sv->ws.bytes;
+    o->lambda = sv->lambda;
 }
 
 }  // namespace bhpp

@@ -50,3 +50,10 @@ def test_argument_errors_need_no_device():
     assert L.bhpp_topk(None, 1, 10, 0, None, 0, None, None, None) == -1       # k < 1
     assert L.bhpp_topk(None, 1, 10, 11, None, 0, None, None, None) == -1      # k > n
     assert L.bhpp_query_batch(None, 1, None, None, 0.15, 1e-6, None, 0, 0, None, None, None, None) == -1
+    srv = ctypes.c_void_p()
+    assert L.bhpp_server_create(None, 64, 0.0, 0.15, 100, 1, ctypes.byref(srv)) == -1   # no graph
+    assert L.bhpp_server_submit(None, 0, 1e-6, 0) == -1
+    n = ctypes.c_int32(5)
+    assert L.bhpp_server_poll(None, 64, None, None, None, None, ctypes.byref(n)) == -1
+    assert L.bhpp_server_info(None, None) == -1
+    L.bhpp_server_destroy(None)                                    # ignored
