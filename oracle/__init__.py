@@ -57,6 +57,14 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class WarmInfo(ctypes.Structure):
+    _fields_ = [("res_l1", ctypes.c_double), ("res_max", ctypes.c_double), ("fell_back", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(res_l1=self.res_l1, res_max=self.res_max, fell_back=self.fell_back)
+
+
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
@@ -94,6 +102,10 @@ def _load():
         L.orc_lambda.argtypes = [P, D, I32, ctypes.POINTER(D), ctypes.POINTER(D)]
         L.orc_approx_bhpp.argtypes = [P, I32, D, D, D, D, P, P, P, ctypes.POINTER(Stats), TRACE_FN, P]
         L.orc_approx_bhpp_many.argtypes = [P, I32, P, D, D, D, D, P, P, I32]
+        L.orc_warm_residue.argtypes = [P, I32, D, P, P]
+        L.orc_approx_bhpp_warm.argtypes = [P, I32, D, D, D, D, P, P, ctypes.POINTER(Stats),
+                                           ctypes.POINTER(WarmInfo)]
+        L.orc_approx_bhpp_warm_many.argtypes = [P, I32, P, D, D, D, D, P, P, P, P, I32]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_t.restype = I32
         L.orc_t.argtypes = [D, D, D]
@@ -239,6 +251,30 @@ class Graph:
                                             _ptr(beta), ctypes.cast(st, ctypes.c_void_p),
                                             int(nthreads)))
         return beta, [st[i].as_dict() for i in range(src.size)]
+
+    def warm_residue(self, u, alpha, y):
+        """Signed residue of a warm start y (estimates of pi(x, u)):
+        r = e_u - (y - (1-alpha) P y) / alpha (Lemma 1 holds for it)."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        r = np.empty(self.n_u)
+        _check(_load().orc_warm_residue(self._h, int(u), alpha, _ptr(y), _ptr(r)))
+        return r
+
+    def approx_bhpp_warm_many(self, sources, alpha, eps, y0, eps_b=None, lam=None, nthreads=0):
+        """Approx-BHPP from warm starts y0[i] (backward coordinates) with signed
+        residues; falls back to the cold start when the start is no better.
+        Returns (beta, stats, warm infos)."""
+        eps_b = self.eps_b(eps) if eps_b is None else eps_b
+        lam = self.lambda_(alpha) if lam is None else lam
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        y0 = np.ascontiguousarray(y0, dtype=np.float64).reshape(src.size, self.n_u)
+        beta = np.empty((src.size, self.n_u))
+        st = (Stats * max(1, src.size))()
+        wi = (WarmInfo * max(1, src.size))()
+        _check(_load().orc_approx_bhpp_warm_many(self._h, src.size, _ptr(src), alpha, eps, eps_b, lam, _ptr(y0),
+                                                 _ptr(beta), ctypes.cast(st, ctypes.c_void_p),
+                                                 ctypes.cast(wi, ctypes.c_void_p), int(nthreads)))
+        return beta, [st[i].as_dict() for i in range(src.size)], [wi[i].as_dict() for i in range(src.size)]
 
 
 def max_threads() -> int:

@@ -528,6 +528,225 @@ int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, dou
     return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Warm start (not in the paper; it rests on Lemma 1 and Lemma 3).
+ *
+ * Lemma 1's invariant pi(., u) = pi_b + Pi r (Pi = alpha (I - (1-alpha) P)^-1
+ * applied to the column vector r) holds for ANY start pi_b = y if the residue
+ * is the signed r = e_u - (y - (1-alpha) P y) / alpha, since
+ * Pi (I - (1-alpha) P) = alpha I; every push keeps it, whatever the signs.
+ * With signed residues every test of Algorithms 3 and 4 uses |r|, and a V
+ * node is pushed when its residue is non-zero.
+ *
+ * Error bound (two-sided). With pi_b* the backward estimate when SS-Push
+ * returns and r* its residue, |pi(x,u) - pi_b*(x)| = |(Pi r*)(x)| <= max|r*|
+ * (rows of Pi sum to 1, Pi >= 0), and max|r*| <= eps_b or sum|r*| <= eps_b
+ * when SS-Push returns. PI-Push then continues on (pi_b, r); by Lemma 3 the
+ * forward value is pi(u,x) = ws(x)/ws(u) pi_b(x) + (r_f Pi)(x) with
+ * r_f = ws/ws(u) r, whose remainder after PowerIteration with t sweeps is at
+ * most (1-alpha)^(t+1) sum|r_f| <= eps_f in L1, and at most
+ * max|r_f| lambda <= eps_f when PI-Push returns (Lemma 4). The combine
+ * therefore takes pi_b* (the backward estimate as SS-Push returned it):
+ * beta' = pi_f + pi_b*, |beta - beta'| <= eps_b + eps_f = eps.
+ *
+ * Fallback: if the start is no better than a cold start
+ * (sum|r_f| >= 1 or max|r| >= 1), the query runs cold (orc_approx_bhpp).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    double res_l1;      /* sum_x ws(x)/ws(u) |r(x)| of the warm start */
+    double res_max;     /* max_x |r(x)| */
+    int32_t fell_back;  /* 1: ran cold */
+    int32_t pad;
+} orc_warm_info;
+
+/* (P y)(x) = sum_v w(x,v)/ws(x) sum_x' w(x',v)/ws(v) y(x') (Eq. (pmatrix)), into out. */
+static void apply_P(const orc_graph* g, const double* y, double* yv, double* out) {
+    for (int32_t v = 0; v < g->nv; ++v) {
+        double s = 0.0;
+        for (int64_t q = g->rp_v[v]; q < g->rp_v[v + 1]; ++q) s += g->w_v[q] * y[g->ci_v[q]];
+        yv[v] = g->ws_v[v] > 0.0 ? s / g->ws_v[v] : 0.0;
+    }
+    for (int32_t x = 0; x < g->nu; ++x) {
+        double s = 0.0;
+        for (int64_t q = g->rp_u[x]; q < g->rp_u[x + 1]; ++q) s += g->w_u[q] * yv[g->ci_u[q]];
+        out[x] = g->ws_u[x] > 0.0 ? s / g->ws_u[x] : 0.0;
+    }
+}
+
+/* Algorithm 2's loop body with signed residues: push x if |r(x)| > thr(x),
+ * then every v with r(v) != 0. Returns n_p. */
+static double push_iteration_signed(const orc_graph* g, orc_work* w, double alpha) {
+    double np = 0.0;
+    for (int32_t x = 0; x < g->nu; ++x) {
+        double rx = w->r[x];
+        if (!(fabs(rx) > w->thr[x])) continue;
+        for (int64_t q = g->rp_u[x]; q < g->rp_u[x + 1]; ++q) {
+            int32_t v = g->ci_u[q];
+            w->rv[v] += (1.0 - alpha) * g->w_u[q] / g->ws_v[v] * rx;
+        }
+        w->pib[x] += alpha * rx;
+        w->r[x] = 0.0;
+        np += (double)(g->rp_u[x + 1] - g->rp_u[x]);
+    }
+    for (int32_t v = 0; v < g->nv; ++v) {
+        double rv = w->rv[v];
+        if (rv == 0.0) continue;
+        for (int64_t q = g->rp_v[v]; q < g->rp_v[v + 1]; ++q) {
+            int32_t y = g->ci_v[q];
+            w->r[y] += g->w_v[q] / g->ws_u[y] * rv;
+        }
+        w->rv[v] = 0.0;
+        np += (double)(g->rp_v[v + 1] - g->rp_v[v]);
+    }
+    return np;
+}
+
+/* Warm-start residue of a start y (backward coordinates: y(x) estimates
+ * pi(x,u)): r = e_u - (y - (1-alpha) P y)/alpha. */
+int orc_warm_residue(const orc_graph* g, int32_t u, double alpha, const double* y, double* r_out) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    double* yv = (double*)malloc(sizeof(double) * (size_t)g->nv);
+    double* py = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    if (!yv || !py) { free(yv); free(py); return ORC_ENOMEM; }
+    apply_P(g, y, yv, py);
+    for (int32_t x = 0; x < g->nu; ++x)
+        r_out[x] = (x == u ? 1.0 : 0.0) - (y[x] - (1.0 - alpha) * py[x]) / alpha;
+    free(yv); free(py);
+    return ORC_OK;
+}
+
+int orc_approx_bhpp_warm(const orc_graph* g, int32_t u, double alpha, double eps, double eps_b, double lambda,
+                         const double* y0, double* beta, orc_stats* st, orc_warm_info* wi) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    if (!(alpha > 0.0 && alpha < 1.0) || !(eps > 0.0) || !(eps_b > 0.0 && eps_b < eps) || !(lambda > 0.0))
+        return ORC_EINVAL;
+    if (g->ws_u[u] == 0.0) return ORC_EISOLATED;
+    const int32_t nu = g->nu;
+    const double wsu = g->ws_u[u];
+    orc_warm_info info;
+    memset(&info, 0, sizeof(info));
+    orc_work w;
+    if (work_alloc(&w, g)) return ORC_ENOMEM;
+    int rc = orc_warm_residue(g, u, alpha, y0, w.r);
+    if (rc) { work_free(&w); return rc; }
+    for (int32_t x = 0; x < nu; ++x) {
+        if (g->ws_u[x] == 0.0) continue;
+        info.res_l1 += g->ws_u[x] / wsu * fabs(w.r[x]);
+        if (fabs(w.r[x]) > info.res_max) info.res_max = fabs(w.r[x]);
+    }
+    if (!(info.res_l1 < 1.0 && info.res_max < 1.0)) {
+        info.fell_back = 1;
+        work_free(&w);
+        if (wi) *wi = info;
+        return orc_approx_bhpp(g, u, alpha, eps, eps_b, lambda, beta, NULL, NULL, st, NULL, NULL);
+    }
+    for (int32_t x = 0; x < nu; ++x) w.pib[x] = y0[x];
+    orc_stats s;
+    memset(&s, 0, sizeof(s));
+    const double E2 = 2.0 * (double)g->ne;
+
+    /* ---- Algorithm 3 with |r| ---- */
+    for (int32_t x = 0; x < nu; ++x) w.thr[x] = eps_b;
+    double np = 0.0;
+    int ss_done = 0;
+    int32_t iters = 0;
+    for (;;) {
+        if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
+        np += push_iteration_signed(g, &w, alpha);
+        ++s.ss_sel_iters;
+        double rmax = 0.0, rsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) { double a = fabs(w.r[x]); if (a > rmax) rmax = a; rsum += a; }
+        if (rmax <= eps_b || rsum <= eps_b) { ss_done = 1; break; }
+        if (np >= E2 * log_base(alpha, 1.0 / rsum)) break;
+    }
+    s.np_ss = np;
+    if (!ss_done) {
+        s.ss_switched = 1;
+        for (int32_t x = 0; x < nu; ++x) w.thr[x] = 0.0;
+        for (;;) {
+            double rmax = 0.0, rsum = 0.0;
+            for (int32_t x = 0; x < nu; ++x) { double a = fabs(w.r[x]); if (a > rmax) rmax = a; rsum += a; }
+            if (!(rmax > eps_b && rsum > eps_b)) break;
+            if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
+            s.np_ss += push_iteration_signed(g, &w, alpha);
+            ++s.ss_seq_iters;
+        }
+    }
+    double* pib_ss = (double*)malloc(sizeof(double) * (size_t)nu);
+    if (!pib_ss) { work_free(&w); return ORC_ENOMEM; }
+    memcpy(pib_ss, w.pib, sizeof(double) * (size_t)nu);      /* pi_b* */
+    {
+        double rsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) rsum += fabs(w.r[x]);
+        s.sum_r_ss = rsum;
+    }
+
+    /* ---- Algorithm 4 with |r| ---- */
+    const double eps_f = eps - eps_b;
+    double gamma = 0.0;
+    for (int32_t x = 0; x < nu; ++x) gamma += g->ws_u[x] / wsu * fabs(w.r[x]);
+    s.gamma = gamma;
+    for (int32_t x = 0; x < nu; ++x)
+        w.thr[x] = g->ws_u[x] > 0.0 ? wsu / g->ws_u[x] * eps_f / lambda : INFINITY;
+    np = 0.0;
+    int pi_returned = 0;
+    for (;;) {
+        if (++iters > ORC_MAX_ITERS) { free(pib_ss); work_free(&w); return ORC_ENOCONV; }
+        np += push_iteration_signed(g, &w, alpha);
+        ++s.pi_sel_iters;
+        int all_below = 1;
+        double fsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) {
+            if (fabs(w.r[x]) > w.thr[x]) all_below = 0;
+            fsum += g->ws_u[x] / wsu * fabs(w.r[x]);
+        }
+        if (all_below) { pi_returned = 1; break; }
+        if (np >= E2 * log_base(alpha, gamma / fsum)) break;
+    }
+    s.np_pi = np;
+    s.pi_returned = pi_returned;
+    double* pif = w.tmp;
+    for (int32_t x = 0; x < nu; ++x) pif[x] = g->ws_u[x] / wsu * w.pib[x];   /* Eq. (fppr) */
+    if (!pi_returned) {
+        double* rf = (double*)malloc(sizeof(double) * (size_t)nu);
+        double* pr = (double*)malloc(sizeof(double) * (size_t)nu);
+        if (!rf || !pr) { free(rf); free(pr); free(pib_ss); work_free(&w); return ORC_ENOMEM; }
+        double fsum = 0.0;
+        for (int32_t x = 0; x < nu; ++x) { rf[x] = g->ws_u[x] / wsu * w.r[x]; fsum += fabs(rf[x]); }
+        s.sum_rf = fsum;
+        int32_t t = orc_t(fsum, eps_f, alpha);
+        s.t = t;
+        rc = orc_power_iteration(g, rf, alpha, t, pr);
+        if (rc) { free(rf); free(pr); free(pib_ss); work_free(&w); return rc; }
+        for (int32_t x = 0; x < nu; ++x) pif[x] += pr[x];
+        free(rf); free(pr);
+    }
+    if (beta) for (int32_t x = 0; x < nu; ++x) beta[x] = pif[x] + pib_ss[x];
+    if (st) *st = s;
+    if (wi) *wi = info;
+    free(pib_ss);
+    work_free(&w);
+    return ORC_OK;
+}
+
+/* Warm-started queries over a thread pool; y0 is [n][nu]. */
+int orc_approx_bhpp_warm_many(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double eps,
+                              double eps_b, double lambda, const double* y0, double* beta, orc_stats* st,
+                              orc_warm_info* wi, int32_t nthreads) {
+    int rc = ORC_OK;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
+    for (int32_t i = 0; i < n; ++i) {
+        int r = orc_approx_bhpp_warm(g, src[i], alpha, eps, eps_b, lambda, y0 + (size_t)i * (size_t)g->nu,
+                                     beta ? beta + (size_t)i * (size_t)g->nu : NULL, st ? st + i : NULL,
+                                     wi ? wi + i : NULL);
+        if (r != ORC_OK) rc = r;
+    }
+    (void)nthreads;
+    return rc;
+}
+
 /* Independent queries over a thread pool: the CPU baseline. */
 int orc_approx_bhpp_many(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double eps,
                          double eps_b, double lambda, double* beta, orc_stats* st, int32_t nthreads) {
