@@ -317,6 +317,31 @@ def pin_series_agree(g, sources, alpha):
     return out
 
 
+def pin_warm_start(g, Pi, sources, alpha, eps=1e-6):
+    """Warm start: Lemma 1 for the signed residue of arbitrary starts, an
+    exact start returns the exact beta, noisy starts stay within eps on both
+    sides, and a useless start is the cold start."""
+    out = []
+    rng = np.random.default_rng(11)
+    src = [int(u) for u in sources[:4]]
+    for u in src[:2]:
+        y = Pi[:, u] * (1 + rng.normal(0, 0.3, g.n_u))
+        r = g.warm_residue(u, alpha, y)
+        _fail(np.abs(y + Pi @ r - Pi[:, u]).max() < 1e-12, f"warm residue breaks Lemma 1 (u={u})", out)
+    exact = np.stack([oracle.bhpp_from_dense(Pi, u) for u in src])
+    y0 = np.stack([Pi[:, u] for u in src])
+    b, st, wi = g.approx_bhpp_warm_many(src, alpha, eps, y0)
+    _fail(np.abs(b - exact).max() < 1e-11, "exact warm start does not return beta", out)
+    y0 = np.stack([Pi[:, u] * (1 + rng.normal(0, 0.05, g.n_u)) for u in src])
+    b, st, wi = g.approx_bhpp_warm_many(src, alpha, eps, y0)
+    _fail(all(w["fell_back"] == 0 for w in wi), "noisy warm start fell back", out)
+    _fail(np.abs(b - exact).max() <= eps + 1e-12, f"warm start outside eps: {np.abs(b - exact).max()}", out)
+    b, st, wi = g.approx_bhpp_warm_many(src[:1], alpha, eps, np.zeros((1, g.n_u)))
+    cold, _ = g.approx_bhpp_many(src[:1], alpha, eps)
+    _fail(wi[0]["fell_back"] == 1 and np.array_equal(b[0], cold[0]), "zero start is not the cold start", out)
+    return out
+
+
 def run_core_pins(small, stop_early=False):
     """The pins the mutation tests rely on; fast enough to run per mutant.
     ``small`` holds the edge list and the dense Pi (computed with numpy, not
@@ -330,7 +355,8 @@ def run_core_pins(small, stop_early=False):
               lambda: pin_golden_gamma(g, src, a),
               lambda: pin_theorems(g, Pi, src[:4], a, [1e-3, 1e-6])[0],
               lambda: pin_lemma1_and_mass(g, Pi, int(src[0]), a, 1e-5),
-              lambda: pin_lambda(g, Pi, a)]
+              lambda: pin_lambda(g, Pi, a),
+              lambda: pin_warm_start(g, Pi, src, a)]
     out = []
     for c in checks:
         try:

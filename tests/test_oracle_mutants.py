@@ -30,6 +30,11 @@ MUTANTS = {
     "ws_is_degree": ("for (int64_t p = g->rp_u[x]; p < g->rp_u[x + 1]; ++p) s += g->w_u[p];",
                      "for (int64_t p = g->rp_u[x]; p < g->rp_u[x + 1]; ++p) s += 1.0;"),
     "ss_threshold_eps": ("w.thr[x] = eps_b;", "w.thr[x] = eps;"),
+    "warm_residue_sign": ("r_out[x] = (x == u ? 1.0 : 0.0) - (y[x]", "r_out[x] = (x == u ? 1.0 : 0.0) + (y[x]"),
+    "warm_residue_no_decay": ("(y[x] - (1.0 - alpha) * py[x]) / alpha", "(y[x] - py[x]) / alpha"),
+    "warm_push_positive_only": ("if (!(fabs(rx) > w->thr[x])) continue;", "if (!(rx > w->thr[x])) continue;"),
+    "warm_combine_start": ("beta[x] = pif[x] + pib_ss[x]", "beta[x] = pif[x] + y0[x]"),
+    "warm_fallback_never": ("if (!(info.res_l1 < 1.0 && info.res_max < 1.0)) {", "if (0) {"),
     "no_sequential_pushes": ("if (!(rmax > eps_b && rsum > eps_b)) break;", "break;"),
 }
 
@@ -38,7 +43,8 @@ MUTANTS = {
 def test_mutant_is_caught(name, tmp_path):
     old, new = MUTANTS[name]
     src = open(SRC).read()
-    assert src.count(old) == 1, f"mutation site for {name} not unique"
+    # a formula written in both the cold and the warm path is mutated in both
+    assert src.count(old) >= 1, f"mutation site for {name} missing"
     mfile = tmp_path / "mutant.c"
     mfile.write_text(src.replace(old, new))
     lib = tmp_path / "libmutant.so"
