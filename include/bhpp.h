@@ -101,6 +101,14 @@ typedef struct {
     double build_ms;          /* device time of the build, preprocessing included */
 } bhpp_graph_summary;
 
+/* Per-query report of a warm start (bhpp_query_batch_warm, servers with a model). */
+typedef struct {
+    double res_l1;        /* sum_x ws(x)/ws(u) |r(x)| of the start's signed residue (cold start: 1) */
+    double res_max;       /* max_x |r(x)| (cold start: 1) */
+    int32_t fell_back;    /* 1: the start was no better than the cold start, the query ran cold */
+    int32_t reserved;
+} bhpp_warm_stats;
+
 /*
  * Build the graph and run the preprocessing step (Sec. 3.1; Lemma 4;
  * Eq. (epsilon-b); the paper excludes this step from query time, Sec. 5.4).
@@ -228,6 +236,94 @@ bhpp_status bhpp_set_launch_config(bhpp_graph* g, const int32_t config[4]);
 bhpp_status bhpp_get_launch_config(const bhpp_graph* g, int32_t config_out[4]);
 
 /* ------------------------------------------------------------------------
+ * Learned warm start (an extension, not in the paper; it rests on Lemma 1 and
+ * Lemma 3).
+ *
+ * Lemma 1's invariant pi(., u) = pi_b + Pi r holds for ANY start pi_b = y when
+ * r = e_u - (y - (1-alpha) P y)/alpha (signed). A model predicts the start;
+ * the residue is computed with one two-hop sweep accumulated in FP64, and
+ * Algorithms 3-5 then run with |r| in every threshold, sum and budget test.
+ * The combine takes pi_b as SS-Push returned it, so |beta - beta'| <= eps on
+ * both sides (a cold start is within [0, eps]). A start whose residue is no
+ * better than the cold start's (sum_x ws(x)/ws(u)|r(x)| >= 1 or max|r| >= 1)
+ * is dropped and the query runs cold.
+ *
+ * The model: 64 hashed features per U node (degree, ws, neighbour-id
+ * buckets), two towers f, g: 64 -> 256 -> 256 -> 128 with GELU, BF16 weights
+ * and activations with FP32 accumulation (MFMA), and the prediction
+ *     p_hat(u, x) = c ws(x) <f(u), g(x)>  of pi(u, x), clamped at 0
+ * (the start y(x) = ws(u)/ws(x) p_hat(u, x)). Parameters are one FP32 vector of
+ * BHPP_MODEL_PARAMS values: tower f then tower g, each W1[64][256] b1[256]
+ * W2[256][256] b2[256] W3[256][128] b3[128] (row-major, y = x W + b).
+ *
+ * bhpp_model_create      computes the features, draws Glorot-uniform weights
+ *                        from `seed` (host RNG), zero biases. The model keeps
+ *                        a pointer to the graph: free it first.
+ * bhpp_model_params      copies the FP32 parameters out (get, host, nullable)
+ *                        and/or in (set, host, nullable; resets the optimizer).
+ *                        c_out / tau_out (nullable): the score scale c and
+ *                        the loss's tau.
+ * bhpp_model_features    features of every U node, device FP32 [n_u][64], rows
+ *                        in caller ids.
+ * bhpp_model_loss_grad   one forward and backward pass (no update) on a batch:
+ *                        sources src[n_src], candidates cand[n_cand] (host,
+ *                        caller ids), targets[n_src][n_cand] (host FP32,
+ *                        estimates of pi(u, x), NaN where unknown);
+ *                        loss = mean over known T of (p_hat - T)^2 / (T + tau);
+ *                        grad_out host FP32[BHPP_MODEL_PARAMS], nullable.
+ * bhpp_model_train       Adam (lr, betas 0.9/0.999) for `steps` steps on lists
+ *                        of BHPP values: ids[n_src][M] (caller ids, -1 for
+ *                        none) and vals[n_src][M] = beta'(src_i, x), e.g. the
+ *                        top entries of each vector from bhpp_query_batch
+ *                        (exclude_self = 0) plus entries at random nodes.
+ *                        Target of a listed pair: pi(u,x) = beta'(u,x)
+ *                        ws(x)/(ws(u)+ws(x)) (Lemma 3); other pairs are left
+ *                        out. Each step takes batch_src sources drawn from
+ *                        `seed` and, as candidates, their listed nodes (at
+ *                        most batch_cand). loss_out: host float[steps], nullable.
+ * bhpp_model_embed       embeddings of every U node by both towers; needed
+ *                        after training and before warm queries.
+ * bhpp_query_batch_warm  bhpp_query_batch with every query warm-started from
+ *                        the model; warm_out: host bhpp_warm_stats[n_src],
+ *                        nullable. Errors as bhpp_query_batch, and
+ *                        INVALID_ARG if the model has no embeddings.
+ * ---------------------------------------------------------------------- */
+#define BHPP_MODEL_FEATURES 64
+#define BHPP_MODEL_PARAMS 230656
+
+typedef struct bhpp_model bhpp_model;
+
+bhpp_status bhpp_model_create(bhpp_graph* g, uint64_t seed, bhpp_model** out);
+bhpp_status bhpp_model_params(bhpp_model* m, float* get_out, const float* set_in, double* c_out, double* tau_out);
+bhpp_status bhpp_model_features(bhpp_model* m, float* out, void* hip_stream);
+bhpp_status bhpp_model_loss_grad(bhpp_model* m, int32_t n_src, const int32_t* src, int32_t n_cand,
+                                 const int32_t* cand, const float* targets, double* loss_out, float* grad_out);
+bhpp_status bhpp_model_train(bhpp_model* m, int32_t n_src, const int32_t* src, int32_t M, const int32_t* ids,
+                             const float* vals, int32_t steps, int32_t batch_src, int32_t batch_cand, double lr,
+                             uint64_t seed, float* loss_out);
+bhpp_status bhpp_model_embed(bhpp_model* m);
+void bhpp_model_free(bhpp_model* m);
+bhpp_status bhpp_query_batch_warm(bhpp_graph* g, bhpp_model* m, int32_t n_src, const int32_t* sources,
+                                  const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
+                                  int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
+                                  bhpp_warm_stats* warm_out, void* hip_stream);
+
+/* Warm start from caller-given starts instead of a model: starts is device
+   [n_src][n_u] of the graph dtype, row i = estimates of pi(sources[i], x) for
+   every x (caller ids; any sign; the start is rounded to FP32). Same
+   residue, phases, bound and fallback as bhpp_query_batch_warm. */
+bhpp_status bhpp_query_batch_start(bhpp_graph* g, const void* starts, int32_t n_src, const int32_t* sources,
+                                   const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
+                                   int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
+                                   bhpp_warm_stats* warm_out, void* hip_stream);
+
+/* GEMM on the matrix cores as the model runs it, exposed for its layout test:
+   C[M][N] = A B, A BF16 [M][K] (or [K][M] if trans_a), B BF16 [K][N] (or
+   [N][K] if trans_b), C FP32 [M][N]; all device. Errors: INVALID_ARG. */
+bhpp_status bhpp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t trans_a, const uint16_t* B,
+                           int32_t trans_b, float* C, void* hip_stream);
+
+/* ------------------------------------------------------------------------
  * Serving (continuous batching). Requests are the queries of Definition 1
  * (source u, error bound eps) answered by Algorithm 5 and reduced to their
  * top-k; they arrive one at a time and leave when done.
@@ -235,8 +331,11 @@ bhpp_status bhpp_get_launch_config(const bhpp_graph* g, int32_t config_out[4]);
  * A server owns a resident query block of `width` columns on its own HIP
  * stream: width is the largest power of two <= max_width (1..64) whose
  * device workspace fits in mem_budget_bytes (<= 0: no cap); the workspace of
- * width 64 on a 1M x 2M graph is about 1.6 GB in FP32. Admission: a request
- * enters the block when a column is free, at the next poll.
+ * width 64 on a 1M x 2M graph is about 1.6 GB in FP32 (plus about 3 GB with a
+ * model, for the warm starts). Admission: a request enters the block when a
+ * column is free, at the next poll. With a model (nullable; it must have
+ * embeddings) every admitted request is warm-started as in
+ * bhpp_query_batch_warm; warm_out of the poll (nullable) reports it.
  *
  * bhpp_server_submit queues a request (host call, no device work; source in
  * caller ids, eps > 0, tag is returned with the result). It may run on
@@ -266,11 +365,12 @@ typedef struct {
     double lambda;          /* Lemma 4 bound used by its PI-Push thresholds */
 } bhpp_server_summary;
 
-bhpp_status bhpp_server_create(bhpp_graph* g, int32_t max_width, double mem_budget_bytes, double alpha,
-                               int32_t k, int32_t exclude_self, bhpp_server** out);
+bhpp_status bhpp_server_create(bhpp_graph* g, bhpp_model* model, int32_t max_width, double mem_budget_bytes,
+                               double alpha, int32_t k, int32_t exclude_self, bhpp_server** out);
 bhpp_status bhpp_server_submit(bhpp_server* s, int32_t source, double eps, int64_t tag);
 bhpp_status bhpp_server_poll(bhpp_server* s, int32_t capacity, int64_t* tags_out, int32_t* ids_out,
-                             void* vals_out, bhpp_query_stats* stats_out, int32_t* n_out);
+                             void* vals_out, bhpp_query_stats* stats_out, bhpp_warm_stats* warm_out,
+                             int32_t* n_out);
 bhpp_status bhpp_server_info(const bhpp_server* s, bhpp_server_summary* out);
 void bhpp_server_destroy(bhpp_server* s);
 

@@ -7,8 +7,11 @@ The warm start is not in the paper; it seeds Lemma 1's invariant (any start
 y of pi(., u) with the signed residue r = e_u - (y - (1-alpha) P y)/alpha).
 Its prediction uses the symmetric kernel of Lemma 3,
 K(u, x) = pi(u, x)/ws(x) = pi(x, u)/ws(u), modelled by two towers f and g:
-    p_hat(u, x) = c * ws(x) * <f(feat(u)), g(feat(x))>   (estimates pi(u, x))
-so y(x) = ws(u)/ws(x) p_hat(u, x) estimates pi(x, u).
+    p_hat(u, x) = c * ws(x) * <f(feat(u)), g(feat(x))> + [x = u] D(u)
+(estimates pi(u, x)), where D(u) = alpha + alpha (1-alpha) P(u,u) is the
+structural self term (the first two terms of the return series, which a
+low-rank product cannot express); y(x) = ws(u)/ws(x) p_hat(u, x) then
+estimates pi(x, u).
 
 Towers: 64 -> 256 -> 256 -> 128, GELU after the two hidden layers,
 GELU(z) = z Phi(z) (exact form with erf). Parameters are one flat vector:
@@ -16,7 +19,10 @@ tower f then tower g, each W1[64][256], b1[256], W2[256][256], b2[256],
 W3[256][128], b3[128] (row-major, y = x W + b).
 
 Training loss on a batch of sources u_i and candidates x_j with targets
-T[i][j] = pi(u_i, x_j):  L = mean_ij ((p_hat(u_i, x_j) - T[i][j]) / sigma)^2.
+T[i][j] = pi(u_i, x_j) (NaN where unknown: left out):
+    L = mean over known (i, j) of (p_hat(u_i, x_j) - T[i][j])^2 / (T[i][j] + tau),
+a squared relative error weighted by the mass T, so the many small entries
+of the far field count by their mass as they do in the residue's L1 norm.
 Everything here is FP64 with no intermediate rounding.
 """
 from __future__ import annotations
@@ -57,6 +63,22 @@ def features(g):
     np.add.at(F[:, 3], rows, frac * np.log1p(deg_v[ci_u]) / 8.0)
     np.add.at(F, (rows, 4 + bucket(ci_u)), frac)
     return F
+
+
+def self_prior(g, alpha):
+    """Structural self term added to the prediction at x = u: the first two
+    terms of the return series of Eq. (hpp), alpha + alpha (1-alpha) P(u,u),
+    with P(u,u) = sum_v w(u,v)^2 / (ws(u) ws(v)) (Eq. (pmatrix)); 0 if isolated."""
+    ex = g.export()
+    rp_u, ci_u, w_u, ws_u, ws_v = ex["rp_u"], ex["ci_u"], ex["w_u"], ex["ws_u"], ex["ws_v"]
+    deg = np.diff(rp_u)
+    rows = np.repeat(np.arange(g.n_u), deg)
+    s = np.zeros(g.n_u)
+    np.add.at(s, rows, w_u * w_u / ws_v[ci_u])
+    out = np.zeros(g.n_u)
+    live = deg > 0
+    out[live] = alpha + alpha * (1 - alpha) * s[live] / ws_u[live]
+    return out
 
 
 def split(theta):
@@ -109,25 +131,33 @@ def tower_backward(p, cache, dz3):
     return [gW1, gb1, gW2, gb2, gW3, gb3]
 
 
-def predict(theta, Xu, Xx, ws_x, c):
-    """p_hat[i][j] = c ws(x_j) <f(Xu_i), g(Xx_j)>."""
+def predict(theta, Xu, Xx, ws_x, c, extra=None):
+    """p_hat[i][j] = c ws(x_j) <f(Xu_i), g(Xx_j)> (+ extra[i][j], the self term)."""
     pf, pg = split(theta)
     F, _ = tower_forward(pf, Xu)
     Gm, _ = tower_forward(pg, Xx)
-    return c * (F @ Gm.T) * np.asarray(ws_x)[None, :]
+    p = c * (F @ Gm.T) * np.asarray(ws_x)[None, :]
+    return p if extra is None else p + extra
 
 
-def loss_and_grad(theta, Xu, Xx, ws_x, T, c, sigma):
-    """The training loss and its gradient (flat, same layout as theta)."""
+def loss_and_grad(theta, Xu, Xx, ws_x, T, c, tau, extra=None):
+    """The training loss and its gradient (flat, same layout as theta);
+    extra[i][j] is added to the prediction (the self term where x_j = u_i)."""
     pf, pg = split(theta)
     F, cf = tower_forward(pf, Xu)
     Gm, cg = tower_forward(pg, Xx)
     ws_x = np.asarray(ws_x, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    known = np.isfinite(T)
+    Tk = np.where(known, T, 0.0)
+    wgt = np.where(known, 1.0 / np.sqrt(np.abs(Tk) + tau), 0.0)
     pred = c * (F @ Gm.T) * ws_x[None, :]
-    diff = (pred - T) / sigma
-    n = T.size
+    if extra is not None:
+        pred = pred + extra
+    diff = (pred - Tk) * wgt
+    n = int(known.sum())
     loss = float((diff * diff).sum() / n)
-    dpred = 2.0 * diff / sigma / n
+    dpred = 2.0 * diff * wgt / n
     dK = dpred * c * ws_x[None, :]
     dF = dK @ Gm
     dG = dK.T @ F

@@ -31,8 +31,11 @@ BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER = 1, 2
 EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
             "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_autotune",
             "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_server_create", "bhpp_server_submit",
-            "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_free_graph",
-            "bhpp_status_string"]
+            "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_model_create", "bhpp_model_params",
+            "bhpp_model_features", "bhpp_model_loss_grad", "bhpp_model_train", "bhpp_model_embed", "bhpp_model_free",
+            "bhpp_query_batch_warm", "bhpp_query_batch_start", "bhpp_gemm_bf16", "bhpp_free_graph", "bhpp_status_string"]
+MODEL_PARAMS = 230656
+MODEL_FEATURES = 64
 
 
 class BhppError(RuntimeError):
@@ -70,6 +73,14 @@ class GraphSummary(ctypes.Structure):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         d["lambda"] = d.pop("lambda_")
         return d
+
+
+class WarmStats(ctypes.Structure):
+    _fields_ = [("res_l1", ctypes.c_double), ("res_max", ctypes.c_double), ("fell_back", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(res_l1=self.res_l1, res_max=self.res_max, fell_back=self.fell_back)
 
 
 class ServerSummary(ctypes.Structure):
@@ -119,11 +130,31 @@ def load_library():
     L.bhpp_get_launch_config.restype = I32
     L.bhpp_get_launch_config.argtypes = [P, P]
     L.bhpp_server_create.restype = I32
-    L.bhpp_server_create.argtypes = [P, I32, D, D, I32, I32, ctypes.POINTER(P)]
+    L.bhpp_server_create.argtypes = [P, P, I32, D, D, I32, I32, ctypes.POINTER(P)]
     L.bhpp_server_submit.restype = I32
     L.bhpp_server_submit.argtypes = [P, I32, D, I64]
     L.bhpp_server_poll.restype = I32
-    L.bhpp_server_poll.argtypes = [P, I32, P, P, P, P, P]
+    L.bhpp_server_poll.argtypes = [P, I32, P, P, P, P, P, P]
+    L.bhpp_model_create.restype = I32
+    L.bhpp_model_create.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(P)]
+    L.bhpp_model_params.restype = I32
+    L.bhpp_model_params.argtypes = [P, P, P, P, P]
+    L.bhpp_model_features.restype = I32
+    L.bhpp_model_features.argtypes = [P, P, P]
+    L.bhpp_model_loss_grad.restype = I32
+    L.bhpp_model_loss_grad.argtypes = [P, I32, P, I32, P, P, P, P]
+    L.bhpp_model_train.restype = I32
+    L.bhpp_model_train.argtypes = [P, I32, P, I32, P, P, I32, I32, I32, D, ctypes.c_uint64, P]
+    L.bhpp_model_embed.restype = I32
+    L.bhpp_model_embed.argtypes = [P]
+    L.bhpp_model_free.restype = None
+    L.bhpp_model_free.argtypes = [P]
+    L.bhpp_query_batch_warm.restype = I32
+    L.bhpp_query_batch_warm.argtypes = [P, P, I32, P, P, D, D, P, I32, I32, P, P, P, P, P]
+    L.bhpp_query_batch_start.restype = I32
+    L.bhpp_query_batch_start.argtypes = [P, P, I32, P, P, D, D, P, I32, I32, P, P, P, P, P]
+    L.bhpp_gemm_bf16.restype = I32
+    L.bhpp_gemm_bf16.argtypes = [I32, I32, I32, P, I32, P, I32, P, P]
     L.bhpp_server_info.restype = I32
     L.bhpp_server_info.argtypes = [P, ctypes.POINTER(ServerSummary)]
     L.bhpp_server_destroy.restype = None
@@ -233,9 +264,12 @@ class Graph:
         _check(rc, "bhpp_query")
         return (out, st.as_dict()) if with_stats else out
 
-    def query_batch(self, sources, eps, alpha=None, k=0, exclude_self=True, scores=True, stats=True):
-        """Many queries (bhpp_query_batch). ``eps`` is a float or one per source.
-        Returns dict(scores=[n, n_u] tensor or None, ids, vals, stats)."""
+    def query_batch(self, sources, eps, alpha=None, k=0, exclude_self=True, scores=True, stats=True, model=None,
+                    starts=None):
+        """Many queries (bhpp_query_batch; bhpp_query_batch_warm with a Model;
+        bhpp_query_batch_start with starts = [n, n_u] estimates of pi(u, x)).
+        ``eps`` is a float or one per source. Returns dict(scores=[n, n_u]
+        tensor or None, ids, vals, stats, warm)."""
         torch = _torch()
         src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
         n = src.size
@@ -244,13 +278,30 @@ class Graph:
         ids = torch.empty((n, k), dtype=torch.int32, device="cuda") if k else None
         vals = torch.empty((n, k), dtype=self._tdtype, device="cuda") if k else None
         st = (QueryStats * max(1, n))()
-        rc = load_library().bhpp_query_batch(
-            self._h, n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha, float(eps_arr[0]),
-            sc.data_ptr() if sc is not None else None, int(k), 1 if exclude_self else 0,
-            ids.data_ptr() if ids is not None else None, vals.data_ptr() if vals is not None else None,
-            ctypes.cast(st, ctypes.c_void_p) if stats else None, _stream())
-        _check(rc, "bhpp_query_batch")
-        return dict(scores=sc, ids=ids, vals=vals, stats=[st[i].as_dict() for i in range(n)] if stats else None)
+        common = (n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha, float(eps_arr[0]),
+                  sc.data_ptr() if sc is not None else None, int(k), 1 if exclude_self else 0,
+                  ids.data_ptr() if ids is not None else None, vals.data_ptr() if vals is not None else None,
+                  ctypes.cast(st, ctypes.c_void_p) if stats else None)
+        warm = None
+        if starts is not None:
+            st0 = _dev(starts, self._tdtype)
+            assert tuple(st0.shape) == (n, self.n_u)
+            ws = (WarmStats * max(1, n))()
+            rc = load_library().bhpp_query_batch_start(self._h, st0.data_ptr(), *common,
+                                                       ctypes.cast(ws, ctypes.c_void_p), _stream())
+            _check(rc, "bhpp_query_batch_start")
+            warm = [ws[i].as_dict() for i in range(n)]
+        elif model is None:
+            rc = load_library().bhpp_query_batch(self._h, *common, _stream())
+            _check(rc, "bhpp_query_batch")
+        else:
+            ws = (WarmStats * max(1, n))()
+            rc = load_library().bhpp_query_batch_warm(self._h, model._h, *common, ctypes.cast(ws, ctypes.c_void_p),
+                                                      _stream())
+            _check(rc, "bhpp_query_batch_warm")
+            warm = [ws[i].as_dict() for i in range(n)]
+        return dict(scores=sc, ids=ids, vals=vals, stats=[st[i].as_dict() for i in range(n)] if stats else None,
+                    warm=warm)
 
     def autotune(self, cache_path=None):
         """Pick the fastest launch setting for this graph (bhpp_autotune) and
@@ -306,15 +357,17 @@ class Server:
     """A resident query block fed by a request queue (bhpp_server_*):
     continuous batching of top-k queries on one graph."""
 
-    def __init__(self, graph, k=100, max_width=64, mem_budget_bytes=0.0, alpha=None, exclude_self=True):
+    def __init__(self, graph, k=100, max_width=64, mem_budget_bytes=0.0, alpha=None, exclude_self=True, model=None):
         _torch()
         L = load_library()
         h = ctypes.c_void_p()
-        rc = L.bhpp_server_create(graph._h, int(max_width), float(mem_budget_bytes), alpha or graph.alpha, int(k),
-                                  1 if exclude_self else 0, ctypes.byref(h))
+        rc = L.bhpp_server_create(graph._h, model._h if model is not None else None, int(max_width),
+                                  float(mem_budget_bytes), alpha or graph.alpha, int(k), 1 if exclude_self else 0,
+                                  ctypes.byref(h))
         _check(rc, "bhpp_server_create")
         self._h = h
-        self.graph = graph          # keeps the graph alive while the server exists
+        self.graph = graph          # keeps the graph (and model) alive while the server exists
+        self.model = model
         self.k = int(k)
         self.width = self.info()["width"]
         self._vdt = np.float64 if graph.dtype == "f64" else np.float32
@@ -322,21 +375,28 @@ class Server:
         self._ids = np.empty((self.width, self.k), dtype=np.int32)
         self._vals = np.empty((self.width, self.k), dtype=self._vdt)
         self._st = (QueryStats * self.width)()
+        self._ws = (WarmStats * self.width)()
 
     def submit(self, source, eps, tag):
         _check(load_library().bhpp_server_submit(self._h, int(source), float(eps), int(tag)), "bhpp_server_submit")
 
     def poll(self, stats=False):
-        """Run one chunk; returns [(tag, ids, vals[, stats])] of the finished requests."""
+        """Run one chunk; returns [(tag, ids, vals[, stats])] of the finished
+        requests (stats includes the warm-start report when there is a model)."""
         n = ctypes.c_int32()
         rc = load_library().bhpp_server_poll(self._h, self.width, self._tags.ctypes.data, self._ids.ctypes.data,
                                              self._vals.ctypes.data, ctypes.cast(self._st, ctypes.c_void_p),
-                                             ctypes.byref(n))
+                                             ctypes.cast(self._ws, ctypes.c_void_p), ctypes.byref(n))
         _check(rc, "bhpp_server_poll")
         out = []
         for j in range(n.value):
             r = (int(self._tags[j]), self._ids[j].copy(), self._vals[j].copy())
-            out.append(r + (self._st[j].as_dict(),) if stats else r)
+            if stats:
+                d = self._st[j].as_dict()
+                if self.model is not None:
+                    d.update(self._ws[j].as_dict())
+                r = r + (d,)
+            out.append(r)
         return out
 
     def info(self):
@@ -354,6 +414,92 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Model:
+    """The warm-start network of a graph (bhpp_model_*): features, two BF16
+    towers trained on the GPU, node embeddings."""
+
+    def __init__(self, graph, seed=0):
+        _torch()
+        h = ctypes.c_void_p()
+        _check(load_library().bhpp_model_create(graph._h, ctypes.c_uint64(seed), ctypes.byref(h)), "bhpp_model_create")
+        self._h = h
+        self.graph = graph
+
+    def params(self):
+        out = np.empty(MODEL_PARAMS, dtype=np.float32)
+        _check(load_library().bhpp_model_params(self._h, out.ctypes.data, None, None, None), "bhpp_model_params")
+        return out
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        assert theta.size == MODEL_PARAMS
+        _check(load_library().bhpp_model_params(self._h, None, theta.ctypes.data, None, None), "bhpp_model_params")
+
+    def scales(self):
+        c, sg = ctypes.c_double(), ctypes.c_double()
+        _check(load_library().bhpp_model_params(self._h, None, None, ctypes.byref(c), ctypes.byref(sg)),
+               "bhpp_model_params")
+        return c.value, sg.value
+
+    def features(self):
+        torch = _torch()
+        out = torch.empty((self.graph.n_u, MODEL_FEATURES), dtype=torch.float32, device="cuda")
+        _check(load_library().bhpp_model_features(self._h, out.data_ptr(), _stream()), "bhpp_model_features")
+        torch.cuda.synchronize()
+        return out
+
+    def loss_grad(self, src, cand, targets, want_grad=True):
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        cand = np.ascontiguousarray(cand, dtype=np.int32)
+        T = np.ascontiguousarray(targets, dtype=np.float32).reshape(src.size, cand.size)
+        loss = ctypes.c_double()
+        g = np.empty(MODEL_PARAMS, dtype=np.float32) if want_grad else None
+        _check(load_library().bhpp_model_loss_grad(self._h, src.size, src.ctypes.data, cand.size, cand.ctypes.data,
+                                                   T.ctypes.data, ctypes.byref(loss),
+                                                   g.ctypes.data if g is not None else None), "bhpp_model_loss_grad")
+        return loss.value, g
+
+    def train(self, src, ids, vals, steps, batch_src=32, batch_cand=4096, lr=1e-3, seed=1):
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        vals = np.ascontiguousarray(vals, dtype=np.float32)
+        M = ids.shape[1]
+        losses = np.empty(max(1, steps), dtype=np.float32)
+        _check(load_library().bhpp_model_train(self._h, src.size, src.ctypes.data, M, ids.ctypes.data,
+                                               vals.ctypes.data, int(steps), int(batch_src), int(batch_cand),
+                                               float(lr), ctypes.c_uint64(seed), losses.ctypes.data),
+               "bhpp_model_train")
+        return losses[:steps]
+
+    def embed(self):
+        _check(load_library().bhpp_model_embed(self._h), "bhpp_model_embed")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bhpp_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_bf16(A, B, trans_a=False, trans_b=False):
+    """bhpp_gemm_bf16 on device bf16 tensors: A @ B in FP32 (operands given
+    transposed when trans_a / trans_b)."""
+    torch = _torch()
+    A = A.contiguous()
+    B = B.contiguous()
+    M, K = (A.shape[1], A.shape[0]) if trans_a else A.shape
+    N = B.shape[0] if trans_b else B.shape[1]
+    C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    _check(load_library().bhpp_gemm_bf16(M, N, K, A.data_ptr(), 1 if trans_a else 0, B.data_ptr(),
+                                         1 if trans_b else 0, C.data_ptr(), _stream()), "bhpp_gemm_bf16")
+    return C
 
 
 def topk(scores, k, exclude=None):

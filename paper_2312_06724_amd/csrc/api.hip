@@ -19,6 +19,11 @@ struct bhpp_server {
     int32_t width;
 };
 
+struct bhpp_model {
+    bhpp_graph* h;
+    bhpp::Model* m;
+};
+
 namespace {
 
 hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -92,13 +97,16 @@ bhpp_status bhpp_build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const in
     }
 }
 
-bhpp_status bhpp_query_batch(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps,
-                             double alpha, double eps_all, void* scores_out, int32_t k, int32_t exclude_self,
-                             int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, void* hip_stream) {
+static bhpp_status query_batch_impl(bhpp_graph* h, bhpp_model* model, const void* starts, int32_t n_src,
+                                    const int32_t* sources,
+                                    const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
+                                    int32_t exclude_self, int32_t* topk_ids, void* topk_vals,
+                                    bhpp_query_stats* stats, bhpp_warm_stats* wstats, void* hip_stream) {
     if (!h || !h->g) return BHPP_INVALID_ARG;
     Graph* g = h->g;
     if (g->sticky_error) return BHPP_DEVICE_ERROR;
     if (n_src < 0 || (n_src > 0 && !sources) || !valid_alpha(alpha)) return BHPP_INVALID_ARG;
+    if (model && (model->h != h || !bhpp::model_ready(model->m))) return BHPP_INVALID_ARG;
     if (n_src == 0) return BHPP_OK;
     if (k < 0 || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
     if (k > 0 && (!topk_ids || !topk_vals)) return BHPP_INVALID_ARG;
@@ -117,13 +125,38 @@ bhpp_status bhpp_query_batch(bhpp_graph* h, int32_t n_src, const int32_t* source
         double lam = 0.0;
         bhpp_status rc = lambda_for(g, alpha, s, &lam);
         if (rc) return sticky(g, rc);
-        rc = bhpp::run_queries(g, n_src, sources, e.data(), alpha, lam, scores_out, k, exclude_self, topk_ids,
-                               topk_vals, stats, s);
+        rc = bhpp::run_queries(g, model ? model->m : nullptr, starts, wstats, n_src, sources, e.data(), alpha, lam,
+                               scores_out, k, exclude_self, topk_ids, topk_vals, stats, s);
         if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
         return sticky(g, rc);
     } catch (...) {
         return BHPP_OUT_OF_MEMORY;
     }
+}
+
+bhpp_status bhpp_query_batch(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps,
+                             double alpha, double eps_all, void* scores_out, int32_t k, int32_t exclude_self,
+                             int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, void* hip_stream) {
+    return query_batch_impl(h, nullptr, nullptr, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
+                            topk_ids, topk_vals, stats, nullptr, hip_stream);
+}
+
+bhpp_status bhpp_query_batch_warm(bhpp_graph* h, bhpp_model* m, int32_t n_src, const int32_t* sources,
+                                  const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
+                                  int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
+                                  bhpp_warm_stats* warm_out, void* hip_stream) {
+    if (!m || !m->m) return BHPP_INVALID_ARG;
+    return query_batch_impl(h, m, nullptr, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self, topk_ids,
+                            topk_vals, stats, warm_out, hip_stream);
+}
+
+bhpp_status bhpp_query_batch_start(bhpp_graph* h, const void* starts, int32_t n_src, const int32_t* sources,
+                                   const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
+                                   int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
+                                   bhpp_warm_stats* warm_out, void* hip_stream) {
+    if (!starts) return BHPP_INVALID_ARG;
+    return query_batch_impl(h, nullptr, starts, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
+                            topk_ids, topk_vals, stats, warm_out, hip_stream);
 }
 
 bhpp_status bhpp_query(bhpp_graph* h, int32_t source, double alpha, double eps, void* scores_out,
@@ -262,11 +295,12 @@ bhpp_status bhpp_get_launch_config(const bhpp_graph* h, int32_t config_out[4]) {
     return BHPP_OK;
 }
 
-bhpp_status bhpp_server_create(bhpp_graph* h, int32_t max_width, double mem_budget_bytes, double alpha, int32_t k,
-                               int32_t exclude_self, bhpp_server** out) {
+bhpp_status bhpp_server_create(bhpp_graph* h, bhpp_model* model, int32_t max_width, double mem_budget_bytes,
+                               double alpha, int32_t k, int32_t exclude_self, bhpp_server** out) {
     if (!out) return BHPP_INVALID_ARG;
     *out = nullptr;
     if (!h || !h->g || !valid_alpha(alpha) || max_width < 1 || max_width > 64) return BHPP_INVALID_ARG;
+    if (model && (model->h != h || !bhpp::model_ready(model->m))) return BHPP_INVALID_ARG;
     Graph* g = h->g;
     if (g->sticky_error) return BHPP_DEVICE_ERROR;
     if (k < 1 || k > bhpp::kTopkTmpK || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
@@ -277,7 +311,8 @@ bhpp_status bhpp_server_create(bhpp_graph* h, int32_t max_width, double mem_budg
         bhpp_status rc = lambda_for(g, alpha, nullptr, &lam);
         if (rc) return sticky(g, rc);
         bhpp::Server* sv = nullptr;
-        rc = bhpp::server_create(g, max_width, mem_budget_bytes, alpha, lam, k, exclude_self ? 1 : 0, &sv);
+        rc = bhpp::server_create(g, model ? model->m : nullptr, max_width, mem_budget_bytes, alpha, lam, k,
+                                 exclude_self ? 1 : 0, &sv);
         if (rc) return sticky(g, rc);
         bhpp_server* s = new (std::nothrow) bhpp_server{h, sv, 0};
         if (!s) {
@@ -307,7 +342,7 @@ bhpp_status bhpp_server_submit(bhpp_server* s, int32_t source, double eps, int64
 }
 
 bhpp_status bhpp_server_poll(bhpp_server* s, int32_t capacity, int64_t* tags_out, int32_t* ids_out, void* vals_out,
-                             bhpp_query_stats* stats_out, int32_t* n_out) {
+                             bhpp_query_stats* stats_out, bhpp_warm_stats* warm_out, int32_t* n_out) {
     if (!s || !s->sv || !n_out) return BHPP_INVALID_ARG;
     *n_out = 0;
     if (capacity < s->width || !tags_out || !ids_out || !vals_out) return BHPP_INVALID_ARG;
@@ -315,7 +350,7 @@ bhpp_status bhpp_server_poll(bhpp_server* s, int32_t capacity, int64_t* tags_out
     if (g->sticky_error) return BHPP_DEVICE_ERROR;
     try {
         std::lock_guard<std::mutex> lock(g->mu);
-        return sticky(g, bhpp::server_poll(s->sv, tags_out, ids_out, vals_out, stats_out, n_out));
+        return sticky(g, bhpp::server_poll(s->sv, tags_out, ids_out, vals_out, stats_out, warm_out, n_out));
     } catch (...) {
         return BHPP_OUT_OF_MEMORY;
     }
@@ -334,6 +369,117 @@ void bhpp_server_destroy(bhpp_server* s) {
         bhpp::server_destroy(s->sv);
     }
     delete s;
+}
+
+bhpp_status bhpp_model_create(bhpp_graph* h, uint64_t seed, bhpp_model** out) {
+    if (!out) return BHPP_INVALID_ARG;
+    *out = nullptr;
+    if (!h || !h->g) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        bhpp::Model* m = nullptr;
+        bhpp_status rc = bhpp::model_create(g, seed, &m);
+        if (rc) return sticky(g, rc);
+        bhpp_model* o = new (std::nothrow) bhpp_model{h, m};
+        if (!o) {
+            bhpp::model_free(m);
+            return BHPP_OUT_OF_MEMORY;
+        }
+        *out = o;
+        return BHPP_OK;
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_model_params(bhpp_model* m, float* get_out, const float* set_in, double* c_out, double* sigma_out) {
+    if (!m || !m->m) return BHPP_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(m->h->g->mu);
+    if (get_out) {
+        bhpp_status rc = bhpp::model_get_params(m->m, get_out);
+        if (rc) return rc;
+    }
+    if (set_in) {
+        for (int64_t i = 0; i < bhpp::model_num_params(); ++i)
+            if (!std::isfinite(set_in[i])) return BHPP_INVALID_ARG;
+        bhpp_status rc = bhpp::model_set_params(m->m, set_in);
+        if (rc) return rc;
+    }
+    double c = 0.0, sg = 0.0;
+    bhpp::model_scales(m->m, &c, &sg);
+    if (c_out) *c_out = c;
+    if (sigma_out) *sigma_out = sg;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_model_features(bhpp_model* m, float* out, void* hip_stream) {
+    if (!m || !m->m || !out) return BHPP_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(m->h->g->mu);
+    return bhpp::model_features(m->m, out, stream_of(hip_stream));
+}
+
+static bool valid_nodes(const Graph* g, int32_t n, const int32_t* ids) {
+    for (int32_t i = 0; i < n; ++i)
+        if (ids[i] < 0 || ids[i] >= g->nu || !(g->h_ws_u[ids[i]] > 0.0)) return false;
+    return true;
+}
+
+bhpp_status bhpp_model_loss_grad(bhpp_model* m, int32_t n_src, const int32_t* src, int32_t n_cand,
+                                 const int32_t* cand, const float* targets, double* loss_out, float* grad_out) {
+    if (!m || !m->m || n_src < 1 || n_cand < 1 || !src || !cand || !targets || !loss_out) return BHPP_INVALID_ARG;
+    Graph* g = m->h->g;
+    if (!valid_nodes(g, n_src, src) || !valid_nodes(g, n_cand, cand)) return BHPP_OUT_OF_RANGE;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        return sticky(g, bhpp::model_loss_grad(m->m, n_src, src, n_cand, cand, targets, loss_out, grad_out));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_model_train(bhpp_model* m, int32_t n_src, const int32_t* src, int32_t M, const int32_t* ids,
+                             const float* vals, int32_t steps, int32_t batch_src, int32_t batch_cand, double lr,
+                             uint64_t seed, float* loss_out) {
+    if (!m || !m->m || n_src < 1 || M < 1 || !src || !ids || !vals || steps < 0 || batch_src < 1 ||
+        batch_cand < 1 || !(lr > 0.0) || !std::isfinite(lr))
+        return BHPP_INVALID_ARG;
+    Graph* g = m->h->g;
+    if (!valid_nodes(g, n_src, src)) return BHPP_OUT_OF_RANGE;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        return sticky(g, bhpp::model_train(m->m, n_src, src, M, ids, vals, steps, batch_src, batch_cand, lr, seed,
+                                           loss_out));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_model_embed(bhpp_model* m) {
+    if (!m || !m->m) return BHPP_INVALID_ARG;
+    Graph* g = m->h->g;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        return sticky(g, bhpp::model_embed(m->m));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+void bhpp_model_free(bhpp_model* m) {
+    if (!m) return;
+    if (m->m) {
+        std::lock_guard<std::mutex> lock(m->h->g->mu);
+        bhpp::model_free(m->m);
+    }
+    delete m;
+}
+
+bhpp_status bhpp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, int32_t trans_a, const uint16_t* B,
+                           int32_t trans_b, float* C, void* hip_stream) {
+    if (M < 1 || N < 1 || K < 1 || !A || !B || !C) return BHPP_INVALID_ARG;
+    return bhpp::gemm_test(M, N, K, A, trans_a, B, trans_b, C, stream_of(hip_stream));
 }
 
 void bhpp_free_graph(bhpp_graph* h) {

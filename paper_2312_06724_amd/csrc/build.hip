@@ -240,7 +240,7 @@ void free_tiles(TileSet* ts) {
 void free_graph(Graph* g) {
     if (!g) return;
     void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u, g->end_bits_u, g->end_bits_v,
-                    g->inv_ws_u_d, g->inv_ws_v_d, g->perm_u, g->iperm_u, g->x_rp_u, g->x_ci_u, g->x_w_u,
+                    g->inv_ws_u_d, g->inv_ws_v_d, g->perm_u, g->iperm_u, g->iperm_v, g->x_rp_u, g->x_ci_u, g->x_w_u,
                     g->x_rp_v, g->x_ci_v, g->x_w_v, g->x_ws_u, g->x_ws_v};
     for (void* p : ptrs) hipFree(p);
     free_tiles(&g->tiles_u);
@@ -410,6 +410,8 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
     if (!sort_keys(tmp, dk0, dk1, nv, 64, s)) return BHPP_DEVICE_ERROR;
     hipLaunchKernelGGL(k_perm_from_keys, grid_for(nv), dim3(256), 0, s, nv, dk1, iperm_v, perm_v);
     BHPP_HIP(hipGetLastError());
+    BHPP_HIP(hipMalloc((void**)&g->iperm_v, sizeof(int32_t) * nv));
+    BHPP_HIP(hipMemcpyAsync(g->iperm_v, iperm_v, sizeof(int32_t) * nv, hipMemcpyDeviceToDevice, s));
 
     // 5. internal adjacency: relabel, then sort each direction
     int32_t* iu = tmp.get<int32_t>(m);

@@ -91,7 +91,13 @@ struct ColState {
     int32_t fresh;
     int32_t src_row;     // internal id of the source
     int32_t qid;         // index of the query in the caller's arrays, -1 if none
-    int32_t pad;
+    // warm start: signed residues; the combine uses pi_b as SS-Push returned it,
+    // whose forward image the update stores in SNAP in the sweep after (snap)
+    int32_t warm;
+    int32_t snap;
+    int32_t fell_back;   // a warm start was no better than the cold start: ran cold
+    double res_l1;       // sum_x |r_f(x)| of the warm start
+    double res_max;      // max_x |r(x)|
 };
 
 struct Workspace {
@@ -109,11 +115,23 @@ struct Workspace {
     ColState* st = nullptr;      // [cols]
     int32_t* n_active = nullptr; // device counter of unfinished sources
     int32_t* h_active = nullptr; // pinned host mirror
+    void* SNAP = nullptr;        // [n_u][cols] warm starts: ACC when SS-Push returned (allocated on demand)
     void* scores = nullptr;      // [cols][n_u]: G during sweeps, row-major score scratch for top-k
     int32_t* ids_tmp = nullptr;  // [cols][kTopkTmpK] top-k scratch
     void* vals_tmp = nullptr;
     int32_t* ex_tmp = nullptr;   // [cols] excluded id per exported row
     size_t bytes = 0;
+    // warm starts: an FP64 block that applies the two-hop operator to the
+    // predictions of newly admitted queries (allocated on demand)
+    int wcols = 0;
+    void *wY = nullptr, *wS = nullptr, *wG = nullptr, *wQ = nullptr, *wpartA = nullptr, *wpartB = nullptr;
+    int32_t* wpartA_any = nullptr;
+    double* wred = nullptr;
+    ColState* wst = nullptr;
+    int32_t* wn_active = nullptr;
+    float* wP = nullptr;         // [n_u][wcols] predictions
+    double* wres = nullptr;      // [2][wcols][blocks] residual norms per block
+    int32_t* wcol_ids = nullptr; // [64] block column of each new query
     // sweep chunks captured as HIP graphs (one per column count), replayed per chunk
     hipGraphExec_t chunk_exec[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
@@ -133,6 +151,7 @@ struct Graph {
     uint64_t* end_bits_v = nullptr;
     int32_t* perm_u = nullptr;   // external U id -> internal
     int32_t* iperm_u = nullptr;  // internal -> external
+    int32_t* iperm_v = nullptr;  // internal V id -> external
     TileSet tiles_u, tiles_v;
     // external-order copies (BHPP_BUILD_KEEP_EXTERNAL)
     int64_t* x_rp_u = nullptr; int32_t* x_ci_u = nullptr; void* x_w_u = nullptr;
@@ -178,7 +197,9 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
                         hipStream_t s, Graph** out);
 void free_graph(Graph* g);
 bhpp_status compute_lambda(Graph* g, double alpha, int32_t tau, hipStream_t s, double* lambda_out);
-bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const double* eps, double alpha,
+struct Model;
+bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t n,
+                        const int32_t* src_ext, const double* eps, double alpha,
                         double lambda, void* scores_out, int32_t k, int32_t exclude_self,
                         int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, hipStream_t s);
 bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
@@ -187,12 +208,29 @@ bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s);
 bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s);
 size_t workspace_bytes(const Graph* g, int cols);
 struct Server;
-bhpp_status server_create(Graph* g, int max_width, double mem_budget, double alpha, double lambda, int k, int excl,
-                          Server** out);
+bhpp_status server_create(Graph* g, Model* model, int max_width, double mem_budget, double alpha, double lambda, int k,
+                          int excl, Server** out);
 bhpp_status server_submit(Server* sv, int32_t src, double eps, int64_t tag);
-bhpp_status server_poll(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st, int32_t* n_out);
+bhpp_status server_poll(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st,
+                        bhpp_warm_stats* wst, int32_t* n_out);
 void server_info(Server* sv, bhpp_server_summary* out);
 void server_destroy(Server* sv);
+bhpp_status model_create(Graph* g, uint64_t seed, Model** out);
+void model_free(Model* m);
+int64_t model_num_params();
+bhpp_status model_set_params(Model* m, const float* host);
+bhpp_status model_get_params(Model* m, float* host);
+void model_scales(const Model* m, double* c, double* sigma);
+bhpp_status model_features(Model* m, float* out_ext, hipStream_t s);
+bhpp_status model_loss_grad(Model* m, int n_src, const int32_t* src, int n_cand, const int32_t* cand,
+                            const float* target, double* loss, float* grad_host);
+bhpp_status model_train(Model* m, int n_src, const int32_t* src, int M, const int32_t* ids, const float* vals,
+                        int steps, int batch_src, int batch_cand, double lr, uint64_t seed, float* loss_out);
+bhpp_status model_embed(Model* m);
+bool model_ready(const Model* m);
+bhpp_status model_predict(Model* m, const int32_t* src_rows_host, int n, int cols, float* out, hipStream_t s);
+bhpp_status gemm_test(int M, int N, int K, const uint16_t* A, int trans_a, const uint16_t* B, int trans_b, float* C,
+                      hipStream_t s);
 bhpp_status set_launch_config(Graph* g, const int* cfg);
 bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts);
 void free_workspace(Workspace& w);

@@ -69,14 +69,10 @@ static Geometry geometry(const Graph* g) {
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
-template <typename VT>
-__device__ __forceinline__ bool select_push(int rule, VT y, VT yw, VT kss, VT kpi) {
-    // yw = y / ws(x) (0 for isolated x)
-    return rule == RULE_SS ? (yw > kss) : rule == RULE_PI ? (y > kpi) : rule == RULE_ALL ? (y > VT(0)) : false;
-}
-
-// Branch-free form of select_push for the inner loops: the rule of a lane
-// becomes (use y/ws(x) or y, threshold); RULE_NONE gets an infinite threshold.
+// Push test of a lane's source: the rule becomes (compare y/ws(x) or y,
+// threshold); RULE_NONE gets an infinite threshold. Residues of a warm-started
+// query are signed, so callers pass |y| and |y/ws(x)| (cold-start residues are
+// never negative, for them this is the plain test).
 template <typename VT>
 struct PushTest {
     bool by_ws;
@@ -188,10 +184,10 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
             if (slot == 0 && valid) {
                 if (T.slot >= 0) {
                     p.part[(size_t)T.slot * COLS + col] = acc;
-                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc > VT(0) ? 1 : 0;
+                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc != VT(0) ? 1 : 0;
                 } else {
                     p.OUT[(size_t)row * COLS + col] = acc;
-                    if (SIDE_A && acc > VT(0)) np += (double)(e1 - e0);
+                    if (SIDE_A && acc != VT(0)) np += (double)(e1 - e0);
                 }
             }
         }
@@ -250,12 +246,12 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
                         if (j + 1 == rend) {                 // last entry of the row: flush
                             if (split) {
                                 p.part[(size_t)T.slot * COLS + col] = acc;
-                                if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc > VT(0) ? 1 : 0;
+                                if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc != VT(0) ? 1 : 0;
                             } else {
                                 const size_t idx = (size_t)row * COLS + col;
                                 if (ns) st_nt(&p.OUT[idx], acc); else p.OUT[idx] = acc;
                                 const int64_t rend_abs = cb + rend;
-                                if (SIDE_A && acc > VT(0)) np += (double)(rend_abs - rbeg);
+                                if (SIDE_A && acc != VT(0)) np += (double)(rend_abs - rbeg);
                                 rbeg = rend_abs;
                             }
                             acc = VT(0);
@@ -342,7 +338,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
                 if (seg == 0) sum += carry;
                 if ((mask[u] >> lane) & 1ull) {
                     p.OUT[(size_t)(row + seg)] = sum;
-                    if (SIDE_A && sum > VT(0)) {
+                    if (SIDE_A && sum != VT(0)) {
                         const int64_t beg = seg == 0 ? open_begin : cb + start;
                         np += (double)(cb + lane + 1 - beg);
                     }
@@ -363,7 +359,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
             for (int m = 1; m < kWave; m <<= 1) part += __shfl_xor(part, m);
             if (lane == 0) {
                 p.part[T.slot] = part;
-                if (SIDE_A) p.part_any[T.slot] = part > VT(0) ? 1 : 0;
+                if (SIDE_A) p.part_any[T.slot] = part != VT(0) ? 1 : 0;
             }
         }
     }
@@ -453,7 +449,7 @@ __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ 
         for (int k = 0; k < U; ++k) {
             const size_t i = i0 + k * stride;
             const VT yw = y[k] * iw[k];
-            if (i < n) S[i] = test(y[k], yw) ? yw : VT(0);
+            if (i < n) S[i] = test(fabs(y[k]), fabs(yw)) ? yw : VT(0);
         }
     }
 }
@@ -467,13 +463,16 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
                                                         const VT* __restrict__ G, const VT* __restrict__ inv_ws,
                                                         const int32_t* __restrict__ deg, int32_t n_rows,
                                                         const ColState* st, const int32_t* n_active, double* red,
-                                                        int n_part, int red_slot) {
+                                                        int n_part, int red_slot, VT* __restrict__ SNAP) {
     __shared__ double sh[kPassThreads];
     if (*n_active == 0) return;
     const int col = threadIdx.x & (COLS - 1);
     const ColState& cs = st[col];
     const PushTest<VT> test(cs.ruleB, (VT)cs.k_ss, (VT)cs.k_pi);
     const int convert = cs.convert;
+    // warm start: combine with pi_b as SS-Push left it (the host never marks a
+    // column warm in a block without SNAP; the check only keeps a slip in bounds)
+    const bool warm = cs.warm != 0 && SNAP != nullptr, snap = warm && cs.snap != 0;
     const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
     const VT one_minus_alpha = VT(1) - alpha;
     const bool fresh = cs.fresh != 0;
@@ -501,20 +500,25 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
             if (d[k] == 0) continue;                          // isolated or past the end: untouched
             const size_t i = i0 + k * stride;
             const VT yw = y[k] * iw[k];
-            const bool sel = test(y[k], yw);
+            const bool sel = test(fabs(y[k]), fabs(yw));
             const VT s = sel ? y[k] : VT(0);
             VT acc = a[k];
-            if (convert) acc = acc * (VT(1) + ws_src * iw[k]);   // Eq. (fppr) + pi_b: ACC -> beta' part
+            if (snap) SNAP[i] = acc;                              // forward image of pi_b when SS-Push returned
+            if (convert) {
+                // Eq. (fppr) plus the backward part of Alg. 5's combine: ACC -> beta' part
+                if (warm) acc = acc + ws_src * iw[k] * (snap ? acc : SNAP[i]);
+                else acc = acc * (VT(1) + ws_src * iw[k]);
+            }
             acc += alpha * s;
             const VT yn = (y[k] - s) + one_minus_alpha * g[k];
             Y[i] = yn;
             ACC[i] = acc;
-            const VT tn = yn * iw[k];
+            const VT tn = fabs(yn * iw[k]), ya = fabs(yn);
             r[RED_NP] += sel ? (double)d[k] : 0.0;
             r[RED_CNT_SS] += (tn > kss) ? 1.0 : 0.0;
             r[RED_SUM_R] += (double)tn;
-            r[RED_CNT_PI] += (yn > kpi) ? 1.0 : 0.0;
-            r[RED_SUM_Y] += (double)yn;
+            r[RED_CNT_PI] += (ya > kpi) ? 1.0 : 0.0;
+            r[RED_SUM_Y] += (double)ya;
         }
     }
 #pragma unroll
@@ -536,8 +540,9 @@ __device__ void set_rules(ColState& s, int mode, int ra, int rb, int conv) {
 __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
     s.np_ss = s.np;
     s.sum_r_ss = sum_r;
-    s.gamma = R[RED_SUM_Y];     // Eq. (gamma): sum_x ws(x)/ws(u) r(x) = sum_x y(x)
+    s.gamma = R[RED_SUM_Y];     // Eq. (gamma): sum_x ws(x)/ws(u) |r(x)| = sum_x |y(x)|
     s.np = 0.0;                 // Algorithm 4 repeats Algorithm 3 from its line 3 (n_p <- 0)
+    s.snap = s.warm;            // a warm start keeps pi_b as it is now for the combine
     if (R[RED_CNT_PI] == 0.0) {
         // the first selective iteration would push nothing and Eq. (fwd-eps)
         // would hold: return pi_f from Eq. (fppr)
@@ -551,11 +556,12 @@ __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
 
 __device__ void control_update(ColState& s, const double* R, int32_t* n_active) {
     s.fresh = 0;   // after its first sweep a column holds its own query's Y and ACC
+    s.snap = 0;    // the snapshot (if any) was taken by the sweep that just ran
     const int m = s.mode;
     if (m == MODE_DONE) return;
     s.steps += 1;
-    const double sum_r = R[RED_SUM_R] * s.ws_src;     // sum_x r(x)
-    const double sum_y = R[RED_SUM_Y];                // sum_x r_f(x)
+    const double sum_r = R[RED_SUM_R] * s.ws_src;     // sum_x |r(x)|
+    const double sum_y = R[RED_SUM_Y];                // sum_x |r_f(x)|
     const bool ss_stop = (R[RED_CNT_SS] == 0.0) || (sum_r <= s.eps_b);
     switch (m) {
         case MODE_SS_SEL:
@@ -674,6 +680,91 @@ __global__ __launch_bounds__(256) void k_extract(const VT* ACC, const int32_t* p
 }
 
 // ---------------------------------------------------------------------------
+// Warm start of newly admitted queries (columns cols[j], j < m). With the
+// prediction p = ACC start (forward image of pi_b = y) and G the two-hop image
+// of p computed in FP64, the signed residue of Lemma 1 in forward coordinates
+// is y0 = e_src - (p - (1-alpha) G) / alpha. Per column the kernel also
+// reduces sum_x |y0| (= sum |r_f|) and max_x ws(u)/ws(x) |y0| (= max |r|) on
+// the stored values.
+// ---------------------------------------------------------------------------
+__global__ void k_warm_load(const float* P, double* Y, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) Y[i] = (double)P[i];
+}
+
+template <int COLS, typename VT>
+__global__ __launch_bounds__(kPassThreads) void k_warm_finish(const float* P, const double* G, int ct, int m,
+                                                             const int32_t* cols, const ColState* st,
+                                                             const double* inv_ws, const int32_t* deg, int32_t nu,
+                                                             VT* Y, VT* ACC, double* res) {
+    __shared__ double s1[kPassThreads], s2[kPassThreads];
+    const int j = threadIdx.x % ct;    // ct is a power of two <= 64: it divides the block
+    const int per = kPassThreads / ct;
+    double l1 = 0.0, mx = 0.0;
+    if (j < m) {
+        const int c = cols[j];
+        const double alpha = st[c].alpha, wsu = st[c].ws_src;
+        const int32_t src = st[c].src_row;
+        for (int32_t x = blockIdx.x * per + threadIdx.x / ct; x < nu; x += gridDim.x * per) {
+            const size_t ij = (size_t)x * ct + j;
+            VT yv = VT(0), pv = VT(0);
+            if (deg[x] > 0) {
+                const double p = (double)P[ij];
+                yv = (VT)((x == src ? 1.0 : 0.0) - (p - (1.0 - alpha) * G[ij]) / alpha);
+                pv = (VT)p;
+                l1 += fabs((double)yv);
+                mx = fmax(mx, wsu * inv_ws[x] * fabs((double)yv));
+            }
+            Y[(size_t)x * COLS + c] = yv;
+            ACC[(size_t)x * COLS + c] = pv;
+        }
+    }
+    s1[threadIdx.x] = l1;
+    s2[threadIdx.x] = mx;
+    __syncthreads();
+    if ((int)threadIdx.x < ct) {
+        double a = 0.0, b = 0.0;
+        for (int t = threadIdx.x; t < kPassThreads; t += ct) {
+            a += s1[t];
+            b = fmax(b, s2[t]);
+        }
+        res[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = a;
+        res[((size_t)ct + threadIdx.x) * gridDim.x + blockIdx.x] = b;
+    }
+}
+
+// Caller-given starts (row q of starts, caller ids, forward coordinates:
+// estimates of pi(u, x)) of the new columns into P [n_u][ct] (internal rows).
+template <typename T>
+__global__ void k_starts_gather(const T* starts, int32_t nu, const int32_t* qids, const int32_t* iperm, int ct,
+                                int m, float* P) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)nu * ct) return;
+    const int32_t x = (int32_t)(i / ct);
+    const int j = (int)(i % ct);
+    P[i] = j < m ? (float)starts[(size_t)qids[j] * nu + iperm[x]] : 0.0f;
+}
+
+// Keep a warm start only if it beats the cold start (sum |r_f| < 1 and
+// max |r| < 1, the cold start's values); otherwise the column restarts cold.
+__global__ void k_warm_decide(ColState* st, const double* res, int ct, int m, const int32_t* cols, int nblk) {
+    const int j = threadIdx.x;
+    if (j >= m) return;
+    double l1 = 0.0, mx = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        l1 += res[(size_t)j * nblk + b];
+        mx = fmax(mx, res[((size_t)ct + j) * nblk + b]);
+    }
+    ColState& c = st[cols[j]];
+    c.res_l1 = l1;
+    c.res_max = mx;
+    const bool fb = !(l1 < 1.0 && mx < 1.0);
+    c.fell_back = fb ? 1 : 0;
+    c.warm = fb ? 0 : 1;
+    c.fresh = fb ? 1 : 0;     // a cold restart reads y = e_src, ACC = 0 in its first sweep
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 template <typename VT>
@@ -706,6 +797,7 @@ struct Block {
     ColState* st;
     int32_t* n_active;
     int32_t* h_active;
+    void* SNAP;          // warm starts only (else null)
 };
 
 template <typename VT, typename WT, bool SIDE_A>
@@ -761,8 +853,11 @@ static double launch_bytes(const Graph* g, int cols, int kind) {
     return (double)g->nu * (vt + 2.0 * cols * vt);   // select: 1/ws_u, read Y, write S
 }
 
+// The V-side half and the U-side gather of one sweep: select, gather A and its
+// fix-up, gather B and its fix-up (G = the two-hop image of S). `prof` adds
+// HIP-event timing when profiling is on.
 template <int COLS, typename VT, typename WT>
-static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipStream_t s) {
+static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_t s, bool prof) {
     GatherArgs<VT, WT> A;
     A.tiles = g->tiles_v.tiles;
     A.n_tiles = g->tiles_v.n_tiles;
@@ -789,13 +884,16 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     B.part = as<VT>(b.partB);
     B.part_any = nullptr;
     B.end_bits = g->end_bits_u;
-    hipEvent_t ev[2];
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto pb = [&](int kind) {
+        if (prof) prof_begin(g, s, kind, launch_bytes<VT, WT>(g, COLS, kind), ev);
+    };
 
-    prof_begin(g, s, 3, launch_bytes<VT, WT>(g, COLS, 3), ev);
+    pb(3);
     hipLaunchKernelGGL((k_select<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.S),
                        inv_ws_u_of<VT>(g), g->nu, b.st, b.n_active);
     prof_end(g, s, ev);
-    prof_begin(g, s, 0, launch_bytes<VT, WT>(g, COLS, 0), ev);
+    pb(0);
     A.red_slot = G.offA;
     if (COLS == 64)
         launch_gather64<VT, WT, true>(g->inflight, G.blkA, s, A);
@@ -808,7 +906,7 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     A.red_slot = G.offFA;
     hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kPassThreads), 0, s, A,
                        g->tiles_v.split, g->tiles_v.n_split);
-    prof_begin(g, s, 1, launch_bytes<VT, WT>(g, COLS, 1), ev);
+    pb(1);
     B.red_slot = 0;
     if (COLS == 64)
         launch_gather64<VT, WT, false>(g->inflight, G.blkB, s, B);
@@ -820,9 +918,16 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     if (g->tiles_u.n_split > 0)
         hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
                            g->tiles_u.split, g->tiles_u.n_split);
+}
+
+template <int COLS, typename VT, typename WT>
+static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipStream_t s) {
+    launch_front<COLS, VT, WT>(g, b, G, s, true);
+    hipEvent_t ev[2] = {nullptr, nullptr};
     prof_begin(g, s, 2, launch_bytes<VT, WT>(g, COLS, 2), ev);
     hipLaunchKernelGGL((k_update<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.ACC),
-                       as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part, G.offU);
+                       as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part, G.offU,
+                       as<VT>(b.SNAP));
     prof_end(g, s, ev);
     hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(256), 0, s, b.st, b.red, G.n_part, G.offU, b.n_active);
     BHPP_HIP(hipGetLastError());
@@ -930,21 +1035,135 @@ static int log2i(int x) {
     return l;
 }
 
+static bhpp_status ensure_warm(Graph* g, Workspace& w, int ct, hipStream_t s) {
+    if (!w.SNAP) {
+        if (hipMalloc(&w.SNAP, (size_t)g->nu * w.cols * w.elem) != hipSuccess) {
+            (void)hipGetLastError();
+            return BHPP_OUT_OF_MEMORY;
+        }
+        w.bytes += (size_t)g->nu * w.cols * w.elem;
+    }
+    if (w.wcols >= ct) return BHPP_OK;
+    void* old[] = {w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB, w.wpartA_any, w.wred, w.wst, w.wn_active, w.wP,
+                   w.wres, w.wcol_ids};
+    for (void* p : old) hipFree(p);
+    w.wcols = 0;
+    const Geometry G = geometry(g);
+    const size_t c = (size_t)ct, nu = (size_t)g->nu, nv = (size_t)g->nv;
+    auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
+    const bool ok = A(&w.wY, nu * c * 8) && A(&w.wS, nu * c * 8) && A(&w.wG, nu * c * 8) && A(&w.wQ, nv * c * 8) &&
+                    A(&w.wpartA, (size_t)g->tiles_v.n_slots * c * 8) &&
+                    A((void**)&w.wpartA_any, (size_t)g->tiles_v.n_slots * c * 4) &&
+                    A(&w.wpartB, (size_t)g->tiles_u.n_slots * c * 8) &&
+                    A((void**)&w.wred, (size_t)kNumRed * c * G.n_part * 8) &&
+                    A((void**)&w.wst, sizeof(ColState) * c) && A((void**)&w.wn_active, 64) &&
+                    A((void**)&w.wP, nu * c * 4) && A((void**)&w.wres, 2 * c * kUpdateBlocks * 8) &&
+                    A((void**)&w.wcol_ids, (size_t)kMaxCols * 4);
+    if (!ok) {
+        (void)hipGetLastError();
+        return BHPP_OUT_OF_MEMORY;
+    }
+    w.wcols = ct;
+    (void)s;
+    return BHPP_OK;
+}
+
+template <int CT, typename WT>
+static void warm_front(Graph* g, Workspace& w, hipStream_t s) {
+    const Block tb{w.wY, nullptr, w.wS, w.wG, w.wQ, w.wpartA, w.wpartA_any, w.wpartB, w.wred, w.wst, w.wn_active,
+                   nullptr, nullptr};
+    launch_front<CT, double, WT>(g, tb, geometry(g), s, false);
+}
+
+// Seed the block columns `cols` (their states already uploaded) from the
+// model's predictions: ACC = p, Y = the signed residue, then keep or reject
+// each start on the device.
+// Where warm starts come from: the model, or starts given by the caller
+// (device [n_query][n_u] of the graph dtype, row = query index).
+struct WarmSource {
+    Model* model = nullptr;
+    const void* starts = nullptr;
+    bool any() const { return model != nullptr || starts != nullptr; }
+};
+
+template <int COLS, typename VT, typename WT>
+static bhpp_status warm_init(Graph* g, const WarmSource& src, Workspace& w, const Block& b,
+                             const std::vector<int32_t>& cols, const std::vector<ColState>& hs, hipStream_t s) {
+    const int m = (int)cols.size();
+    if (m == 0) return BHPP_OK;
+    const int ct = next_pow2(m);
+    bhpp_status rc = ensure_warm(g, w, ct, s);
+    if (rc) return rc;
+    if (src.model) {
+        std::vector<int32_t> rows(m);
+        for (int j = 0; j < m; ++j) rows[j] = hs[cols[j]].src_row;
+        rc = model_predict(src.model, rows.data(), m, ct, w.wP, s);
+        if (rc) return rc;
+    } else {
+        std::vector<int32_t> q(m);
+        for (int j = 0; j < m; ++j) q[j] = hs[cols[j]].qid;
+        BHPP_HIP(hipMemcpyAsync(w.wcol_ids, q.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+        const size_t n = (size_t)g->nu * ct;
+        hipLaunchKernelGGL(k_starts_gather<VT>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           (const VT*)src.starts, g->nu, w.wcol_ids, g->iperm_u, ct, m, w.wP);
+        BHPP_HIP(hipStreamSynchronize(s));   // q is read by the copy
+    }
+    const size_t n = (size_t)g->nu * ct;
+    hipLaunchKernelGGL(k_warm_load, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.wP, (double*)w.wY, n);
+    std::vector<ColState> ts(ct);
+    for (ColState& c : ts) {
+        done_state(c);
+        c.mode = MODE_POWER;
+        c.ruleA = c.ruleB = RULE_ALL;
+    }
+    const int32_t one = 1;
+    BHPP_HIP(hipMemcpyAsync(w.wst, ts.data(), sizeof(ColState) * ct, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.wn_active, &one, 4, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.wcol_ids, cols.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+    switch (ct) {
+        case 1: warm_front<1, WT>(g, w, s); break;
+        case 2: warm_front<2, WT>(g, w, s); break;
+        case 4: warm_front<4, WT>(g, w, s); break;
+        case 8: warm_front<8, WT>(g, w, s); break;
+        case 16: warm_front<16, WT>(g, w, s); break;
+        case 32: warm_front<32, WT>(g, w, s); break;
+        default: warm_front<64, WT>(g, w, s); break;
+    }
+    hipLaunchKernelGGL((k_warm_finish<COLS, VT>), dim3(kUpdateBlocks), dim3(kPassThreads), 0, s, w.wP,
+                       (const double*)w.wG, ct, m, w.wcol_ids, b.st, g->inv_ws_u_d, g->deg_u, g->nu, as<VT>(b.Y),
+                       as<VT>(b.ACC), w.wres);
+    hipLaunchKernelGGL(k_warm_decide, dim3(1), dim3(64), 0, s, b.st, w.wres, ct, m, w.wcol_ids, kUpdateBlocks);
+    BHPP_HIP(hipGetLastError());
+    // the host vectors above must outlive their copies
+    BHPP_HIP(hipStreamSynchronize(s));
+    return BHPP_OK;
+}
+
+static void fill_warm(const ColState& c, bhpp_warm_stats& o) {
+    o.res_l1 = c.res_l1;
+    o.res_max = c.res_max;
+    o.fell_back = c.fell_back;
+    o.reserved = 0;
+}
+
 // Queries are fed to a block of COLS columns from a queue. When enough
 // columns have finished (or the queue is empty and all have), their beta'
 // rows are extracted, their top-k computed, and the free columns take the
 // next queries; a reused column needs no reset pass (ColState::fresh).
 template <int COLS, typename VT, typename WT>
-static bhpp_status run_sched(Graph* g, int n, const int32_t* src_ext, const double* eps, double alpha,
-                             double lambda, void* scores_out, int k, int exclude_self, int32_t* ids_out,
-                             void* vals_out, bhpp_query_stats* stats, hipStream_t s) {
+static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* wstats, int n, const int32_t* src_ext,
+                             const double* eps, double alpha, double lambda, void* scores_out, int k,
+                             int exclude_self, int32_t* ids_out, void* vals_out, bhpp_query_stats* stats,
+                             hipStream_t s) {
     Workspace& w = g->ws;
-    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
+                  w.SNAP};
     const Geometry G = geometry(g);
     const size_t nu = (size_t)g->nu, e = (size_t)g->elem;
     std::vector<ColState> hs(COLS);
     for (int c = 0; c < COLS; ++c) done_state(hs[c]);
     int next = 0;
+    std::vector<int32_t> newcols;   // columns given a query since the last upload (warm starts)
     auto assign = [&](int c) {
         const int q = next++;
         const int32_t u = src_ext[q];
@@ -952,6 +1171,7 @@ static bhpp_status run_sched(Graph* g, int n, const int32_t* src_ext, const doub
         hs[c].fresh = 1;
         hs[c].src_row = g->h_perm_u[u];
         hs[c].qid = q;
+        if (warm.any()) newcols.push_back(c);
     };
     for (int c = 0; c < COLS && next < n; ++c) assign(c);
     auto upload = [&]() -> bhpp_status {
@@ -960,6 +1180,11 @@ static bhpp_status run_sched(Graph* g, int n, const int32_t* src_ext, const doub
         w.h_active[2] = act;
         BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
         BHPP_HIP(hipMemcpyAsync(w.n_active, &w.h_active[2], sizeof(int32_t), hipMemcpyHostToDevice, s));
+        if (warm.any() && !newcols.empty()) {
+            const bhpp_status r = warm_init<COLS, VT, WT>(g, warm, w, b, newcols, hs, s);
+            newcols.clear();
+            if (r) return r;
+        }
         return BHPP_OK;
     };
     bhpp_status rc = upload();
@@ -1036,6 +1261,7 @@ static bhpp_status run_sched(Graph* g, int n, const int32_t* src_ext, const doub
                                             e * k, hipMemcpyDeviceToDevice, s));
                 }
                 if (stats) fill_stats(hs[cols[j]], stats[q]);
+                if (wstats) fill_warm(hs[cols[j]], wstats[q]);
                 hs[cols[j]].qid = -1;
                 --live;
                 if (next < n) {
@@ -1057,19 +1283,22 @@ static bhpp_status run_sched(Graph* g, int n, const int32_t* src_ext, const doub
 }
 
 template <typename VT, typename WT>
-static bhpp_status run_sched_dispatch(Graph* g, int cols, int n, const int32_t* src, const double* eps, double alpha,
-                                      double lambda, void* scores, int k, int ex, int32_t* ids, void* vals,
-                                      bhpp_query_stats* st, hipStream_t s) {
+static bhpp_status run_sched_dispatch(Graph* g, const WarmSource& model, bhpp_warm_stats* ws, int cols, int n,
+                                      const int32_t* src, const double* eps, double alpha, double lambda,
+                                      void* scores, int k, int ex, int32_t* ids, void* vals, bhpp_query_stats* st,
+                                      hipStream_t s) {
+#define BHPP_RUN(C) return run_sched<C, VT, WT>(g, model, ws, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s)
     switch (cols) {
-        case 1: return run_sched<1, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
-        case 2: return run_sched<2, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
-        case 4: return run_sched<4, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
-        case 8: return run_sched<8, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
-        case 16: return run_sched<16, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
-        case 32: return run_sched<32, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
-        case 64: return run_sched<64, VT, WT>(g, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
+        case 1: BHPP_RUN(1);
+        case 2: BHPP_RUN(2);
+        case 4: BHPP_RUN(4);
+        case 8: BHPP_RUN(8);
+        case 16: BHPP_RUN(16);
+        case 32: BHPP_RUN(32);
+        case 64: BHPP_RUN(64);
         default: return BHPP_INVALID_ARG;
     }
+#undef BHPP_RUN
 }
 
 void free_workspace(Workspace& w) {
@@ -1079,7 +1308,8 @@ void free_workspace(Workspace& w) {
             x = nullptr;
         }
     void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores,
-                    w.ids_tmp, w.vals_tmp, w.ex_tmp};
+                    w.ids_tmp, w.vals_tmp, w.ex_tmp, w.SNAP, w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB,
+                    w.wpartA_any, w.wred, w.wst, w.wn_active, w.wP, w.wres, w.wcol_ids};
     for (void* p : ptrs) hipFree(p);
     if (w.h_active) hipHostFree(w.h_active);
     w = Workspace{};
@@ -1142,9 +1372,13 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
     return BHPP_OK;
 }
 
-bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const double* eps, double alpha,
-                        double lambda, void* scores_out, int32_t k, int32_t exclude_self, int32_t* topk_ids,
-                        void* topk_vals, bhpp_query_stats* stats, hipStream_t caller) {
+bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t n,
+                        const int32_t* src_ext, const double* eps, double alpha, double lambda, void* scores_out,
+                        int32_t k, int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
+                        hipStream_t caller) {
+    WarmSource warm;
+    warm.model = model;
+    warm.starts = starts;
     if (k > kTopkTmpK) return BHPP_NOT_SUPPORTED;
     if (!g->work) BHPP_HIP(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
     hipStream_t s = g->work;
@@ -1157,11 +1391,11 @@ bhpp_status run_queries(Graph* g, int32_t n, const int32_t* src_ext, const doubl
     bhpp_status rc = ensure_workspace(g, cols, s);
     if (rc == BHPP_OK) {
         if (g->dtype == BHPP_DTYPE_F64)
-            rc = run_sched_dispatch<double, double>(g, cols, n, src_ext, eps, alpha, lambda, scores_out, k,
-                                                    exclude_self, topk_ids, topk_vals, stats, s);
+            rc = run_sched_dispatch<double, double>(g, warm, wstats, cols, n, src_ext, eps, alpha, lambda,
+                                                    scores_out, k, exclude_self, topk_ids, topk_vals, stats, s);
         else
-            rc = run_sched_dispatch<float, float>(g, cols, n, src_ext, eps, alpha, lambda, scores_out, k,
-                                                  exclude_self, topk_ids, topk_vals, stats, s);
+            rc = run_sched_dispatch<float, float>(g, warm, wstats, cols, n, src_ext, eps, alpha, lambda,
+                                                  scores_out, k, exclude_self, topk_ids, topk_vals, stats, s);
     }
     // and the caller's stream waits for the library's work
     if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(caller, ev, 0) != hipSuccess) rc = BHPP_DEVICE_ERROR;
@@ -1241,7 +1475,8 @@ static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out
     bhpp_status rc = ensure_workspace(g, COLS_T, s);
     if (rc) return rc;
     Workspace& w = g->ws;
-    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
+                  w.SNAP};
     const Geometry G = geometry(g);
     std::vector<ColState> hs(COLS_T);
     for (int c = 0; c < COLS_T; ++c) {
@@ -1348,6 +1583,7 @@ bhpp_status set_launch_config(Graph* g, const int* cfg) {
 // ---------------------------------------------------------------------------
 struct Server {
     Graph* g = nullptr;
+    Model* model = nullptr;               // warm starts for admitted requests (nullable)
     Workspace ws;
     int cols = 0, k = 0, excl = 0;
     double alpha = 0.0, lambda = 0.0;
@@ -1375,10 +1611,12 @@ static bhpp_status server_upload(Server* sv) {
 
 template <int COLS, typename VT, typename WT>
 static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st,
-                                    int32_t* n_out) {
+                                    bhpp_warm_stats* wst, int32_t* n_out) {
     Graph* g = sv->g;
     Workspace& w = sv->ws;
-    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active};
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
+                  w.SNAP};
+    std::vector<int32_t> newcols;
     const Geometry G = geometry(g);
     hipStream_t s = sv->s;
     *n_out = 0;
@@ -1395,6 +1633,7 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
             sv->hs[c].qid = c;
             sv->tag[c] = r.tag;
             sv->src[c] = r.src;
+            if (sv->model) newcols.push_back(c);
             dirty = true;
         }
     }
@@ -1402,6 +1641,12 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
         bhpp_status rc = server_upload(sv);
         if (rc) return rc;
         sv->dirty = false;
+        if (!newcols.empty()) {
+            WarmSource ws;
+            ws.model = sv->model;
+            rc = warm_init<COLS, VT, WT>(g, ws, w, b, newcols, sv->hs, sv->s);
+            if (rc) return rc;
+        }
     }
     int live = 0;
     for (int c = 0; c < COLS; ++c) live += sv->hs[c].qid >= 0 ? 1 : 0;
@@ -1442,6 +1687,7 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
         memcpy(ids + (size_t)j * kk, sv->h_ids + (size_t)j * kk, sizeof(int32_t) * kk);
         memcpy((char*)vals + (size_t)j * kk * e, (char*)sv->h_vals + (size_t)j * kk * e, e * kk);
         if (st) fill_stats(sv->hs[c], st[j]);
+        if (wst) fill_warm(sv->hs[c], wst[j]);
         sv->hs[c].qid = -1;
     }
     sv->dirty = true;   // freed columns: the device copy still names their request
@@ -1452,15 +1698,15 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
 
 template <typename VT, typename WT>
 static bhpp_status server_poll_dispatch(Server* sv, int64_t* t, int32_t* i, void* v, bhpp_query_stats* st,
-                                        int32_t* n) {
+                                        bhpp_warm_stats* ws, int32_t* n) {
     switch (sv->cols) {
-        case 1: return server_poll_impl<1, VT, WT>(sv, t, i, v, st, n);
-        case 2: return server_poll_impl<2, VT, WT>(sv, t, i, v, st, n);
-        case 4: return server_poll_impl<4, VT, WT>(sv, t, i, v, st, n);
-        case 8: return server_poll_impl<8, VT, WT>(sv, t, i, v, st, n);
-        case 16: return server_poll_impl<16, VT, WT>(sv, t, i, v, st, n);
-        case 32: return server_poll_impl<32, VT, WT>(sv, t, i, v, st, n);
-        case 64: return server_poll_impl<64, VT, WT>(sv, t, i, v, st, n);
+        case 1: return server_poll_impl<1, VT, WT>(sv, t, i, v, st, ws, n);
+        case 2: return server_poll_impl<2, VT, WT>(sv, t, i, v, st, ws, n);
+        case 4: return server_poll_impl<4, VT, WT>(sv, t, i, v, st, ws, n);
+        case 8: return server_poll_impl<8, VT, WT>(sv, t, i, v, st, ws, n);
+        case 16: return server_poll_impl<16, VT, WT>(sv, t, i, v, st, ws, n);
+        case 32: return server_poll_impl<32, VT, WT>(sv, t, i, v, st, ws, n);
+        case 64: return server_poll_impl<64, VT, WT>(sv, t, i, v, st, ws, n);
         default: return BHPP_INVALID_ARG;
     }
 }
@@ -1476,16 +1722,27 @@ void server_destroy(Server* sv) {
     delete sv;
 }
 
-bhpp_status server_create(Graph* g, int max_width, double mem_budget, double alpha, double lambda, int k, int excl,
-                          Server** out) {
+// device bytes of the warm-start side of a block of `cols` columns: SNAP and
+// the FP64 block that computes the residues of up to `cols` new queries
+static size_t warm_bytes(const Graph* g, int cols) {
+    const Geometry G = geometry(g);
+    const size_t c = (size_t)cols, nu = (size_t)g->nu, nv = (size_t)g->nv;
+    return nu * c * g->elem + nu * c * (3 * 8 + 4) + nv * c * 8 + (size_t)g->tiles_v.n_slots * c * 12 +
+           (size_t)g->tiles_u.n_slots * c * 8 + (size_t)kNumRed * c * G.n_part * 8 + 2 * c * kUpdateBlocks * 8 + 4096;
+}
+
+bhpp_status server_create(Graph* g, Model* model, int max_width, double mem_budget, double alpha, double lambda, int k,
+                          int excl, Server** out) {
+    auto need = [&](int c) { return (double)workspace_bytes(g, c) + (model ? (double)warm_bytes(g, c) : 0.0); };
     int cols = 1;
     while (cols * 2 <= max_width && cols * 2 <= kMaxCols) cols *= 2;
     if (mem_budget > 0.0)
-        while (cols > 1 && (double)workspace_bytes(g, cols) > mem_budget) cols /= 2;
-    if (mem_budget > 0.0 && (double)workspace_bytes(g, cols) > mem_budget) return BHPP_OUT_OF_MEMORY;
+        while (cols > 1 && need(cols) > mem_budget) cols /= 2;
+    if (mem_budget > 0.0 && need(cols) > mem_budget) return BHPP_OUT_OF_MEMORY;
     Server* sv = new (std::nothrow) Server();
     if (!sv) return BHPP_OUT_OF_MEMORY;
     sv->g = g;
+    sv->model = model;
     g->n_servers += 1;
     sv->cols = cols;
     sv->k = k;
@@ -1499,6 +1756,7 @@ bhpp_status server_create(Graph* g, int max_width, double mem_budget, double alp
     bhpp_status rc = BHPP_OK;
     if (hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking) != hipSuccess) rc = BHPP_DEVICE_ERROR;
     if (rc == BHPP_OK) rc = ensure_workspace(g, sv->ws, cols, sv->s);
+    if (rc == BHPP_OK && model) rc = ensure_warm(g, sv->ws, cols, sv->s);
     if (rc == BHPP_OK && (hipHostMalloc((void**)&sv->h_ids, sizeof(int32_t) * (size_t)cols * k) != hipSuccess ||
                           hipHostMalloc(&sv->h_vals, (size_t)g->elem * cols * k) != hipSuccess))
         rc = BHPP_OUT_OF_MEMORY;
@@ -1519,9 +1777,11 @@ bhpp_status server_submit(Server* sv, int32_t src, double eps, int64_t tag) {
     return BHPP_OK;
 }
 
-bhpp_status server_poll(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st, int32_t* n_out) {
-    if (sv->g->dtype == BHPP_DTYPE_F64) return server_poll_dispatch<double, double>(sv, tags, ids, vals, st, n_out);
-    return server_poll_dispatch<float, float>(sv, tags, ids, vals, st, n_out);
+bhpp_status server_poll(Server* sv, int64_t* tags, int32_t* ids, void* vals, bhpp_query_stats* st,
+                        bhpp_warm_stats* wst, int32_t* n_out) {
+    if (sv->g->dtype == BHPP_DTYPE_F64)
+        return server_poll_dispatch<double, double>(sv, tags, ids, vals, st, wst, n_out);
+    return server_poll_dispatch<float, float>(sv, tags, ids, vals, st, wst, n_out);
 }
 
 void server_info(Server* sv, bhpp_server_summary* o) {

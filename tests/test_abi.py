@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "bhpp.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(bhpp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(bhpp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_boundary():
@@ -51,9 +51,18 @@ def test_argument_errors_need_no_device():
     assert L.bhpp_topk(None, 1, 10, 11, None, 0, None, None, None) == -1      # k > n
     assert L.bhpp_query_batch(None, 1, None, None, 0.15, 1e-6, None, 0, 0, None, None, None, None) == -1
     srv = ctypes.c_void_p()
-    assert L.bhpp_server_create(None, 64, 0.0, 0.15, 100, 1, ctypes.byref(srv)) == -1   # no graph
+    assert L.bhpp_server_create(None, None, 64, 0.0, 0.15, 100, 1, ctypes.byref(srv)) == -1   # no graph
     assert L.bhpp_server_submit(None, 0, 1e-6, 0) == -1
     n = ctypes.c_int32(5)
-    assert L.bhpp_server_poll(None, 64, None, None, None, None, ctypes.byref(n)) == -1
+    assert L.bhpp_server_poll(None, 64, None, None, None, None, None, ctypes.byref(n)) == -1
     assert L.bhpp_server_info(None, None) == -1
     L.bhpp_server_destroy(None)                                    # ignored
+    mdl = ctypes.c_void_p()
+    assert L.bhpp_model_create(None, 0, ctypes.byref(mdl)) == -1
+    assert L.bhpp_model_params(None, None, None, None, None) == -1
+    assert L.bhpp_model_embed(None) == -1
+    assert L.bhpp_model_train(None, 1, None, 1, None, None, 1, 1, 1, 1e-3, 0, None) == -1
+    assert L.bhpp_query_batch_warm(None, None, 1, None, None, 0.15, 1e-6, None, 0, 0, None, None, None, None,
+                                   None) == -1
+    assert L.bhpp_gemm_bf16(0, 1, 1, None, 0, None, 0, None, None) == -1
+    L.bhpp_model_free(None)

@@ -66,11 +66,13 @@ def test_gradient_matches_finite_differences():
     Xu, Xx = rng.normal(0, 1, (3, mlp.IN)), rng.normal(0, 1, (5, mlp.IN))
     ws = rng.uniform(1, 5, 5)
     T = rng.uniform(0, 1e-2, (3, 5))
-    c, sigma = 0.05, 1e-2
+    T[1, 2] = T[0, 4] = np.nan                     # unknown targets are left out
+    c, sigma = 0.05, 1e-4
     loss, grad = mlp.loss_and_grad(theta, Xu, Xx, ws, T, c, sigma)
     # the loss is what predict() implies
     p = mlp.predict(theta, Xu, Xx, ws, c)
-    assert abs(loss - (((p - T) / sigma) ** 2).mean()) < 1e-12 * max(1.0, loss)
+    k = np.isfinite(T)
+    assert abs(loss - ((p[k] - T[k]) ** 2 / (T[k] + sigma)).mean()) < 1e-12 * max(1.0, loss)
     # coordinates in every block of both towers
     offs, o = [], 0
     for _ in range(2):
@@ -85,3 +87,29 @@ def test_gradient_matches_finite_differences():
         tm[i] -= h
         fd = (mlp.loss_and_grad(tp, Xu, Xx, ws, T, c, sigma)[0] - mlp.loss_and_grad(tm, Xu, Xx, ws, T, c, sigma)[0]) / (2 * h)
         assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, grad[i])
+
+
+def test_self_prior_matches_dense(small_graph):
+    s = small_graph
+    a = s["wl"].alpha
+    D = mlp.self_prior(s["g"], a)
+    live = s["g"].deg_u > 0
+    ref = a + a * (1 - a) * np.diag(s["P"])
+    assert np.abs(D[live] - ref[live]).max() < 1e-14 and np.all(D[~live] == 0)
+    # a lower bound of pi(u, u) (both dropped terms are non-negative)
+    assert np.all(D[live] <= np.diag(s["Pi"])[live] + 1e-15)
+
+
+def test_extra_term_only_shifts_the_prediction():
+    rng = np.random.default_rng(3)
+    theta = init(2)
+    Xu, Xx = rng.normal(0, 1, (2, mlp.IN)), rng.normal(0, 1, (4, mlp.IN))
+    ws = rng.uniform(1, 5, 4)
+    E = np.zeros((2, 4))
+    E[1, 3] = 0.2
+    p0 = mlp.predict(theta, Xu, Xx, ws, 0.05)
+    p1 = mlp.predict(theta, Xu, Xx, ws, 0.05, E)
+    assert np.array_equal(p1 - p0, E)
+    T = p1.copy()
+    loss, grad = mlp.loss_and_grad(theta, Xu, Xx, ws, T, 0.05, 1e-4, E)
+    assert loss < 1e-20 and np.abs(grad).max() < 1e-12
