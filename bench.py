@@ -102,12 +102,79 @@ def run_large(bh, torch, np):
     return res
 
 
-def run_serving(bh, G, el, wl, rates, duration, np):
+def run_learned(bh, torch, np, G, el, wl, src, n_train, steps, reps):
+    """Learned warm start on the same graph: training data from the plain GPU
+    path (top-64 of beta' plus 64 random entries per source, for n_train
+    uniform sources disjoint from the benchmark's), GPU training, then the
+    benchmark's 64 sources batched and warm-started, beside the no-network
+    ablation (the structural self term alone)."""
+    import synth
+    live = np.nonzero(el.degrees_u() > 0)[0]
+    rng = np.random.default_rng(77)
+    cand = synth.sample_sources(el, n_train + src.size, "uniform", 4242)
+    train = np.setdiff1d(cand, src)[:n_train].astype(np.int32)
+    t0 = time.perf_counter()
+    ids, vals = [], []
+    for i in range(0, train.size, 64):
+        chunk = train[i:i + 64]
+        out = G.query_batch(chunk, wl.eps, k=64, exclude_self=False, scores=True, stats=False)
+        r = torch.from_numpy(rng.choice(live, (chunk.size, 64))).to("cuda")
+        rv = torch.gather(out["scores"], 1, r.long())
+        ii = torch.cat([out["ids"], r.int()], 1).cpu().numpy()
+        vv = torch.cat([out["vals"], rv], 1).cpu().numpy()
+        for a, b in zip(ii, vv):
+            _, keep = np.unique(a, return_index=True)
+            a2 = np.full(128, -1, np.int32)
+            b2 = np.zeros(128, np.float32)
+            a2[:keep.size], b2[:keep.size] = a[keep], b[keep]
+            ids.append(a2)
+            vals.append(b2)
+        del out
+    t_data = time.perf_counter() - t0
+    log(f"learned: training data from {train.size} plain queries in {t_data:.1f}s")
+    t0 = time.perf_counter()
+    M = bh.Model(G, seed=1)
+    losses = M.train(train, np.array(ids), np.array(vals), steps=steps, batch_src=32, batch_cand=4096, lr=5e-4)
+    M.embed()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"learned: {steps} training steps + embedding in {t_train:.1f}s, loss {losses[:50].mean():.3g} -> "
+        f"{losses[-50:].mean():.3g}")
+
+    def timed(model):
+        model_q = lambda: G.query_batch(src, wl.eps, k=wl.k, exclude_self=True, scores=True, stats=True, model=model)
+        model_q()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            o = model_q()
+        torch.cuda.synchronize()
+        qps = src.size * reps / (time.perf_counter() - t1)
+        r = np.array([w["res_l1"] for w in o["warm"]])
+        fb = np.array([w["fell_back"] for w in o["warm"]])
+        return dict(queries_per_s=round(qps, 3), res_l1_median=round(float(np.median(r)), 4),
+                    res_l1_max=round(float(r.max()), 4), fallback_rate=round(float(fb.mean()), 3),
+                    mean_sweeps_per_query=float(np.mean([x["steps"] for x in o["stats"]])))
+
+    learned = timed(M)
+    M0 = bh.Model(G, seed=1)
+    M0.set_params(np.zeros(bh.MODEL_PARAMS, np.float32))
+    M0.embed()
+    ablation = timed(M0)
+    M0.close()
+    log(f"learned: {learned}; self term only: {ablation}")
+    return M, dict(train_sources=int(train.size), train_steps=steps, batch="32 sources x 4096 candidates",
+                   data_s=round(t_data, 1), train_s=round(t_train, 1),
+                   loss_first=float(losses[:50].mean()), loss_last=float(losses[-50:].mean()),
+                   batched_learned=learned, ablation_self_term_only=ablation)
+
+
+def run_serving(bh, G, el, wl, rates, duration, np, model=None):
     """Continuous batching on the resident graph: Poisson arrivals at each rate
     for `duration` seconds, degree-proportional sources, eps uniform on
     {1e-5, 1e-6, 1e-7}, top-k per request. Latency = arrival to result."""
     import synth
-    S = bh.Server(G, k=wl.k)
+    S = bh.Server(G, k=wl.k, model=model)
     # warm-up: capture the sweep chunk once
     warm = synth.sample_sources(el, 4, "degree", 90)
     for i, u in enumerate(warm):
@@ -153,8 +220,9 @@ def run_serving(bh, G, el, wl, rates, duration, np):
         log(f"serve {rate} q/s: {out[-1]}")
         if ok.size < n:   # overloaded: drop what is left before the next rate
             S.close()
-            S = bh.Server(G, k=wl.k)
+            S = bh.Server(G, k=wl.k, model=model)
     res = dict(width=S.width, k=wl.k, resident_bytes=int(S.info()["resident_bytes"]),
+               learned_warm_start=model is not None,
                eps_mix=[1e-5, 1e-6, 1e-7], source_sampling="degree-proportional", duration_s=duration,
                rates=out)
     S.close()
@@ -171,6 +239,9 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--large", action="store_true",
                     help="also run the 100M-edge workload: 1024 degree-proportional sources in one queue-fed block")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--train-sources", type=int, default=2048)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--serve", default="150,250,2000",
                     help="Poisson arrival rates (q/s) for the serving run; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
@@ -263,8 +334,14 @@ def main():
                                      gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
                              for i, k in enumerate(["gather_a", "gather_b", "update", "select"])})
 
+    model, learned = None, None
+    if not args.no_learned:
+        model, learned = run_learned(bh, torch, np, G, el, wl, src, args.train_sources, args.train_steps, 2)
+
     rates = [float(x) for x in args.serve.split(",") if x.strip()]
-    serving = run_serving(bh, G, el, wl, rates, args.serve_seconds, np) if rates else None
+    serving = run_serving(bh, G, el, wl, rates, args.serve_seconds, np, model) if rates else None
+    if model is not None:
+        model.close()
 
     large = run_large(bh, torch, np) if args.large else None
 
@@ -275,7 +352,7 @@ def main():
         cpu = cpu_baseline(el, src, wl, n)
 
     out = {
-        "metric": "BHPP queries/s at eps=1e-6 (64 sources batched, top-100)",
+        "metric": "BHPP queries/s at eps=1e-6 (plain vs batched+learned); HBM GB/s; p99 ms",
         "value": round(qps, 3),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -293,6 +370,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "single_source_qps": round(single_qps, 3) if single_qps else None,
+        "learned": learned,
         "serving": serving,
         "large": large,
         "mean_sweeps_per_query": sweeps,
