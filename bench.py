@@ -221,8 +221,10 @@ def run_serving(bh, G, el, wl, rates, duration, np, model=None):
         if ok.size < n:   # overloaded: drop what is left before the next rate
             S.close()
             S = bh.Server(G, k=wl.k, model=model)
-    res = dict(width=S.width, k=wl.k, resident_bytes=int(S.info()["resident_bytes"]),
-               learned_warm_start=model is not None,
+    inf = S.info()
+    res = dict(width=S.width, k=wl.k, resident_bytes=int(inf["resident_bytes"]),
+               learned_warm_start=model is not None, warm_started=int(inf["warm_started"]),
+               warm_fell_back=int(inf["warm_fell_back"]),
                eps_mix=[1e-5, 1e-6, 1e-7], source_sampling="degree-proportional", duration_s=duration,
                rates=out)
     S.close()

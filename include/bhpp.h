@@ -334,8 +334,10 @@ bhpp_status bhpp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, i
  * width 64 on a 1M x 2M graph is about 1.6 GB in FP32 (plus about 3 GB with a
  * model, for the warm starts). Admission: a request enters the block when a
  * column is free, at the next poll. With a model (nullable; it must have
- * embeddings) every admitted request is warm-started as in
- * bhpp_query_batch_warm; warm_out of the poll (nullable) reports it.
+ * embeddings) admitted requests are warm-started as in bhpp_query_batch_warm
+ * (warm_out of the poll, nullable, reports it); once the model's recent
+ * starts fall back in 90% of cases (after 32 tries) only every 16th admission
+ * is warm-started, until the rate improves: a useless start only costs time.
  *
  * bhpp_server_submit queues a request (host call, no device work; source in
  * caller ids, eps > 0, tag is returned with the result). It may run on
@@ -363,6 +365,8 @@ typedef struct {
     int64_t sweeps;         /* sweeps run by this server */
     double resident_bytes;  /* device bytes of its workspace */
     double lambda;          /* Lemma 4 bound used by its PI-Push thresholds */
+    int64_t warm_started;   /* requests that got a warm start from the model */
+    int64_t warm_fell_back; /* ... whose start was dropped for the cold start */
 } bhpp_server_summary;
 
 bhpp_status bhpp_server_create(bhpp_graph* g, bhpp_model* model, int32_t max_width, double mem_budget_bytes,

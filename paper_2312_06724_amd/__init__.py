@@ -86,7 +86,8 @@ class WarmStats(ctypes.Structure):
 class ServerSummary(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("k", ctypes.c_int32), ("queued", ctypes.c_int64),
                 ("running", ctypes.c_int64), ("completed", ctypes.c_int64), ("sweeps", ctypes.c_int64),
-                ("resident_bytes", ctypes.c_double), ("lambda_", ctypes.c_double)]
+                ("resident_bytes", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("warm_started", ctypes.c_int64), ("warm_fell_back", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

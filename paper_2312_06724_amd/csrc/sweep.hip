@@ -1598,6 +1598,12 @@ struct Server {
     void* h_vals = nullptr;
     int64_t completed = 0, sweeps = 0, since_done = 0;
     bool dirty = false;                   // host states changed since the last upload
+    // adaptive warm starts: a model whose starts keep falling back only costs
+    // time, so after a while it is used for every 16th admission only, until
+    // its recent fallback rate drops below 0.9
+    std::vector<uint8_t> tried;           // per column: the request was warm-started
+    double w_tries = 0.0, w_falls = 0.0;  // decayed counts over recent warm starts
+    int64_t admitted = 0, warm_started = 0, warm_fell_back = 0;
 };
 
 static bhpp_status server_upload(Server* sv) {
@@ -1633,7 +1639,11 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
             sv->hs[c].qid = c;
             sv->tag[c] = r.tag;
             sv->src[c] = r.src;
-            if (sv->model) newcols.push_back(c);
+            const bool useful = sv->w_tries < 32.0 || sv->w_falls < 0.9 * sv->w_tries;
+            const bool warm = sv->model && (useful || sv->admitted % 16 == 0);
+            sv->tried[c] = warm ? 1 : 0;
+            if (warm) newcols.push_back(c);
+            sv->admitted += 1;
             dirty = true;
         }
     }
@@ -1687,7 +1697,20 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
         memcpy(ids + (size_t)j * kk, sv->h_ids + (size_t)j * kk, sizeof(int32_t) * kk);
         memcpy((char*)vals + (size_t)j * kk * e, (char*)sv->h_vals + (size_t)j * kk * e, e * kk);
         if (st) fill_stats(sv->hs[c], st[j]);
-        if (wst) fill_warm(sv->hs[c], wst[j]);
+        if (wst) {
+            fill_warm(sv->hs[c], wst[j]);
+            if (!sv->tried[c]) {   // admitted cold: report the cold start's values
+                wst[j].res_l1 = wst[j].res_max = 1.0;
+                wst[j].fell_back = 1;
+            }
+        }
+        if (sv->tried[c]) {
+            const int fb = sv->hs[c].fell_back;
+            sv->w_tries = 0.99 * sv->w_tries + 1.0;
+            sv->w_falls = 0.99 * sv->w_falls + (fb ? 1.0 : 0.0);
+            sv->warm_started += 1;
+            sv->warm_fell_back += fb;
+        }
         sv->hs[c].qid = -1;
     }
     sv->dirty = true;   // freed columns: the device copy still names their request
@@ -1753,6 +1776,7 @@ bhpp_status server_create(Graph* g, Model* model, int max_width, double mem_budg
     for (ColState& c : sv->hs) done_state(c);
     sv->tag.assign(cols, -1);
     sv->src.assign(cols, -1);
+    sv->tried.assign(cols, 0);
     bhpp_status rc = BHPP_OK;
     if (hipStreamCreateWithFlags(&sv->s, hipStreamNonBlocking) != hipSuccess) rc = BHPP_DEVICE_ERROR;
     if (rc == BHPP_OK) rc = ensure_workspace(g, sv->ws, cols, sv->s);
@@ -1799,6 +1823,8 @@ void server_info(Server* sv, bhpp_server_summary* o) {
     o->sweeps = sv->sweeps;
     o->resident_bytes = (double)sv->ws.bytes;
     o->lambda = sv->lambda;
+    o->warm_started = sv->warm_started;
+    o->warm_fell_back = sv->warm_fell_back;
 }
 
 }  // namespace bhpp

@@ -104,3 +104,50 @@ def test_memory_budget_sets_width_and_errors(setup):
     G.set_launch_config(G.launch_config())
     with pytest.raises(bh.BhppError):
         bh.Server(G, k=10, mem_budget_bytes=1000.0)
+
+
+def test_warm_started_serving(setup):
+    """Serving with a model: the structural self term alone (network output
+    zero) never falls back; each result meets the bound and matches the same
+    request served alone within the tolerance."""
+    s = setup
+    bh, G, src, eps = s["bh"], s["G"], s["src"][:40], s["eps"][:40]
+    M0 = bh.Model(G, seed=1)
+    M0.set_params(np.zeros(bh.MODEL_PARAMS, np.float32))
+    M0.embed()
+    k = 20
+    S = bh.Server(G, k=k, model=M0)
+    rng = np.random.default_rng(8)
+    plan = {}
+    for i in range(src.size):
+        plan.setdefault(int(rng.integers(0, 20)), []).append((i, int(src[i]), float(eps[i])))
+    mix = drain(S, plan)
+    inf = S.info()
+    assert inf["warm_started"] == src.size and inf["warm_fell_back"] == 0
+    assert all(mix[i][2]["fell_back"] == 0 and mix[i][2]["res_l1"] < 1 for i in range(src.size))
+    for i in (0, 13, 39):
+        alone = drain(S, {0: [(500 + i, int(src[i]), float(eps[i]))]})[500 + i]
+        assert np.abs(alone[1].astype(np.float64) - mix[i][1]).max() <= 1e-6
+    S.close()
+    ex = oracle.Graph.from_edges(s["el"]).exact_beta_many(src[:6], 0.15, tail=1e-11, nthreads=16)
+    for i in range(6):
+        row = ex[i].copy()
+        row[src[i]] = -np.inf
+        d = row[mix[i][0]] - mix[i][1].astype(np.float64)
+        assert np.abs(d).max() <= eps[i] + 1e-6, (i, np.abs(d).max())
+    M0.close()
+
+
+def test_server_stops_using_a_useless_model(setup):
+    s = setup
+    bh, G, src = s["bh"], s["G"], s["src"]
+    M1 = bh.Model(G, seed=2)
+    M1.set_params(np.random.default_rng(3).normal(0, 0.5, bh.MODEL_PARAMS).astype(np.float32))
+    M1.embed()
+    S = bh.Server(G, k=10, model=M1)
+    res = drain(S, {p: [(p * 10 + j, int(src[(p * 10 + j) % src.size]), 1e-5) for j in range(10)] for p in range(40)})
+    inf = S.info()
+    assert len(res) == 400
+    assert inf["warm_fell_back"] >= 32 and inf["warm_started"] < 300
+    S.close()
+    M1.close()
