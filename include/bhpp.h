@@ -65,6 +65,11 @@ typedef struct {
 #define BHPP_BUILD_KEEP_EXTERNAL 1u
 /* Do not renumber nodes by degree internally (identity order). */
 #define BHPP_BUILD_NO_REORDER    2u
+/* One-source queries sweep densely from the start. By default SS-Push's
+   selective iterations of a lone source run as sparse frontier pushes (work
+   proportional to the frontier's edges) while the frontier's edges number
+   under |E|/16. */
+#define BHPP_BUILD_DENSE_ONLY    4u
 
 typedef struct bhpp_graph bhpp_graph;  /* opaque; owns all of its device memory */
 

@@ -132,6 +132,18 @@ struct Workspace {
     float* wP = nullptr;         // [n_u][wcols] predictions
     double* wres = nullptr;      // [2][wcols][blocks] residual norms per block
     int32_t* wcol_ids = nullptr; // [64] block column of each new query
+    // sparse frontier steps of a one-source block (allocated on demand)
+    int32_t* fF = nullptr;       // [n_u] frontier
+    void* fS = nullptr;          // [n_u] y/ws of the frontier
+    int64_t* fDeg = nullptr;     // [max(n_u, n_v)] degrees, then their inclusive scan in fOffs
+    int64_t* fOffs = nullptr;
+    int32_t* fTV = nullptr;      // [n_v] touched V nodes
+    void* fQ = nullptr;          // [n_v] V-side residue of a sparse step, kept zero between steps
+    int32_t* fMark = nullptr;    // [n_v] touched marks, kept zero between steps
+    void* fCnt = nullptr;        // counters: |F|, |T_V|, sum d over F, sum d over T_V
+    void* fScanTmp = nullptr;
+    size_t fScanBytes = 0;
+    unsigned long long* h_fCnt = nullptr;   // pinned mirror
     // sweep chunks captured as HIP graphs (one per column count), replayed per chunk
     hipGraphExec_t chunk_exec[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
@@ -173,6 +185,7 @@ struct Graph {
     int inflight = 8;
     int nt_stream = 0;
     int use_graphs = 1;
+    int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
     bool sticky_error = false;
     int n_servers = 0;               // live servers hold captured graphs of the tiles
     // profiling of the sweep kernels
@@ -183,6 +196,21 @@ struct Graph {
     std::vector<hipEvent_t> prof_ev;      // pairs, recorded on the query stream
     std::vector<int32_t> prof_kind;
     std::vector<double> prof_b;
+};
+
+// Push test of a lane's source: the rule becomes (compare y/ws(x) or y,
+// threshold); RULE_NONE gets an infinite threshold. Residues of a warm-started
+// query are signed, so callers pass |y| and |y/ws(x)| (cold-start residues are
+// never negative, for them this is the plain test).
+template <typename VT>
+struct PushTest {
+    bool by_ws;
+    VT thr;
+    __device__ __forceinline__ PushTest(int rule, VT kss, VT kpi) {
+        by_ws = rule == RULE_SS;
+        thr = rule == RULE_SS ? kss : rule == RULE_PI ? kpi : rule == RULE_ALL ? VT(0) : VT(INFINITY);
+    }
+    __device__ __forceinline__ bool operator()(VT y, VT yw) const { return (by_ws ? yw : y) > thr; }
 };
 
 // ---- host helpers (api.hip / build.hip / sweep.hip / topk.hip) ----
@@ -197,6 +225,20 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
                         hipStream_t s, Graph** out);
 void free_graph(Graph* g);
 bhpp_status compute_lambda(Graph* g, double alpha, int32_t tau, hipStream_t s, double* lambda_out);
+// One sparse push step of a one-source block (frontier.hip): sparse_front
+// (frontier, take, U->V scatter into w.fQ), then the caller's dense U-side
+// gather of w.fQ into G, then sparse_finish (y += (1-alpha) G, reductions).
+struct SparseStep {
+    int64_t max_work = 0;   // in: above this sum of frontier degrees the step is not taken
+    int red_blocks = 0, n_part = 0, off_u = 0;   // in: reduction slots of the phase control
+    int32_t frontier = 0;   // out: |F|
+    int64_t work_u = 0;     // out: sum of d(x) over F
+    bool done = false;      // out: the step was taken
+};
+bhpp_status ensure_sparse(Graph* g, Workspace& w, hipStream_t s);
+bhpp_status sparse_front(Graph* g, Workspace& w, SparseStep& io, hipStream_t s);
+bhpp_status sparse_finish(Graph* g, Workspace& w, const SparseStep& io, const void* G, hipStream_t s);
+
 struct Model;
 bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t n,
                         const int32_t* src_ext, const double* eps, double alpha,

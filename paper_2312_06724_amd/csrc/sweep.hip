@@ -69,21 +69,6 @@ static Geometry geometry(const Graph* g) {
 // ---------------------------------------------------------------------------
 // small device helpers
 // ---------------------------------------------------------------------------
-// Push test of a lane's source: the rule becomes (compare y/ws(x) or y,
-// threshold); RULE_NONE gets an infinite threshold. Residues of a warm-started
-// query are signed, so callers pass |y| and |y/ws(x)| (cold-start residues are
-// never negative, for them this is the plain test).
-template <typename VT>
-struct PushTest {
-    bool by_ws;
-    VT thr;
-    __device__ __forceinline__ PushTest(int rule, VT kss, VT kpi) {
-        by_ws = rule == RULE_SS;
-        thr = rule == RULE_SS ? kss : rule == RULE_PI ? kpi : rule == RULE_ALL ? VT(0) : VT(INFINITY);
-    }
-    __device__ __forceinline__ bool operator()(VT y, VT yw) const { return (by_ws ? yw : y) > thr; }
-};
-
 // Sum `v` over the lanes of the block that serve the same column and store
 // it at out[col * n_part + slot] (fixed order, so results are deterministic).
 template <int COLS>
@@ -1146,6 +1131,67 @@ static void fill_warm(const ColState& c, bhpp_warm_stats& o) {
     o.reserved = 0;
 }
 
+// SS-Push's selective iterations of a lone source as sparse frontier steps
+// (frontier.hip: frontier compaction and U->V scatter; the V->U half is the
+// dense U-side gather) while the frontier's edges are few (at most |E|/16);
+// the first larger frontier, or the end of the selective phase, hands the
+// state (Y, ACC and the source's phase control, all on the device) over to
+// the dense sweeps. Counts toward the same per-query statistics.
+template <typename VT, typename WT>
+static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& hs, hipStream_t s) {
+    bhpp_status rc = ensure_sparse(g, w, s);
+    if (rc) return rc;
+    const Geometry G = geometry(g);
+    // explicit start y = e_src, ACC = 0 (instead of the lazy reset of the first dense sweep)
+    const size_t nu = (size_t)g->nu;
+    hipLaunchKernelGGL(k_fill<VT>, dim3(1024), dim3(256), 0, s, as<VT>(w.Y), nu, VT(0));
+    hipLaunchKernelGGL(k_fill<VT>, dim3(1024), dim3(256), 0, s, as<VT>(w.ACC), nu, VT(0));
+    int32_t one_row[1] = {hs[0].src_row};
+    BHPP_HIP(hipMemcpyAsync(w.ex_tmp, one_row, 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_seed<VT>, dim3(1), dim3(64), 0, s, as<VT>(w.Y), w.ex_tmp, 1, 1);
+    hs[0].fresh = 0;
+    BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState), hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipStreamSynchronize(s));
+    GatherArgs<VT, WT> B;
+    B.tiles = g->tiles_u.tiles;
+    B.n_tiles = g->tiles_u.n_tiles;
+    B.rp = g->rp_u;
+    B.ci = g->ci_u;
+    B.w = reinterpret_cast<const WT*>(g->w_u);
+    B.X = as<VT>(w.fQ);
+    B.OUT = as<VT>(w.scores);
+    B.part = as<VT>(w.partB);
+    B.part_any = nullptr;
+    B.end_bits = g->end_bits_u;
+    B.n_active = w.n_active;
+    B.red = w.red;
+    B.n_part = G.n_part;
+    B.nt_stream = g->nt_stream;
+    B.red_slot = 0;
+    for (int it = 0; it < kMaxSteps; ++it) {
+        SparseStep io;
+        io.max_work = g->ne / 16;
+        io.red_blocks = G.n_part - G.offU;
+        io.n_part = G.n_part;
+        io.off_u = G.offU;
+        rc = sparse_front(g, w, io, s);
+        if (rc) return rc;
+        if (!io.done) break;
+        hipLaunchKernelGGL((k_gather1<VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
+        if (g->tiles_u.n_split > 0)
+            hipLaunchKernelGGL((k_fixup<1, VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
+                               g->tiles_u.split, g->tiles_u.n_split);
+        rc = sparse_finish(g, w, io, w.scores, s);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_control<1>), dim3(1), dim3(256), 0, s, w.st, w.red, G.n_part, G.offU, w.n_active);
+        BHPP_HIP(hipGetLastError());
+        BHPP_HIP(hipMemcpyAsync(hs.data(), w.st, sizeof(ColState), hipMemcpyDeviceToHost, s));
+        BHPP_HIP(hipStreamSynchronize(s));
+        if (hs[0].mode != MODE_SS_SEL) break;
+    }
+    return BHPP_OK;
+}
+
 // Queries are fed to a block of COLS columns from a queue. When enough
 // columns have finished (or the queue is empty and all have), their beta'
 // rows are extracted, their top-k computed, and the free columns take the
@@ -1189,6 +1235,10 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
     };
     bhpp_status rc = upload();
     if (rc) return rc;
+    if (COLS == 1 && n == 1 && !warm.any() && g->sparse_steps && !g->prof_on) {
+        rc = sparse_phase<VT, WT>(g, w, hs, s);
+        if (rc) return rc;
+    }
     int live = 0;
     for (int c = 0; c < COLS; ++c) live += hs[c].qid >= 0 ? 1 : 0;
     const int R = COLS >= 8 ? COLS / 8 : 1;   // finished columns that trigger an export round
@@ -1309,9 +1359,11 @@ void free_workspace(Workspace& w) {
         }
     void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores,
                     w.ids_tmp, w.vals_tmp, w.ex_tmp, w.SNAP, w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB,
-                    w.wpartA_any, w.wred, w.wst, w.wn_active, w.wP, w.wres, w.wcol_ids};
+                    w.wpartA_any, w.wred, w.wst, w.wn_active, w.wP, w.wres, w.wcol_ids, w.fF, w.fS, w.fDeg,
+                    w.fOffs, w.fTV, w.fQ, w.fMark, w.fCnt, w.fScanTmp};
     for (void* p : ptrs) hipFree(p);
     if (w.h_active) hipHostFree(w.h_active);
+    if (w.h_fCnt) hipHostFree(w.h_fCnt);
     w = Workspace{};
 }
 

@@ -173,3 +173,27 @@ def test_fp32_random_graph_batch(bh, reorder):
     for i, u in enumerate(src):
         rid, _ = oracle.topk_bruteforce(out["scores"][i].cpu().numpy(), 20, exclude=int(u))
         assert np.array_equal(ids[i], rid)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sparse_frontier_steps_match_dense(small, bh, dtype):
+    """One-source queries take SS-Push's selective iterations as sparse
+    frontier pushes; the result and every phase counter match the dense
+    sweeps of the same graph (up to summation order), and the bound holds."""
+    el, Pi = small["el"], small["Pi"]
+    Gs = bh.Graph.from_edges(el, dtype=dtype)
+    Gd = bh.Graph.from_edges(el, dtype=dtype, sparse=False)
+    eps = 1e-7 if dtype == "f64" else 1e-6
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    for u in small["sources"][:8]:
+        u = int(u)
+        bs, ss = Gs.query(u, eps)
+        bd, sd = Gd.query(u, eps)
+        bs, bd = bs.double().cpu().numpy(), bd.double().cpu().numpy()
+        assert np.abs(bs - bd).max() <= tol, u
+        for key in ("ss_sel_iters", "ss_seq_iters", "pi_sel_iters", "t", "ss_switched", "pi_returned"):
+            assert ss[key] == sd[key], (u, key, ss, sd)
+        assert abs(ss["np_ss"] - sd["np_ss"]) <= 1e-9 * max(1.0, sd["np_ss"])
+        beta = Pi[u, :] + Pi[:, u]
+        d = beta - bs
+        assert d.min() >= -tol and d.max() <= eps + tol
