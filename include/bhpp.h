@@ -70,6 +70,13 @@ typedef struct {
    proportional to the frontier's edges) while the frontier's edges number
    under |E|/16. */
 #define BHPP_BUILD_DENSE_ONLY    4u
+/* A batch keeps its block width to the end. By default, once no source is
+   waiting and at most half of the block's columns are still running, the
+   block narrows to the next power of two above the running count (cheaper
+   sweeps); a source's result then depends, in its last bits, on when the
+   others finished. With this flag it does not: the same source gives the same
+   bits in any batch of the same width. */
+#define BHPP_BUILD_FIXED_WIDTH   8u
 
 typedef struct bhpp_graph bhpp_graph;  /* opaque; owns all of its device memory */
 

@@ -25,7 +25,7 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range", -3: "sour
           -7: "not supported", -8: "step limit reached"}
 
 DTYPE_F32, DTYPE_F64 = 0, 1
-BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER, BUILD_DENSE_ONLY = 1, 2, 4
+BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER, BUILD_DENSE_ONLY, BUILD_FIXED_WIDTH = 1, 2, 4, 8
 
 # names exported by include/bhpp.h
 EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
@@ -197,7 +197,7 @@ class Graph:
     """A built bipartite graph resident in HBM (bhpp_build_graph)."""
 
     def __init__(self, n_u, n_v, edge_u, edge_v, edge_w, alpha=0.15, dtype="f32", tau=-1,
-                 keep_external=False, reorder=True, sparse=True):
+                 keep_external=False, reorder=True, sparse=True, fixed_width=False):
         torch = _torch()
         L = load_library()
         self.dtype = dtype
@@ -206,7 +206,7 @@ class Graph:
         ev = _dev(edge_v, torch.int32)
         ew = _dev(edge_w, self._tdtype)
         flags = ((BUILD_KEEP_EXTERNAL if keep_external else 0) | (0 if reorder else BUILD_NO_REORDER) |
-                 (0 if sparse else BUILD_DENSE_ONLY))
+                 (0 if sparse else BUILD_DENSE_ONLY) | (BUILD_FIXED_WIDTH if fixed_width else 0))
         opts = GraphOpts(alpha, tau, DTYPE_F64 if dtype == "f64" else DTYPE_F32, flags)
         h = ctypes.c_void_p()
         rc = L.bhpp_build_graph(n_u, n_v, eu.numel(), eu.data_ptr(), ev.data_ptr(), ew.data_ptr(),

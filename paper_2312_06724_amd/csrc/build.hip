@@ -571,8 +571,10 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "nt=")) && sscanf(q, "nt=%d", &v) == 1) g->nt_stream = v ? 1 : 0;
         if ((q = strstr(e, "graphs=")) && sscanf(q, "graphs=%d", &v) == 1) g->use_graphs = v ? 1 : 0;
         if ((q = strstr(e, "sparse=")) && sscanf(q, "sparse=%d", &v) == 1) g->sparse_steps = v ? 1 : 0;
+        if ((q = strstr(e, "narrow=")) && sscanf(q, "narrow=%d", &v) == 1) g->narrow = v ? 1 : 0;
     }
     if (opts.flags & BHPP_BUILD_DENSE_ONLY) g->sparse_steps = 0;
+    if (opts.flags & BHPP_BUILD_FIXED_WIDTH) g->narrow = 0;
     g->nu = n_u;
     g->nv = n_v;
     g->dtype = opts.dtype;

@@ -119,7 +119,7 @@ struct Workspace {
     void* scores = nullptr;      // [cols][n_u]: G during sweeps, row-major score scratch for top-k
     int32_t* ids_tmp = nullptr;  // [cols][kTopkTmpK] top-k scratch
     void* vals_tmp = nullptr;
-    int32_t* ex_tmp = nullptr;   // [cols] excluded id per exported row
+    int32_t* ex_tmp = nullptr;   // [3][64]: exported columns, their excluded ids, a narrowing map
     size_t bytes = 0;
     // warm starts: an FP64 block that applies the two-hop operator to the
     // predictions of newly admitted queries (allocated on demand)
@@ -186,6 +186,7 @@ struct Graph {
     int nt_stream = 0;
     int use_graphs = 1;
     int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
+    int narrow = 1;                  // batches narrow their block as sources finish
     bool sticky_error = false;
     int n_servers = 0;               // live servers hold captured graphs of the tiles
     // profiling of the sweep kernels

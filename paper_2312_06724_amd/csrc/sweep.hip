@@ -640,6 +640,17 @@ __global__ void k_seed(VT* Y, const int32_t* rows, int ncols, int cols) {
     if (c < ncols) Y[(size_t)rows[c] * cols + c] = VT(1);
 }
 
+// Block narrowing: column j of the c2-wide dst is column map[j] of the
+// c1-wide src (map[j] < 0: zero).
+template <typename VT>
+__global__ void k_compact(const VT* src, int c1, VT* dst, int c2, const int32_t* map, int32_t nu) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)nu * c2) return;
+    const size_t x = i / c2;
+    const int m = map[i % c2];
+    dst[i] = m >= 0 ? src[x * c1 + m] : VT(0);
+}
+
 // Finished columns cols[0..m) of ACC (internal node order) -> out[j][external x]
 // (row-major, one row per finished query), through an LDS tile: reads and
 // writes are both coalesced.
@@ -1200,15 +1211,19 @@ template <int COLS, typename VT, typename WT>
 static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* wstats, int n, const int32_t* src_ext,
                              const double* eps, double alpha, double lambda, void* scores_out, int k,
                              int exclude_self, int32_t* ids_out, void* vals_out, bhpp_query_stats* stats,
-                             hipStream_t s) {
+                             hipStream_t s, std::vector<ColState>& carry, int& next, int& narrow_to) {
     Workspace& w = g->ws;
     const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
                   w.SNAP};
     const Geometry G = geometry(g);
     const size_t nu = (size_t)g->nu, e = (size_t)g->elem;
+    narrow_to = 0;
     std::vector<ColState> hs(COLS);
     for (int c = 0; c < COLS; ++c) done_state(hs[c]);
-    int next = 0;
+    const bool resumed = !carry.empty();   // narrowed from a wider block: the columns continue
+    if (resumed)
+        for (int c = 0; c < COLS; ++c) hs[c] = carry[c];
+    carry.clear();
     std::vector<int32_t> newcols;   // columns given a query since the last upload (warm starts)
     auto assign = [&](int c) {
         const int q = next++;
@@ -1219,7 +1234,8 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
         hs[c].qid = q;
         if (warm.any()) newcols.push_back(c);
     };
-    for (int c = 0; c < COLS && next < n; ++c) assign(c);
+    if (!resumed)
+        for (int c = 0; c < COLS && next < n; ++c) assign(c);
     auto upload = [&]() -> bhpp_status {
         int32_t act = 0;
         for (int c = 0; c < COLS; ++c) act += hs[c].mode != MODE_DONE ? 1 : 0;
@@ -1235,7 +1251,7 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
     };
     bhpp_status rc = upload();
     if (rc) return rc;
-    if (COLS == 1 && n == 1 && !warm.any() && g->sparse_steps && !g->prof_on) {
+    if (COLS == 1 && n == 1 && !resumed && !warm.any() && g->sparse_steps && !g->prof_on) {
         rc = sparse_phase<VT, WT>(g, w, hs, s);
         if (rc) return rc;
     }
@@ -1264,7 +1280,8 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
             if (hipEventSynchronize(evs[slot ^ 1]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
             const int act = w.h_active[slot ^ 1];
             const int done = live - act;
-            round = act == 0 || (next < n && done >= R);
+            // with an empty queue, a block at most half busy narrows to the next power of two
+            round = act == 0 || (next < n && done >= R) || (g->narrow && next >= n && COLS > 1 && 2 * act <= COLS);
         }
         pending = true;
         ++chunk;
@@ -1325,6 +1342,41 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
         }
         pending = false;
         chunk = 0;
+        if (g->narrow && next >= n && live > 0 && COLS > 1 && 2 * live <= COLS) {
+            // narrow: the live columns move to a block of next_pow2(live) columns
+            // (states re-read: warm starts of this round were decided on the device)
+            if (hipStreamSynchronize(s) != hipSuccess ||
+                hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = BHPP_DEVICE_ERROR;
+                break;
+            }
+            const int c2 = next_pow2(live);
+            std::vector<int32_t> map(kMaxCols, -1);
+            std::vector<ColState> nh(c2);
+            for (auto& c : nh) done_state(c);
+            int j = 0;
+            for (int c = 0; c < COLS; ++c)
+                if (hs[c].qid >= 0) {
+                    map[j] = c;
+                    nh[j] = hs[c];
+                    ++j;
+                }
+            int32_t* d_map = w.ex_tmp + 2 * kMaxCols;
+            BHPP_HIP(hipMemcpyAsync(d_map, map.data(), sizeof(int32_t) * kMaxCols, hipMemcpyHostToDevice, s));
+            const size_t tot = nu * c2;
+            void* arrays[3] = {w.Y, w.ACC, w.SNAP};
+            for (void* a : arrays) {
+                if (!a) continue;
+                hipLaunchKernelGGL(k_compact<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, as<VT>(a), COLS,
+                                   as<VT>(w.S), c2, d_map, g->nu);
+                BHPP_HIP(hipMemcpyAsync(a, w.S, tot * e, hipMemcpyDeviceToDevice, s));
+            }
+            BHPP_HIP(hipGetLastError());
+            BHPP_HIP(hipStreamSynchronize(s));   // map is read by the copy above
+            carry = nh;
+            narrow_to = c2;
+            break;
+        }
     }
     if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
     hipEventDestroy(evs[0]);
@@ -1337,18 +1389,27 @@ static bhpp_status run_sched_dispatch(Graph* g, const WarmSource& model, bhpp_wa
                                       const int32_t* src, const double* eps, double alpha, double lambda,
                                       void* scores, int k, int ex, int32_t* ids, void* vals, bhpp_query_stats* st,
                                       hipStream_t s) {
-#define BHPP_RUN(C) return run_sched<C, VT, WT>(g, model, ws, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s)
-    switch (cols) {
-        case 1: BHPP_RUN(1);
-        case 2: BHPP_RUN(2);
-        case 4: BHPP_RUN(4);
-        case 8: BHPP_RUN(8);
-        case 16: BHPP_RUN(16);
-        case 32: BHPP_RUN(32);
-        case 64: BHPP_RUN(64);
-        default: return BHPP_INVALID_ARG;
-    }
+    std::vector<ColState> carry;
+    int next = 0;
+    for (;;) {
+        int to = 0;
+        bhpp_status rc;
+#define BHPP_RUN(C) \
+    rc = run_sched<C, VT, WT>(g, model, ws, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s, carry, next, to)
+        switch (cols) {
+            case 1: BHPP_RUN(1); break;
+            case 2: BHPP_RUN(2); break;
+            case 4: BHPP_RUN(4); break;
+            case 8: BHPP_RUN(8); break;
+            case 16: BHPP_RUN(16); break;
+            case 32: BHPP_RUN(32); break;
+            case 64: BHPP_RUN(64); break;
+            default: return BHPP_INVALID_ARG;
+        }
 #undef BHPP_RUN
+        if (rc || to == 0) return rc;
+        cols = to;   // the block narrowed; continue with the live columns
+    }
 }
 
 void free_workspace(Workspace& w) {
@@ -1402,7 +1463,7 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
               alloc(&w.scores, (size_t)g->nu * c * e) &&
               alloc((void**)&w.ids_tmp, (size_t)kMaxCols * kTopkTmpK * 4) &&
               alloc(&w.vals_tmp, (size_t)kMaxCols * kTopkTmpK * e) &&
-              alloc((void**)&w.ex_tmp, (size_t)2 * kMaxCols * 4);
+              alloc((void**)&w.ex_tmp, (size_t)3 * kMaxCols * 4);
     if (ok) ok = hipHostMalloc((void**)&w.h_active, 64) == hipSuccess;
     if (!ok) {
         free_workspace(w);

@@ -17,8 +17,9 @@ def setup():
     eps = rng.choice([1e-4, 1e-5, 1e-6], size=src.size)
     print(f"[gpu] graph 20k x 40k, 300k edges; {src.size} degree-proportional sources", flush=True)
     G = bh.Graph.from_edges(el, dtype="f32")
+    Gf = bh.Graph.from_edges(el, dtype="f32", fixed_width=True)
     g = oracle.Graph.from_edges(el)
-    return dict(bh=bh, el=el, src=src, eps=eps, G=G, g=g)
+    return dict(bh=bh, el=el, src=src, eps=eps, G=G, Gf=Gf, g=g)
 
 
 def test_many_uneven_sources_against_exact(setup):
@@ -41,19 +42,36 @@ def test_many_uneven_sources_against_exact(setup):
 
 
 def test_alone_and_in_mix_identical(setup):
-    """A query's result does not depend on the other queries sharing its block
-    (same block width: 64 columns), nor on its column or its position."""
+    """With a fixed block width, a query's result does not depend on the other
+    queries sharing its block (64 columns), nor on its column or position."""
     s = setup
     src, eps = s["src"], s["eps"]
-    a = s["G"].query_batch(src, eps, k=10)
+    a = s["Gf"].query_batch(src, eps, k=10)
     perm = np.random.default_rng(9).permutation(src.size)
-    b = s["G"].query_batch(src[perm], eps[perm], k=10)
+    b = s["Gf"].query_batch(src[perm], eps[perm], k=10)
     Sa, Sb = a["scores"].cpu().numpy(), b["scores"].cpu().numpy()
     assert np.array_equal(Sa[perm], Sb)
     assert np.array_equal(a["ids"].cpu().numpy()[perm], b["ids"].cpu().numpy())
     # one query with 63 others vs with 63 different others
-    c = s["G"].query_batch(np.concatenate([src[:1], src[100:163]]), np.concatenate([eps[:1], eps[100:163]]))
+    c = s["Gf"].query_batch(np.concatenate([src[:1], src[100:163]]), np.concatenate([eps[:1], eps[100:163]]))
     assert np.array_equal(c["scores"][0].cpu().numpy(), Sa[0])
+
+
+def test_narrowing_blocks_match_fixed_width(setup):
+    """A batch that narrows its block as sources finish gives every source the
+    same result as a fixed-width block, within the rounding of the narrower
+    kernels (both within eps of the exact scores: the other test)."""
+    s = setup
+    src, eps = s["src"][:64], s["eps"][:64]
+    a = s["G"].query_batch(src, eps, k=10)
+    b = s["Gf"].query_batch(src, eps, k=10)
+    Sa, Sb = a["scores"].cpu().numpy().astype(np.float64), b["scores"].cpu().numpy().astype(np.float64)
+    d = np.abs(Sa - Sb).max(axis=1)
+    assert np.all(d <= eps + 1e-6), d.max()
+    steps_a = np.array([x["steps"] for x in a["stats"]])
+    steps_b = np.array([x["steps"] for x in b["stats"]])
+    assert np.abs(steps_a - steps_b).max() <= 2
+    assert np.mean(d <= 1e-6) > 0.9
 
 
 def test_launch_settings_do_not_change_results(setup):

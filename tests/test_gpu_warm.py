@@ -41,7 +41,7 @@ def small():
     wl = synth.SMALL
     el = wl.graph()
     print("[gpu] warm: 2k x 3k graph", flush=True)
-    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f64")
+    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f64", fixed_width=True)
     g = oracle.Graph.from_edges(el)
     Pi, _, _ = oracle.exact_dense(el.n_u, el.n_v, el.u, el.v, el.w, wl.alpha)
     return dict(bh=bh, wl=wl, el=el, G=G, g=g, Pi=Pi, src=wl.sources(el))
