@@ -108,7 +108,7 @@ typedef struct {
     double alpha;             /* alpha that lambda was computed for */
     double lambda;            /* Eq. (lambda) */
     double mu;                /* sqrt(|U||V|)/|E| */
-    double eps_b_ratio;       /* eps_b / eps from Eq. (epsilon-b); 0.5 when mu >= 1 */
+    double eps_b_ratio;       /* eps_b / eps in use: Eq. (epsilon-b) (0.5 when mu >= 1) unless set or tuned */
     double ws_u_max, ws_u_min;/* over U nodes with at least one edge */
     double build_ms;          /* device time of the build, preprocessing included */
 } bhpp_graph_summary;
@@ -389,6 +389,22 @@ bhpp_status bhpp_server_poll(bhpp_server* s, int32_t capacity, int64_t* tags_out
                              int32_t* n_out);
 bhpp_status bhpp_server_info(const bhpp_server* s, bhpp_server_summary* out);
 void bhpp_server_destroy(bhpp_server* s);
+
+/* ------------------------------------------------------------------------
+ * The split of eps between SS-Push and PI-Push. Theorem 3 holds for any
+ * eps_b in (0, eps); Eq. (epsilon-b) picks eps_b from mu, which only affects
+ * speed. bhpp_set_eps_b_ratio sets eps_b = ratio * eps for later queries
+ * (0 < ratio < 1; ratio = 0 restores Eq. (epsilon-b)). bhpp_tune_eps_b runs
+ * the sample sources (host ids, eps, alpha; no outputs) once per candidate
+ * ratio, writes each run's wall time in ms to ms_out[n_ratios] (host,
+ * nullable), keeps the fastest ratio and returns it in *best_out. It
+ * synchronises hip_stream. Errors: INVALID_ARG, OUT_OF_RANGE, ISOLATED_SOURCE,
+ * NO_CONVERGENCE, DEVICE_ERROR.
+ * ---------------------------------------------------------------------- */
+bhpp_status bhpp_set_eps_b_ratio(bhpp_graph* g, double ratio);
+bhpp_status bhpp_tune_eps_b(bhpp_graph* g, int32_t n_src, const int32_t* sources, double eps, double alpha,
+                            int32_t n_ratios, const double* ratios, double* ms_out, double* best_out,
+                            void* hip_stream);
 
 /* Free the handle and all device memory it owns (NULL is ignored). The caller
    must make sure no work using it is still running. */

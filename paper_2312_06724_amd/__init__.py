@@ -33,7 +33,8 @@ EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "
             "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_server_create", "bhpp_server_submit",
             "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_model_create", "bhpp_model_params",
             "bhpp_model_features", "bhpp_model_loss_grad", "bhpp_model_train", "bhpp_model_embed", "bhpp_model_free",
-            "bhpp_query_batch_warm", "bhpp_query_batch_start", "bhpp_gemm_bf16", "bhpp_free_graph", "bhpp_status_string"]
+            "bhpp_query_batch_warm", "bhpp_query_batch_start", "bhpp_gemm_bf16", "bhpp_set_eps_b_ratio",
+            "bhpp_tune_eps_b", "bhpp_free_graph", "bhpp_status_string"]
 MODEL_PARAMS = 230656
 MODEL_FEATURES = 64
 
@@ -154,6 +155,10 @@ def load_library():
     L.bhpp_query_batch_warm.argtypes = [P, P, I32, P, P, D, D, P, I32, I32, P, P, P, P, P]
     L.bhpp_query_batch_start.restype = I32
     L.bhpp_query_batch_start.argtypes = [P, P, I32, P, P, D, D, P, I32, I32, P, P, P, P, P]
+    L.bhpp_set_eps_b_ratio.restype = I32
+    L.bhpp_set_eps_b_ratio.argtypes = [P, D]
+    L.bhpp_tune_eps_b.restype = I32
+    L.bhpp_tune_eps_b.argtypes = [P, I32, P, D, D, I32, P, P, P, P]
     L.bhpp_gemm_bf16.restype = I32
     L.bhpp_gemm_bf16.argtypes = [I32, I32, I32, P, I32, P, I32, P, P]
     L.bhpp_server_info.restype = I32
@@ -343,6 +348,22 @@ class Graph:
         cfg = (ctypes.c_int32 * 4)()
         _check(load_library().bhpp_get_launch_config(self._h, cfg), "bhpp_get_launch_config")
         return dict(tile_edges=cfg[0], inflight=cfg[1], nt_stream=cfg[2], graphs=cfg[3])
+
+    def set_eps_b_ratio(self, ratio):
+        """eps_b = ratio * eps for later queries; 0 restores Eq. (epsilon-b)."""
+        _check(load_library().bhpp_set_eps_b_ratio(self._h, float(ratio)), "bhpp_set_eps_b_ratio")
+
+    def tune_eps_b(self, sources, eps, ratios, alpha=None):
+        """Time the sample once per candidate ratio, keep the fastest;
+        returns (best ratio, ms per candidate)."""
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        r = np.ascontiguousarray(ratios, dtype=np.float64)
+        ms = np.zeros(r.size)
+        best = ctypes.c_double()
+        _check(load_library().bhpp_tune_eps_b(self._h, src.size, src.ctypes.data, float(eps), alpha or self.alpha,
+                                              r.size, r.ctypes.data, ms.ctypes.data, ctypes.byref(best), _stream()),
+               "bhpp_tune_eps_b")
+        return best.value, ms
 
     def profile(self, enable):
         _check(load_library().bhpp_profile_enable(self._h, 1 if enable else 0), "bhpp_profile_enable")

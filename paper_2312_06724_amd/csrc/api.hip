@@ -1,6 +1,7 @@
 // C ABI entry points (include/bhpp.h): argument checking, handle ownership,
 // error mapping. All computation happens in the kernels of build.hip,
 // sweep.hip and topk.hip.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -480,6 +481,58 @@ bhpp_status bhpp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, i
                            int32_t trans_b, float* C, void* hip_stream) {
     if (M < 1 || N < 1 || K < 1 || !A || !B || !C) return BHPP_INVALID_ARG;
     return bhpp::gemm_test(M, N, K, A, trans_a, B, trans_b, C, stream_of(hip_stream));
+}
+
+bhpp_status bhpp_set_eps_b_ratio(bhpp_graph* h, double ratio) {
+    if (!h || !h->g || !(ratio >= 0.0 && ratio < 1.0)) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    std::lock_guard<std::mutex> lock(g->mu);
+    g->info.eps_b_ratio = ratio > 0.0 ? ratio : g->eps_b_paper;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_tune_eps_b(bhpp_graph* h, int32_t n_src, const int32_t* sources, double eps, double alpha,
+                            int32_t n_ratios, const double* ratios, double* ms_out, double* best_out,
+                            void* hip_stream) {
+    if (!h || !h->g || n_src < 1 || !sources || n_ratios < 1 || !ratios || !best_out || !valid_eps(eps) ||
+        !valid_alpha(alpha))
+        return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    for (int32_t i = 0; i < n_ratios; ++i)
+        if (!(ratios[i] > 0.0 && ratios[i] < 1.0)) return BHPP_INVALID_ARG;
+    for (int32_t i = 0; i < n_src; ++i) {
+        if (sources[i] < 0 || sources[i] >= g->nu) return BHPP_OUT_OF_RANGE;
+        if (!(g->h_ws_u[sources[i]] > 0.0)) return BHPP_ISOLATED_SOURCE;
+    }
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        hipStream_t s = stream_of(hip_stream);
+        double lam = 0.0;
+        bhpp_status rc = lambda_for(g, alpha, s, &lam);
+        if (rc) return sticky(g, rc);
+        const double saved = g->info.eps_b_ratio;
+        std::vector<double> e((size_t)n_src, eps);
+        double best_ms = 0.0, best = saved;
+        for (int32_t i = 0; i < n_ratios && rc == BHPP_OK; ++i) {
+            g->info.eps_b_ratio = ratios[i];
+            const auto t0 = std::chrono::steady_clock::now();
+            rc = bhpp::run_queries(g, nullptr, nullptr, nullptr, n_src, sources, e.data(), alpha, lam, nullptr, 0, 0,
+                                   nullptr, nullptr, nullptr, s);
+            if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (ms_out) ms_out[i] = ms;
+            if (rc == BHPP_OK && (i == 0 || ms < best_ms)) {
+                best_ms = ms;
+                best = ratios[i];
+            }
+        }
+        g->info.eps_b_ratio = rc == BHPP_OK ? best : saved;
+        *best_out = g->info.eps_b_ratio;
+        return sticky(g, rc);
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
 }
 
 void bhpp_free_graph(bhpp_graph* h) {

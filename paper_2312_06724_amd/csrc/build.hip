@@ -527,6 +527,7 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
     // Eq. (epsilon-b); mu >= 1 would leave (0, eps), then eps/2
     I.mu = m > 0 ? std::sqrt((double)nu * (double)nv) / (double)m : INFINITY;
     I.eps_b_ratio = I.mu < 1.0 ? (1.0 - I.mu) / (2.0 - I.mu) : 0.5;
+    g->eps_b_paper = I.eps_b_ratio;
 
     // 8. lambda (Lemma 4)
     I.alpha = opts.alpha;

@@ -187,6 +187,7 @@ struct Graph {
     int use_graphs = 1;
     int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
     int narrow = 1;                  // batches narrow their block as sources finish
+    double eps_b_paper = 0.5;        // eps_b / eps of Eq. (epsilon-b); info.eps_b_ratio is the one in use
     bool sticky_error = false;
     int n_servers = 0;               // live servers hold captured graphs of the tiles
     // profiling of the sweep kernels

@@ -197,3 +197,31 @@ def test_sparse_frontier_steps_match_dense(small, bh, dtype):
         beta = Pi[u, :] + Pi[:, u]
         d = beta - bs
         assert d.min() >= -tol and d.max() <= eps + tol
+
+
+def test_eps_b_split_keeps_the_bound(small, bh):
+    """Theorem 3 holds for any eps_b in (0, eps): queries with a set split stay
+    in [beta - eps, beta], follow the oracle run with the same eps_b phase for
+    phase, and the tuner keeps one of its candidates."""
+    el, Pi, g = small["el"], small["Pi"], small["g"]
+    G = bh.Graph.from_edges(el, dtype="f64")
+    paper = G.info()["eps_b_ratio"]
+    eps = 1e-7
+    src = small["sources"][:6]
+    for ratio in (0.05, 0.9):
+        G.set_eps_b_ratio(ratio)
+        assert abs(G.info()["eps_b_ratio"] - ratio) < 1e-15
+        out = G.query_batch(src, eps)
+        S = out["scores"].cpu().numpy()
+        for i, u in enumerate(src):
+            u = int(u)
+            d = Pi[u, :] + Pi[:, u] - S[i]
+            assert d.min() >= -1e-10 and d.max() <= eps + 1e-10, (ratio, u)
+            _, _, _, st = g.approx_bhpp(u, 0.15, eps, eps_b=ratio * eps)
+            assert out["stats"][i]["t"] == st["t"] and out["stats"][i]["ss_switched"] == st["ss_switched"]
+    best, ms = G.tune_eps_b(small["sources"][6:], eps, [0.05, 0.2, paper])
+    assert best in (0.05, 0.2, paper) and np.all(ms > 0)
+    G.set_eps_b_ratio(0.0)
+    assert G.info()["eps_b_ratio"] == paper
+    with pytest.raises(bh.BhppError):
+        G.set_eps_b_ratio(1.0)
