@@ -344,7 +344,7 @@ def main():
         paper = info["eps_b_ratio"]
         sample = np.setdiff1d(synth.sample_sources(el, 128, "uniform", 9090), src)[:64]
         ratios = [0.01, 0.03, 0.1, 0.2, paper]
-        best, ms = G.tune_eps_b(sample, wl.eps, ratios)
+        best, ms, gm, swc = G.tune_eps_b(sample, wl.eps, ratios, curve=True)
         step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -355,6 +355,7 @@ def main():
         sw = float(np.mean([x["steps"] for x in G.query_batch(src, wl.eps, k=0, scores=False)["stats"]]))
         G.set_eps_b_ratio(0.0)
         tuned = dict(candidates=[round(r, 4) for r in ratios], sample_ms=[round(m, 1) for m in ms],
+                     gamma_curve=[round(float(x), 5) for x in gm], sample_sweeps=[round(float(x), 1) for x in swc],
                      best_ratio=round(best, 4), paper_ratio=round(paper, 4), queries_per_s=round(tq, 3),
                      mean_sweeps_per_query=sw)
         log(f"tuned eps_b ratio {best:.3f}: {tq:.1f} q/s, {sw:.1f} sweeps per query")

@@ -320,6 +320,25 @@ bhpp_status bhpp_query_batch_warm(bhpp_graph* g, bhpp_model* m, int32_t n_src, c
                                   int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
                                   bhpp_warm_stats* warm_out, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * One direction of HPP alone (the sub-results Algorithm 5 combines), for
+ * n_src sources as in bhpp_query_batch (no top-k):
+ *   BHPP_HPP_FORWARD   scores_out[i][x] ~ pi(u_i, x), single-source HPP
+ *                      (Eq. (hpp), a row of Pi) by PI-Push (Algorithm 4) from
+ *                      (pi_b, r) = (0, e_u) with eps_f = eps: within
+ *                      [pi - eps, pi] (Theorem 2);
+ *   BHPP_HPP_BACKWARD  scores_out[i][x] ~ pi(x, u_i), single-target HPP (a
+ *                      column of Pi) by SS-Push (Algorithm 3) with
+ *                      eps_b = eps: within [pi - eps, pi] (Theorem 1).
+ * scores_out: device [n_src][n_u] of the graph dtype (required). Errors: as
+ * bhpp_query_batch, INVALID_ARG for another direction.
+ * ---------------------------------------------------------------------- */
+#define BHPP_HPP_FORWARD  0
+#define BHPP_HPP_BACKWARD 1
+bhpp_status bhpp_query_hpp(bhpp_graph* g, int32_t n_src, const int32_t* sources, const double* eps, double alpha,
+                           double eps_all, int32_t direction, void* scores_out, bhpp_query_stats* stats,
+                           void* hip_stream);
+
 /* Warm start from caller-given starts instead of a model: starts is device
    [n_src][n_u] of the graph dtype, row i = estimates of pi(sources[i], x) for
    every x (caller ids; any sign; the start is rounded to FP32). Same
@@ -396,15 +415,17 @@ void bhpp_server_destroy(bhpp_server* s);
  * speed. bhpp_set_eps_b_ratio sets eps_b = ratio * eps for later queries
  * (0 < ratio < 1; ratio = 0 restores Eq. (epsilon-b)). bhpp_tune_eps_b runs
  * the sample sources (host ids, eps, alpha; no outputs) once per candidate
- * ratio, writes each run's wall time in ms to ms_out[n_ratios] (host,
- * nullable), keeps the fastest ratio and returns it in *best_out. It
- * synchronises hip_stream. Errors: INVALID_ARG, OUT_OF_RANGE, ISOLATED_SOURCE,
- * NO_CONVERGENCE, DEVICE_ERROR.
+ * ratio and writes, per candidate (host arrays [n_ratios], each nullable),
+ * the run's wall time in ms, the mean gamma of Eq. (gamma) over the sample
+ * (the quantity of Fig. 1) and the mean number of sweeps per source; it keeps
+ * the fastest ratio and returns it in *best_out. It synchronises hip_stream.
+ * Errors: INVALID_ARG, OUT_OF_RANGE, ISOLATED_SOURCE, NO_CONVERGENCE,
+ * DEVICE_ERROR.
  * ---------------------------------------------------------------------- */
 bhpp_status bhpp_set_eps_b_ratio(bhpp_graph* g, double ratio);
 bhpp_status bhpp_tune_eps_b(bhpp_graph* g, int32_t n_src, const int32_t* sources, double eps, double alpha,
-                            int32_t n_ratios, const double* ratios, double* ms_out, double* best_out,
-                            void* hip_stream);
+                            int32_t n_ratios, const double* ratios, double* ms_out, double* gamma_out,
+                            double* sweeps_out, double* best_out, void* hip_stream);
 
 /* Free the handle and all device memory it owns (NULL is ignored). The caller
    must make sure no work using it is still running. */

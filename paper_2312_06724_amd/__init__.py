@@ -34,7 +34,7 @@ EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "
             "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_model_create", "bhpp_model_params",
             "bhpp_model_features", "bhpp_model_loss_grad", "bhpp_model_train", "bhpp_model_embed", "bhpp_model_free",
             "bhpp_query_batch_warm", "bhpp_query_batch_start", "bhpp_gemm_bf16", "bhpp_set_eps_b_ratio",
-            "bhpp_tune_eps_b", "bhpp_free_graph", "bhpp_status_string"]
+            "bhpp_tune_eps_b", "bhpp_query_hpp", "bhpp_free_graph", "bhpp_status_string"]
 MODEL_PARAMS = 230656
 MODEL_FEATURES = 64
 
@@ -158,7 +158,9 @@ def load_library():
     L.bhpp_set_eps_b_ratio.restype = I32
     L.bhpp_set_eps_b_ratio.argtypes = [P, D]
     L.bhpp_tune_eps_b.restype = I32
-    L.bhpp_tune_eps_b.argtypes = [P, I32, P, D, D, I32, P, P, P, P]
+    L.bhpp_tune_eps_b.argtypes = [P, I32, P, D, D, I32, P, P, P, P, P, P]
+    L.bhpp_query_hpp.restype = I32
+    L.bhpp_query_hpp.argtypes = [P, I32, P, P, D, D, I32, P, P, P]
     L.bhpp_gemm_bf16.restype = I32
     L.bhpp_gemm_bf16.argtypes = [I32, I32, I32, P, I32, P, I32, P, P]
     L.bhpp_server_info.restype = I32
@@ -349,21 +351,37 @@ class Graph:
         _check(load_library().bhpp_get_launch_config(self._h, cfg), "bhpp_get_launch_config")
         return dict(tile_edges=cfg[0], inflight=cfg[1], nt_stream=cfg[2], graphs=cfg[3])
 
+    def query_hpp(self, sources, eps, direction="forward", alpha=None, stats=True):
+        """One direction of HPP (bhpp_query_hpp): "forward" pi(u, .) or
+        "backward" pi(., u) for each source; returns ([n, n_u] tensor, stats)."""
+        torch = _torch()
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        n = src.size
+        eps_arr = np.broadcast_to(np.asarray(eps, dtype=np.float64), (n,)).copy()
+        out = torch.empty((n, self.n_u), dtype=self._tdtype, device="cuda")
+        st = (QueryStats * max(1, n))()
+        d = {"forward": 0, "backward": 1}[direction]
+        rc = load_library().bhpp_query_hpp(self._h, n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha,
+                                           float(eps_arr[0]), d, out.data_ptr(),
+                                           ctypes.cast(st, ctypes.c_void_p) if stats else None, _stream())
+        _check(rc, "bhpp_query_hpp")
+        return out, ([st[i].as_dict() for i in range(n)] if stats else None)
+
     def set_eps_b_ratio(self, ratio):
         """eps_b = ratio * eps for later queries; 0 restores Eq. (epsilon-b)."""
         _check(load_library().bhpp_set_eps_b_ratio(self._h, float(ratio)), "bhpp_set_eps_b_ratio")
 
-    def tune_eps_b(self, sources, eps, ratios, alpha=None):
+    def tune_eps_b(self, sources, eps, ratios, alpha=None, curve=False):
         """Time the sample once per candidate ratio, keep the fastest;
-        returns (best ratio, ms per candidate)."""
+        returns (best ratio, ms per candidate[, mean gamma, mean sweeps])."""
         src = np.ascontiguousarray(sources, dtype=np.int32)
         r = np.ascontiguousarray(ratios, dtype=np.float64)
-        ms = np.zeros(r.size)
+        ms, gm, sw = np.zeros(r.size), np.zeros(r.size), np.zeros(r.size)
         best = ctypes.c_double()
         _check(load_library().bhpp_tune_eps_b(self._h, src.size, src.ctypes.data, float(eps), alpha or self.alpha,
-                                              r.size, r.ctypes.data, ms.ctypes.data, ctypes.byref(best), _stream()),
-               "bhpp_tune_eps_b")
-        return best.value, ms
+                                              r.size, r.ctypes.data, ms.ctypes.data, gm.ctypes.data, sw.ctypes.data,
+                                              ctypes.byref(best), _stream()), "bhpp_tune_eps_b")
+        return (best.value, ms, gm, sw) if curve else (best.value, ms)
 
     def profile(self, enable):
         _check(load_library().bhpp_profile_enable(self._h, 1 if enable else 0), "bhpp_profile_enable")

@@ -98,8 +98,8 @@ bhpp_status bhpp_build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const in
     }
 }
 
-static bhpp_status query_batch_impl(bhpp_graph* h, bhpp_model* model, const void* starts, int32_t n_src,
-                                    const int32_t* sources,
+static bhpp_status query_batch_impl(bhpp_graph* h, bhpp_model* model, const void* starts, int32_t target,
+                                    int32_t n_src, const int32_t* sources,
                                     const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
                                     int32_t exclude_self, int32_t* topk_ids, void* topk_vals,
                                     bhpp_query_stats* stats, bhpp_warm_stats* wstats, void* hip_stream) {
@@ -126,7 +126,8 @@ static bhpp_status query_batch_impl(bhpp_graph* h, bhpp_model* model, const void
         double lam = 0.0;
         bhpp_status rc = lambda_for(g, alpha, s, &lam);
         if (rc) return sticky(g, rc);
-        rc = bhpp::run_queries(g, model ? model->m : nullptr, starts, wstats, n_src, sources, e.data(), alpha, lam,
+        rc = bhpp::run_queries(g, model ? model->m : nullptr, starts, wstats, target, n_src, sources, e.data(), alpha,
+                               lam,
                                scores_out, k, exclude_self, topk_ids, topk_vals, stats, s);
         if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
         return sticky(g, rc);
@@ -138,7 +139,7 @@ static bhpp_status query_batch_impl(bhpp_graph* h, bhpp_model* model, const void
 bhpp_status bhpp_query_batch(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps,
                              double alpha, double eps_all, void* scores_out, int32_t k, int32_t exclude_self,
                              int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, void* hip_stream) {
-    return query_batch_impl(h, nullptr, nullptr, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
+    return query_batch_impl(h, nullptr, nullptr, 0, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
                             topk_ids, topk_vals, stats, nullptr, hip_stream);
 }
 
@@ -147,8 +148,8 @@ bhpp_status bhpp_query_batch_warm(bhpp_graph* h, bhpp_model* m, int32_t n_src, c
                                   int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
                                   bhpp_warm_stats* warm_out, void* hip_stream) {
     if (!m || !m->m) return BHPP_INVALID_ARG;
-    return query_batch_impl(h, m, nullptr, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self, topk_ids,
-                            topk_vals, stats, warm_out, hip_stream);
+    return query_batch_impl(h, m, nullptr, 0, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
+                            topk_ids, topk_vals, stats, warm_out, hip_stream);
 }
 
 bhpp_status bhpp_query_batch_start(bhpp_graph* h, const void* starts, int32_t n_src, const int32_t* sources,
@@ -156,8 +157,17 @@ bhpp_status bhpp_query_batch_start(bhpp_graph* h, const void* starts, int32_t n_
                                    int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
                                    bhpp_warm_stats* warm_out, void* hip_stream) {
     if (!starts) return BHPP_INVALID_ARG;
-    return query_batch_impl(h, nullptr, starts, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
+    return query_batch_impl(h, nullptr, starts, 0, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
                             topk_ids, topk_vals, stats, warm_out, hip_stream);
+}
+
+bhpp_status bhpp_query_hpp(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps, double alpha,
+                           double eps_all, int32_t direction, void* scores_out, bhpp_query_stats* stats,
+                           void* hip_stream) {
+    if (direction != BHPP_HPP_FORWARD && direction != BHPP_HPP_BACKWARD) return BHPP_INVALID_ARG;
+    if (!scores_out && n_src > 0) return BHPP_INVALID_ARG;
+    return query_batch_impl(h, nullptr, nullptr, direction == BHPP_HPP_FORWARD ? 1 : 2, n_src, sources, eps, alpha,
+                            eps_all, scores_out, 0, 0, nullptr, nullptr, stats, nullptr, hip_stream);
 }
 
 bhpp_status bhpp_query(bhpp_graph* h, int32_t source, double alpha, double eps, void* scores_out,
@@ -492,8 +502,8 @@ bhpp_status bhpp_set_eps_b_ratio(bhpp_graph* h, double ratio) {
 }
 
 bhpp_status bhpp_tune_eps_b(bhpp_graph* h, int32_t n_src, const int32_t* sources, double eps, double alpha,
-                            int32_t n_ratios, const double* ratios, double* ms_out, double* best_out,
-                            void* hip_stream) {
+                            int32_t n_ratios, const double* ratios, double* ms_out, double* gamma_out,
+                            double* sweeps_out, double* best_out, void* hip_stream) {
     if (!h || !h->g || n_src < 1 || !sources || n_ratios < 1 || !ratios || !best_out || !valid_eps(eps) ||
         !valid_alpha(alpha))
         return BHPP_INVALID_ARG;
@@ -513,15 +523,23 @@ bhpp_status bhpp_tune_eps_b(bhpp_graph* h, int32_t n_src, const int32_t* sources
         if (rc) return sticky(g, rc);
         const double saved = g->info.eps_b_ratio;
         std::vector<double> e((size_t)n_src, eps);
+        std::vector<bhpp_query_stats> st((size_t)n_src);
         double best_ms = 0.0, best = saved;
         for (int32_t i = 0; i < n_ratios && rc == BHPP_OK; ++i) {
             g->info.eps_b_ratio = ratios[i];
             const auto t0 = std::chrono::steady_clock::now();
-            rc = bhpp::run_queries(g, nullptr, nullptr, nullptr, n_src, sources, e.data(), alpha, lam, nullptr, 0, 0,
-                                   nullptr, nullptr, nullptr, s);
+            rc = bhpp::run_queries(g, nullptr, nullptr, nullptr, 0, n_src, sources, e.data(), alpha, lam, nullptr, 0,
+                                   0, nullptr, nullptr, st.data(), s);
             if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             if (ms_out) ms_out[i] = ms;
+            double gm = 0.0, sw = 0.0;
+            for (const bhpp_query_stats& q : st) {
+                gm += q.gamma;
+                sw += q.steps;
+            }
+            if (gamma_out) gamma_out[i] = gm / n_src;   // Eq. (gamma) averaged over the sample (Fig. 1's quantity)
+            if (sweeps_out) sweeps_out[i] = sw / n_src;
             if (rc == BHPP_OK && (i == 0 || ms < best_ms)) {
                 best_ms = ms;
                 best = ratios[i];

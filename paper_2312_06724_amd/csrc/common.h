@@ -96,6 +96,7 @@ struct ColState {
     int32_t warm;
     int32_t snap;
     int32_t fell_back;   // a warm start was no better than the cold start: ran cold
+    int32_t target;      // 0: beta (Algorithm 5); 1: pi(u, .) (PI-Push alone); 2: pi(., u) (SS-Push alone)
     double res_l1;       // sum_x |r_f(x)| of the warm start
     double res_max;      // max_x |r(x)|
 };
@@ -242,8 +243,8 @@ bhpp_status sparse_front(Graph* g, Workspace& w, SparseStep& io, hipStream_t s);
 bhpp_status sparse_finish(Graph* g, Workspace& w, const SparseStep& io, const void* G, hipStream_t s);
 
 struct Model;
-bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t n,
-                        const int32_t* src_ext, const double* eps, double alpha,
+bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t target,
+                        int32_t n, const int32_t* src_ext, const double* eps, double alpha,
                         double lambda, void* scores_out, int32_t k, int32_t exclude_self,
                         int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, hipStream_t s);
 bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,

@@ -199,12 +199,29 @@ GemmArgs gemm_args(int M, int N, int K, const bf16* A, int64_t a_rs, int64_t a_c
     return g;
 }
 
-// column sums of an FP32 [rows][cols] matrix (bias gradients), fixed order
-__global__ void k_colsum(const float* X, int rows, int cols, float* out) {
+// Column sums of an FP32 [rows][cols] matrix (bias gradients) in a fixed
+// order: block (b, c) sums rows b, b + kColSplit, ... of 64 columns with 4
+// row-interleaved lanes per column into part[b][cols]; k_colsum_fin adds the
+// kColSplit partials of each column in order.
+constexpr int kColSplit = 32;
+
+__global__ __launch_bounds__(256) void k_colsum(const float* X, int rows, int cols, float* part) {
+    __shared__ float sh[4][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int j = blockIdx.y * 64 + c;
+    float s = 0.0f;
+    if (j < cols)
+        for (int i = blockIdx.x + g * kColSplit; i < rows; i += 4 * kColSplit) s += X[(int64_t)i * cols + j];
+    sh[g][c] = s;
+    __syncthreads();
+    if (g == 0 && j < cols) part[(int64_t)blockIdx.x * cols + j] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+}
+
+__global__ void k_colsum_fin(const float* part, int cols, float* out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= cols) return;
     float s = 0.0f;
-    for (int i = 0; i < rows; ++i) s += X[(int64_t)i * cols + j];
+    for (int b = 0; b < kColSplit; ++b) s += part[(int64_t)b * cols + j];
     out[j] = s;
 }
 
@@ -301,16 +318,21 @@ __global__ void k_ws_of(int32_t n, const double* inv_ws, float* ws) {
 // series of Eq. (hpp), alpha + alpha (1-alpha) P(x,x), with
 // P(x,x) = sum_v w(x,v)^2 / (ws(x) ws(v)) (Eq. (pmatrix)); one thread per row.
 template <typename WT>
-__global__ void k_self_prior(int32_t nu, const int64_t* rp_u, const WT* w_u, const int32_t* ci_u,
-                             const double* inv_ws_u, const double* inv_ws_v, double alpha, float* out) {
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= nu) return;
+__global__ __launch_bounds__(256) void k_self_prior(int32_t nu, const int64_t* rp_u, const WT* w_u, const int32_t* ci_u,
+                                                    const double* inv_ws_u, const double* inv_ws_v, double alpha,
+                                                    float* out) {
+    // one wavefront per row; lanes take strided entries, then a fixed tree
+    const int lane = threadIdx.x & 63;
+    const int32_t x = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (x >= nu) return;   // whole wavefront
+    const int64_t e0 = rp_u[x], e1 = rp_u[x + 1];
     double s = 0.0;
-    for (int64_t e = rp_u[x]; e < rp_u[x + 1]; ++e) {
+    for (int64_t e = e0 + lane; e < e1; e += 64) {
         const double q = (double)w_u[e];                  // w(x,v)/ws(v)
         s += q * q / inv_ws_v[ci_u[e]];                   // w^2 / ws(v)
     }
-    out[x] = rp_u[x + 1] > rp_u[x] ? (float)(alpha + alpha * (1.0 - alpha) * s * inv_ws_u[x]) : 0.0f;
+    for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m);
+    if (lane == 0) out[x] = e1 > e0 ? (float)(alpha + alpha * (1.0 - alpha) * s * inv_ws_u[x]) : 0.0f;
 }
 
 uint64_t splitmix(uint64_t& s) {
@@ -360,6 +382,7 @@ struct Model {
     float* loss_part = nullptr;
     int cap_u = 0, cap_x = 0;
     bf16* fsel = nullptr;     // [64][128] tower-f rows of the sources being predicted
+    float* csum = nullptr;    // [kColSplit][256] partial column sums
     int32_t* d_rows = nullptr;
 };
 
@@ -391,6 +414,11 @@ bhpp_status alloc_tower(TowerBuf& b, int cap) {
     return BHPP_OK;
 }
 
+void colsum(const float* X, int rows, int cols, float* part, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum, dim3(kColSplit, (cols + 63) / 64), dim3(256), 0, s, X, rows, cols, part);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((cols + 127) / 128), dim3(128), 0, s, part, cols, out);
+}
+
 // forward pass of one tower over rows b.X[0..n): z3 (FP32) and z3h (BF16)
 void tower_forward(const Model* m, int tower, TowerBuf& b, int n, hipStream_t s) {
     const bf16* P = m->theta_h + tower * kTower;
@@ -414,7 +442,7 @@ void tower_backward(Model* m, int tower, TowerBuf& b, int n, hipStream_t s) {
     GemmArgs a = gemm_args(kHid, kOut, n, b.a2, 1, kHid, b.d3h, kOut, 1, EPI_F32);
     a.outf = G + kOffW3;
     gemm(a, s);
-    hipLaunchKernelGGL(k_colsum, dim3((kOut + 127) / 128), dim3(128), 0, s, b.d3, n, kOut, G + kOffB3);
+    colsum(b.d3, n, kOut, m->csum, G + kOffB3, s);
     // d2 = (d3 W3^T) * gelu'(z2)
     a = gemm_args(n, kHid, kOut, b.d3h, kOut, 1, P + kOffW3, 1, kOut, EPI_GELU_BWD);
     a.aux = b.z2; a.outf = b.d2; a.outh = b.d2h;
@@ -422,7 +450,7 @@ void tower_backward(Model* m, int tower, TowerBuf& b, int n, hipStream_t s) {
     a = gemm_args(kHid, kHid, n, b.a1, 1, kHid, b.d2h, kHid, 1, EPI_F32);
     a.outf = G + kOffW2;
     gemm(a, s);
-    hipLaunchKernelGGL(k_colsum, dim3((kHid + 127) / 128), dim3(128), 0, s, b.d2, n, kHid, G + kOffB2);
+    colsum(b.d2, n, kHid, m->csum, G + kOffB2, s);
     // d1 = (d2 W2^T) * gelu'(z1)
     a = gemm_args(n, kHid, kHid, b.d2h, kHid, 1, P + kOffW2, 1, kHid, EPI_GELU_BWD);
     a.aux = b.z1; a.outf = b.d1; a.outh = b.d1h;
@@ -430,7 +458,7 @@ void tower_backward(Model* m, int tower, TowerBuf& b, int n, hipStream_t s) {
     a = gemm_args(kIn, kHid, n, b.X, 1, kIn, b.d1h, kHid, 1, EPI_F32);
     a.outf = G + kOffW1;
     gemm(a, s);
-    hipLaunchKernelGGL(k_colsum, dim3((kHid + 127) / 128), dim3(128), 0, s, b.d1, n, kHid, G + kOffB1);
+    colsum(b.d1, n, kHid, m->csum, G + kOffB1, s);
 }
 
 bhpp_status ensure_batch(Model* m, int nu_b, int nx_b) {
@@ -493,7 +521,7 @@ void model_free(Model* m) {
     if (!m) return;
     if (m->s) hipStreamSynchronize(m->s);
     void* p[] = {m->theta, m->theta_h, m->grad, m->adam_m, m->adam_v, m->X, m->ws, m->prior, m->Femb, m->Gemb,
-                 m->dK, m->T, m->wsx, m->idx, m->loss_part, m->fsel, m->d_rows};
+                 m->dK, m->T, m->wsx, m->idx, m->loss_part, m->fsel, m->d_rows, m->csum};
     for (void* q : p) hipFree(q);
     free_tower(m->tf);
     free_tower(m->tg);
@@ -544,7 +572,8 @@ bhpp_status model_create(Graph* g, uint64_t seed, Model** out) {
               hipMalloc((void**)&m->Femb, nu * kOut * 2) == hipSuccess &&
               hipMalloc((void**)&m->Gemb, nu * kOut * 2) == hipSuccess &&
               hipMalloc((void**)&m->fsel, (size_t)kMaxCols * kOut * 2) == hipSuccess &&
-              hipMalloc((void**)&m->d_rows, (size_t)kMaxCols * 4) == hipSuccess;
+              hipMalloc((void**)&m->d_rows, (size_t)kMaxCols * 4) == hipSuccess &&
+              hipMalloc((void**)&m->csum, (size_t)kColSplit * kHid * 4) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         model_free(m);
@@ -564,10 +593,10 @@ bhpp_status model_create(Graph* g, uint64_t seed, Model** out) {
                            m->X);
         hipLaunchKernelGGL(k_ws_of, dim3((g->nu + 255) / 256), dim3(256), 0, s, g->nu, g->inv_ws_u_d, m->ws);
         if (g->dtype == BHPP_DTYPE_F64)
-            hipLaunchKernelGGL(k_self_prior<double>, dim3((g->nu + 255) / 256), dim3(256), 0, s, g->nu, g->rp_u,
+            hipLaunchKernelGGL(k_self_prior<double>, dim3((g->nu + 3) / 4), dim3(256), 0, s, g->nu, g->rp_u,
                                (const double*)g->w_u, g->ci_u, g->inv_ws_u_d, g->inv_ws_v_d, g->info.alpha, m->prior);
         else
-            hipLaunchKernelGGL(k_self_prior<float>, dim3((g->nu + 255) / 256), dim3(256), 0, s, g->nu, g->rp_u,
+            hipLaunchKernelGGL(k_self_prior<float>, dim3((g->nu + 3) / 4), dim3(256), 0, s, g->nu, g->rp_u,
                                (const float*)g->w_u, g->ci_u, g->inv_ws_u_d, g->inv_ws_v_d, g->info.alpha, m->prior);
         m->h_prior.resize(nu);
         if (hipMemcpyAsync(m->h_prior.data(), m->prior, 4 * nu, hipMemcpyDeviceToHost, s) != hipSuccess ||

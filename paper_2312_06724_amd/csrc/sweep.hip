@@ -120,6 +120,14 @@ struct GatherArgs {
     int nt_stream;          // stream adjacency and row outputs past the caches
 };
 
+// Columns of a block in use: n_active[1] (0: all). A batch keeps its running
+// sources in the low columns, so lanes at or past the bound skip their loads
+// and stores (a 64-wide row read of 32 columns fetches one 128-byte line).
+__device__ __forceinline__ int live_cols(const int32_t* n_active, int cols) {
+    const int c = n_active[1];
+    return c > 0 && c < cols ? c : cols;
+}
+
 // Gather A (rows v of W^T) forms Q(v) = sum_x w(x,v) S(x) with S(x) = y(x)/ws(x)
 // for the pushed x and 0 otherwise; gather B (rows x of W) forms
 // G(x) = sum_v w(x,v)/ws(v) Q(v); the update then adds (1-alpha) G(x). Both are
@@ -198,6 +206,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x / kWave;
     const int col = lane;
+    const bool on = col < live_cols(p.n_active, COLS);
     double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
@@ -221,7 +230,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
 #pragma unroll
                 for (int jj = 0; jj < INF; ++jj) {
                     const int j = j0 + jj;
-                    v[jj] = j < n ? p.X[(size_t)rl(lx, j) * COLS + col] : VT(0);
+                    v[jj] = (j < n && on) ? p.X[(size_t)rl(lx, j) * COLS + col] : VT(0);
                 }
 #pragma unroll
                 for (int jj = 0; jj < INF; ++jj) {
@@ -230,11 +239,15 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
                         acc += rl(lw, j) * v[jj];
                         if (j + 1 == rend) {                 // last entry of the row: flush
                             if (split) {
-                                p.part[(size_t)T.slot * COLS + col] = acc;
-                                if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc != VT(0) ? 1 : 0;
+                                if (on) {
+                                    p.part[(size_t)T.slot * COLS + col] = acc;
+                                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc != VT(0) ? 1 : 0;
+                                }
                             } else {
                                 const size_t idx = (size_t)row * COLS + col;
-                                if (ns) st_nt(&p.OUT[idx], acc); else p.OUT[idx] = acc;
+                                if (on) {
+                                    if (ns) st_nt(&p.OUT[idx], acc); else p.OUT[idx] = acc;
+                                }
                                 const int64_t rend_abs = cb + rend;
                                 if (SIDE_A && acc != VT(0)) np += (double)(rend_abs - rbeg);
                                 rbeg = rend_abs;
@@ -364,12 +377,13 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
     const int tid = threadIdx.x;
     const int col = tid & (COLS - 1);
     const int sl = tid / COLS;
+    const bool on = col < live_cols(p.n_active, COLS);
     double np = 0.0;
     for (int i = blockIdx.x; i < n_split; i += gridDim.x) {
         const SplitRow S = split[i];
         VT a0 = VT(0), a1 = VT(0), a2 = VT(0), a3 = VT(0);
         int any = 0;
-        int s = S.slot_begin + sl;
+        int s = on ? S.slot_begin + sl : S.slot_end;
         for (; s + 3 * L < S.slot_end; s += 4 * L) {   // four independent loads in flight
             a0 += p.part[(size_t)s * COLS + col];
             a1 += p.part[(size_t)(s + L) * COLS + col];
@@ -393,7 +407,7 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
             }
             __syncthreads();
         }
-        if (sl == 0) {
+        if (sl == 0 && on) {
             const int row = S.row;
             p.OUT[(size_t)row * COLS + col] = sv[tid];
             if (SIDE_A && sa[tid]) np += (double)(p.rp[row + 1] - p.rp[row]);
@@ -414,6 +428,7 @@ __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ 
                                                         const ColState* st, const int32_t* n_active) {
     if (*n_active == 0) return;
     const int col = threadIdx.x & (COLS - 1);
+    if (col >= live_cols(n_active, COLS)) return;   // no barrier below
     const ColState& cs = st[col];
     const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
     const bool fresh = cs.fresh != 0;
@@ -463,7 +478,7 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
     const bool fresh = cs.fresh != 0;
     const int32_t src_row = cs.src_row;
     double r[kNumRed] = {0, 0, 0, 0, 0};
-    const size_t n = (size_t)n_rows * COLS;
+    const size_t n = col < live_cols(n_active, COLS) ? (size_t)n_rows * COLS : 0;   // unused columns: no work
     const size_t stride = (size_t)gridDim.x * kPassThreads;   // a multiple of COLS: the column stays fixed
     constexpr int U = 4;
     for (size_t i0 = (size_t)blockIdx.x * kPassThreads + threadIdx.x; i0 < n; i0 += U * stride) {
@@ -489,11 +504,13 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
             const VT s = sel ? y[k] : VT(0);
             VT acc = a[k];
             if (snap) SNAP[i] = acc;                              // forward image of pi_b when SS-Push returned
-            if (convert) {
+            if (convert == 1) {
                 // Eq. (fppr) plus the backward part of Alg. 5's combine: ACC -> beta' part
                 if (warm) acc = acc + ws_src * iw[k] * (snap ? acc : SNAP[i]);
                 else acc = acc * (VT(1) + ws_src * iw[k]);
-            }
+            } else if (convert == 3) {
+                acc = acc * ws_src * iw[k];   // SS-Push alone: the forward image back to pi_b(x) ~ pi(x, u)
+            }                                 // convert == 2 (PI-Push alone): ACC already holds pi_f's part
             acc += alpha * s;
             const VT yn = (y[k] - s) + one_minus_alpha * g[k];
             Y[i] = yn;
@@ -525,6 +542,10 @@ __device__ void set_rules(ColState& s, int mode, int ra, int rb, int conv) {
 __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
     s.np_ss = s.np;
     s.sum_r_ss = sum_r;
+    if (s.target == 2) {        // single-target HPP: SS-Push's pi_b is the result (Theorem 1)
+        set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, 3);
+        return;
+    }
     s.gamma = R[RED_SUM_Y];     // Eq. (gamma): sum_x ws(x)/ws(u) |r(x)| = sum_x |y(x)|
     s.np = 0.0;                 // Algorithm 4 repeats Algorithm 3 from its line 3 (n_p <- 0)
     s.snap = s.warm;            // a warm start keeps pi_b as it is now for the combine
@@ -533,7 +554,7 @@ __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
         // would hold: return pi_f from Eq. (fppr)
         s.pi_sel_iters = 1;
         s.pi_returned = 1;
-        set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, 1);
+        set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, s.target == 1 ? 2 : 1);
     } else {
         set_rules(s, MODE_PI_SEL, RULE_PI, RULE_PI, 0);
     }
@@ -570,18 +591,19 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
             if (R[RED_CNT_PI] == 0.0) {                                         // Eq. (fwd-eps)
                 s.np_pi = s.np;
                 s.pi_returned = 1;
-                set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, 1);
+                set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, s.target == 1 ? 2 : 1);
             } else if (s.np >= s.two_e * (log(s.gamma / sum_y) / s.ln_inv)) {  // Eq. (fwd-np)
                 s.np_pi = s.np;
                 s.sum_rf = sum_y;
                 const double tr = ceil(log(sum_y / s.eps_f) / s.ln_inv - 1.0);   // Eq. (t)
                 const int t = tr > 0.0 ? (int)tr : 0;
                 s.t = t;
+                const int cv = s.target == 1 ? 2 : 1;
                 if (t == 0) {
-                    set_rules(s, MODE_FINAL, RULE_NONE, RULE_ALL, 1);
+                    set_rules(s, MODE_FINAL, RULE_NONE, RULE_ALL, cv);
                 } else {
                     s.t_rem = t;
-                    set_rules(s, MODE_POWER, RULE_ALL, RULE_ALL, 1);
+                    set_rules(s, MODE_POWER, RULE_ALL, RULE_ALL, cv);
                 }
             }
             break;
@@ -601,26 +623,31 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
 
 // Reduction slots [0, off_u) carry only n_p (gather A and its fix-up);
 // [off_u, n_part) carry all reductions (update).
+constexpr int kControlThreads = kNumRed * kWave;   // one wavefront per reduction
+
 template <int COLS>
-__global__ __launch_bounds__(256) void k_control(ColState* st, const double* red, int n_part, int off_u,
-                                                 int32_t* n_active) {
-    __shared__ double sh[256];
+__global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const double* red, int n_part, int off_u,
+                                                             int32_t* n_active) {
     __shared__ double R[kNumRed];
     if (*n_active == 0) return;
     const int col = blockIdx.x;
-    for (int k = 0; k < kNumRed; ++k) {
-        const double* src = red + ((size_t)k * COLS + col) * n_part;
-        double s = 0.0;
-        for (int i = (k == RED_NP ? 0 : off_u) + threadIdx.x; i < n_part; i += 256) s += src[i];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) R[k] = sh[0];
-        __syncthreads();
+    if (col >= live_cols(n_active, COLS)) return;   // whole block
+    const int k = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const double* src = red + ((size_t)k * COLS + col) * n_part;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = (k == RED_NP ? 0 : off_u) + lane;
+    for (; i + 3 * kWave < n_part; i += 4 * kWave) {
+        a0 += src[i];
+        a1 += src[i + kWave];
+        a2 += src[i + 2 * kWave];
+        a3 += src[i + 3 * kWave];
     }
+    for (; i < n_part; i += kWave) a0 += src[i];
+    double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+    for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    if (lane == 0) R[k] = v;
+    __syncthreads();
     if (threadIdx.x == 0) control_update(st[col], R, n_active);
 }
 
@@ -925,7 +952,8 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
                        as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part, G.offU,
                        as<VT>(b.SNAP));
     prof_end(g, s, ev);
-    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(256), 0, s, b.st, b.red, G.n_part, G.offU, b.n_active);
+    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(kControlThreads), 0, s, b.st, b.red, G.n_part, G.offU,
+                       b.n_active);
     BHPP_HIP(hipGetLastError());
     return BHPP_OK;
 }
@@ -984,21 +1012,30 @@ static bhpp_status run_plain(Graph* g, const Block& b, hipStream_t s) {
 }
 
 static void init_state(ColState& c, double alpha, double ws_src, double eps, double eps_b_ratio, double lambda,
-                       int64_t ne) {
+                       int64_t ne, int target = 0) {
     memset(&c, 0, sizeof(c));
     c.alpha = alpha;
     c.ws_src = ws_src;
     c.eps = eps;
-    c.eps_b = eps * eps_b_ratio;
-    c.eps_f = eps - c.eps_b;                 // Algorithm 5, line 2
+    c.target = target;
+    // Algorithm 5, line 2; one direction alone takes the whole eps
+    c.eps_b = target == 1 ? 0.0 : target == 2 ? eps : eps * eps_b_ratio;
+    c.eps_f = eps - c.eps_b;
     c.k_ss = ws_src > 0 ? c.eps_b / ws_src : 0.0;
     c.k_pi = c.eps_f / lambda;
     c.two_e = 2.0 * (double)ne;
     c.ln_inv = log(1.0 / (1.0 - alpha));
-    c.mode = MODE_SS_SEL;                    // Algorithm 3 starts with selective pushes
-    c.ruleA = c.ruleB = RULE_SS;
     c.convert = 0;
     c.qid = -1;
+    if (target == 1) {
+        // single-source HPP: Algorithm 4 from (pi_b, r) = (0, e_u), gamma = 1
+        c.mode = MODE_PI_SEL;
+        c.ruleA = c.ruleB = RULE_PI;
+        c.gamma = 1.0;
+    } else {
+        c.mode = MODE_SS_SEL;                // Algorithm 3 starts with selective pushes
+        c.ruleA = c.ruleB = RULE_SS;
+    }
 }
 
 static void done_state(ColState& c) {
@@ -1112,9 +1149,9 @@ static bhpp_status warm_init(Graph* g, const WarmSource& src, Workspace& w, cons
         c.mode = MODE_POWER;
         c.ruleA = c.ruleB = RULE_ALL;
     }
-    const int32_t one = 1;
+    const int32_t one[2] = {1, 0};   // one active; all columns in use
     BHPP_HIP(hipMemcpyAsync(w.wst, ts.data(), sizeof(ColState) * ct, hipMemcpyHostToDevice, s));
-    BHPP_HIP(hipMemcpyAsync(w.wn_active, &one, 4, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.wn_active, one, 8, hipMemcpyHostToDevice, s));
     BHPP_HIP(hipMemcpyAsync(w.wcol_ids, cols.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
     switch (ct) {
         case 1: warm_front<1, WT>(g, w, s); break;
@@ -1194,7 +1231,8 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
                                g->tiles_u.split, g->tiles_u.n_split);
         rc = sparse_finish(g, w, io, w.scores, s);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_control<1>), dim3(1), dim3(256), 0, s, w.st, w.red, G.n_part, G.offU, w.n_active);
+        hipLaunchKernelGGL((k_control<1>), dim3(1), dim3(kControlThreads), 0, s, w.st, w.red, G.n_part, G.offU,
+                           w.n_active);
         BHPP_HIP(hipGetLastError());
         BHPP_HIP(hipMemcpyAsync(hs.data(), w.st, sizeof(ColState), hipMemcpyDeviceToHost, s));
         BHPP_HIP(hipStreamSynchronize(s));
@@ -1208,40 +1246,38 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
 // rows are extracted, their top-k computed, and the free columns take the
 // next queries; a reused column needs no reset pass (ColState::fresh).
 template <int COLS, typename VT, typename WT>
-static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* wstats, int n, const int32_t* src_ext,
+static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* wstats, int target, int n,
+                             const int32_t* src_ext,
                              const double* eps, double alpha, double lambda, void* scores_out, int k,
                              int exclude_self, int32_t* ids_out, void* vals_out, bhpp_query_stats* stats,
-                             hipStream_t s, std::vector<ColState>& carry, int& next, int& narrow_to) {
+                             hipStream_t s) {
     Workspace& w = g->ws;
     const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
                   w.SNAP};
     const Geometry G = geometry(g);
     const size_t nu = (size_t)g->nu, e = (size_t)g->elem;
-    narrow_to = 0;
     std::vector<ColState> hs(COLS);
     for (int c = 0; c < COLS; ++c) done_state(hs[c]);
-    const bool resumed = !carry.empty();   // narrowed from a wider block: the columns continue
-    if (resumed)
-        for (int c = 0; c < COLS; ++c) hs[c] = carry[c];
-    carry.clear();
+    int next = 0;
+    int ncols = n < COLS ? n : COLS;   // columns in use (the kernels skip the others)
     std::vector<int32_t> newcols;   // columns given a query since the last upload (warm starts)
     auto assign = [&](int c) {
         const int q = next++;
         const int32_t u = src_ext[q];
-        init_state(hs[c], alpha, g->h_ws_u[u], eps[q], g->info.eps_b_ratio, lambda, g->ne);
+        init_state(hs[c], alpha, g->h_ws_u[u], eps[q], g->info.eps_b_ratio, lambda, g->ne, target);
         hs[c].fresh = 1;
         hs[c].src_row = g->h_perm_u[u];
         hs[c].qid = q;
         if (warm.any()) newcols.push_back(c);
     };
-    if (!resumed)
-        for (int c = 0; c < COLS && next < n; ++c) assign(c);
+    for (int c = 0; c < COLS && next < n; ++c) assign(c);
     auto upload = [&]() -> bhpp_status {
         int32_t act = 0;
         for (int c = 0; c < COLS; ++c) act += hs[c].mode != MODE_DONE ? 1 : 0;
         w.h_active[2] = act;
+        w.h_active[3] = ncols;
         BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
-        BHPP_HIP(hipMemcpyAsync(w.n_active, &w.h_active[2], sizeof(int32_t), hipMemcpyHostToDevice, s));
+        BHPP_HIP(hipMemcpyAsync(w.n_active, &w.h_active[2], 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
         if (warm.any() && !newcols.empty()) {
             const bhpp_status r = warm_init<COLS, VT, WT>(g, warm, w, b, newcols, hs, s);
             newcols.clear();
@@ -1251,7 +1287,7 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
     };
     bhpp_status rc = upload();
     if (rc) return rc;
-    if (COLS == 1 && n == 1 && !resumed && !warm.any() && g->sparse_steps && !g->prof_on) {
+    if (COLS == 1 && n == 1 && target != 1 && !warm.any() && g->sparse_steps && !g->prof_on) {
         rc = sparse_phase<VT, WT>(g, w, hs, s);
         if (rc) return rc;
     }
@@ -1280,8 +1316,8 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
             if (hipEventSynchronize(evs[slot ^ 1]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
             const int act = w.h_active[slot ^ 1];
             const int done = live - act;
-            // with an empty queue, a block at most half busy narrows to the next power of two
-            round = act == 0 || (next < n && done >= R) || (g->narrow && next >= n && COLS > 1 && 2 * act <= COLS);
+            // with an empty queue, a block whose running sources fit in 32 columns packs them there
+            round = act == 0 || (next < n && done >= R) || (g->narrow && next >= n && ncols > 32 && act <= 32);
         }
         pending = true;
         ++chunk;
@@ -1342,17 +1378,16 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
         }
         pending = false;
         chunk = 0;
-        if (g->narrow && next >= n && live > 0 && COLS > 1 && 2 * live <= COLS) {
-            // narrow: the live columns move to a block of next_pow2(live) columns
+        if (g->narrow && next >= n && live > 0 && ncols > 32 && live <= 32) {
+            // pack: the running columns move to columns [0, live), in order
             // (states re-read: warm starts of this round were decided on the device)
             if (hipStreamSynchronize(s) != hipSuccess ||
                 hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost) != hipSuccess) {
                 rc = BHPP_DEVICE_ERROR;
                 break;
             }
-            const int c2 = next_pow2(live);
             std::vector<int32_t> map(kMaxCols, -1);
-            std::vector<ColState> nh(c2);
+            std::vector<ColState> nh(COLS);
             for (auto& c : nh) done_state(c);
             int j = 0;
             for (int c = 0; c < COLS; ++c)
@@ -1363,19 +1398,20 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
                 }
             int32_t* d_map = w.ex_tmp + 2 * kMaxCols;
             BHPP_HIP(hipMemcpyAsync(d_map, map.data(), sizeof(int32_t) * kMaxCols, hipMemcpyHostToDevice, s));
-            const size_t tot = nu * c2;
+            const size_t tot = nu * COLS;
             void* arrays[3] = {w.Y, w.ACC, w.SNAP};
             for (void* a : arrays) {
                 if (!a) continue;
                 hipLaunchKernelGGL(k_compact<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, as<VT>(a), COLS,
-                                   as<VT>(w.S), c2, d_map, g->nu);
+                                   as<VT>(w.S), COLS, d_map, g->nu);
                 BHPP_HIP(hipMemcpyAsync(a, w.S, tot * e, hipMemcpyDeviceToDevice, s));
             }
             BHPP_HIP(hipGetLastError());
+            hs = nh;
+            ncols = live;
+            rc = upload();
+            if (rc) break;
             BHPP_HIP(hipStreamSynchronize(s));   // map is read by the copy above
-            carry = nh;
-            narrow_to = c2;
-            break;
         }
     }
     if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
@@ -1385,31 +1421,22 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
 }
 
 template <typename VT, typename WT>
-static bhpp_status run_sched_dispatch(Graph* g, const WarmSource& model, bhpp_warm_stats* ws, int cols, int n,
+static bhpp_status run_sched_dispatch(Graph* g, const WarmSource& model, bhpp_warm_stats* ws, int target, int cols,
+                                      int n,
                                       const int32_t* src, const double* eps, double alpha, double lambda,
                                       void* scores, int k, int ex, int32_t* ids, void* vals, bhpp_query_stats* st,
                                       hipStream_t s) {
-    std::vector<ColState> carry;
-    int next = 0;
-    for (;;) {
-        int to = 0;
-        bhpp_status rc;
 #define BHPP_RUN(C) \
-    rc = run_sched<C, VT, WT>(g, model, ws, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s, carry, next, to)
-        switch (cols) {
-            case 1: BHPP_RUN(1); break;
-            case 2: BHPP_RUN(2); break;
-            case 4: BHPP_RUN(4); break;
-            case 8: BHPP_RUN(8); break;
-            case 16: BHPP_RUN(16); break;
-            case 32: BHPP_RUN(32); break;
-            case 64: BHPP_RUN(64); break;
-            default: return BHPP_INVALID_ARG;
-        }
-#undef BHPP_RUN
-        if (rc || to == 0) return rc;
-        cols = to;   // the block narrowed; continue with the live columns
+    return run_sched<C, VT, WT>(g, model, ws, target, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s)
+    switch (cols) {
+        case 1: BHPP_RUN(1);
+        case 2: BHPP_RUN(2);
+        case 4: BHPP_RUN(4);
+        case 8: BHPP_RUN(8);
+        case 64: BHPP_RUN(64);
+        default: return BHPP_INVALID_ARG;
     }
+#undef BHPP_RUN
 }
 
 void free_workspace(Workspace& w) {
@@ -1470,6 +1497,7 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
         (void)hipGetLastError();
         return BHPP_OUT_OF_MEMORY;
     }
+    BHPP_HIP(hipMemsetAsync(w.n_active, 0, 64, s));   // [0] active sources, [1] columns in use (0: all)
     const size_t nU = (size_t)g->nu * c;
     if (e == 8) {
         hipLaunchKernelGGL(k_fill<double>, dim3(2048), dim3(256), 0, s, as<double>(w.Y), nU, 0.0);
@@ -1485,8 +1513,9 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
     return BHPP_OK;
 }
 
-bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t n,
-                        const int32_t* src_ext, const double* eps, double alpha, double lambda, void* scores_out,
+bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_stats* wstats, int32_t target,
+                        int32_t n, const int32_t* src_ext, const double* eps, double alpha, double lambda,
+                        void* scores_out,
                         int32_t k, int32_t exclude_self, int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats,
                         hipStream_t caller) {
     WarmSource warm;
@@ -1500,14 +1529,17 @@ bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_st
     BHPP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     BHPP_HIP(hipEventRecord(ev, caller));
     BHPP_HIP(hipStreamWaitEvent(s, ev, 0));
-    const int cols = next_pow2(n < kMaxCols ? n : kMaxCols);
+    // one source: the entry-parallel kernels; up to 8: a block of that many
+    // columns; more: the 64-column kernels, with the columns past the batch
+    // skipped (measured faster than the narrower kernels from 16 columns on)
+    const int cols = n <= 8 ? next_pow2(n) : kMaxCols;
     bhpp_status rc = ensure_workspace(g, cols, s);
     if (rc == BHPP_OK) {
         if (g->dtype == BHPP_DTYPE_F64)
-            rc = run_sched_dispatch<double, double>(g, warm, wstats, cols, n, src_ext, eps, alpha, lambda,
+            rc = run_sched_dispatch<double, double>(g, warm, wstats, target, cols, n, src_ext, eps, alpha, lambda,
                                                     scores_out, k, exclude_self, topk_ids, topk_vals, stats, s);
         else
-            rc = run_sched_dispatch<float, float>(g, warm, wstats, cols, n, src_ext, eps, alpha, lambda,
+            rc = run_sched_dispatch<float, float>(g, warm, wstats, target, cols, n, src_ext, eps, alpha, lambda,
                                                   scores_out, k, exclude_self, topk_ids, topk_vals, stats, s);
     }
     // and the caller's stream waits for the library's work
@@ -1547,9 +1579,9 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
             c.ruleA = RULE_NONE;
             c.ruleB = RULE_ALL;
         }
-        int32_t one = 1;
+        int32_t one[2] = {1, 0};
         if (hipMemcpyAsync(b.st, &c, sizeof(c), hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(b.n_active, &one, 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            hipMemcpyAsync(b.n_active, one, 8, hipMemcpyHostToDevice, s) != hipSuccess)
             rc = BHPP_DEVICE_ERROR;
         hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, as<double>(b.Y), nU, 1.0);
         hipLaunchKernelGGL(k_fill<double>, dim3(1024), dim3(256), 0, s, as<double>(b.ACC), nU, 0.0);
@@ -1601,9 +1633,9 @@ static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out
         hs[c].fresh = 1;
         hs[c].src_row = c % g->nu;           // hubs first in internal order
     }
-    int32_t act = COLS_T;
+    int32_t act[2] = {COLS_T, 0};
     BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS_T, hipMemcpyHostToDevice, s));
-    BHPP_HIP(hipMemcpyAsync(w.n_active, &act, 4, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.n_active, act, 8, hipMemcpyHostToDevice, s));
     hipGraphExec_t* cache = &w.chunk_exec[log2i(COLS_T)];
     rc = launch_chunk<COLS_T, VT, WT>(g, b, G, s, cache);   // warm-up (and capture)
     if (rc) return rc;
@@ -1622,9 +1654,9 @@ static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out
     // leave the block inactive
     done_state(hs[0]);
     for (int c = 0; c < COLS_T; ++c) done_state(hs[c]);
-    act = 0;
+    act[0] = 0;
     BHPP_HIP(hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS_T, hipMemcpyHostToDevice, s));
-    BHPP_HIP(hipMemcpyAsync(w.n_active, &act, 4, hipMemcpyHostToDevice, s));
+    BHPP_HIP(hipMemcpyAsync(w.n_active, act, 8, hipMemcpyHostToDevice, s));
     BHPP_HIP(hipStreamSynchronize(s));
     return rc;
 }

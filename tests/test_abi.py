@@ -67,4 +67,5 @@ def test_argument_errors_need_no_device():
     assert L.bhpp_gemm_bf16(0, 1, 1, None, 0, None, 0, None, None) == -1
     L.bhpp_model_free(None)
     assert L.bhpp_set_eps_b_ratio(None, 0.3) == -1
-    assert L.bhpp_tune_eps_b(None, 1, None, 1e-6, 0.15, 1, None, None, None, None) == -1
+    assert L.bhpp_tune_eps_b(None, 1, None, 1e-6, 0.15, 1, None, None, None, None, None, None) == -1
+    assert L.bhpp_query_hpp(None, 1, None, None, 0.15, 1e-6, 0, None, None, None) == -1

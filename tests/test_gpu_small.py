@@ -219,9 +219,35 @@ def test_eps_b_split_keeps_the_bound(small, bh):
             assert d.min() >= -1e-10 and d.max() <= eps + 1e-10, (ratio, u)
             _, _, _, st = g.approx_bhpp(u, 0.15, eps, eps_b=ratio * eps)
             assert out["stats"][i]["t"] == st["t"] and out["stats"][i]["ss_switched"] == st["ss_switched"]
-    best, ms = G.tune_eps_b(small["sources"][6:], eps, [0.05, 0.2, paper])
-    assert best in (0.05, 0.2, paper) and np.all(ms > 0)
+    best, ms, gm, sw = G.tune_eps_b(small["sources"][6:], eps, [0.05, 0.2, paper], curve=True)
+    assert best in (0.05, 0.2, paper) and np.all(ms > 0) and np.all(sw > 0)
+    # Fig. 1's shape: gamma does not grow with eps_b (a larger eps_b leaves more residue)...
+    # here measured on the same sources: gamma at 0.05 <= gamma at the paper's ratio
+    assert gm[0] <= gm[2] + 1e-12
     G.set_eps_b_ratio(0.0)
     assert G.info()["eps_b_ratio"] == paper
     with pytest.raises(bh.BhppError):
         G.set_eps_b_ratio(1.0)
+
+
+def test_single_direction_hpp(small, bh):
+    """pi(u, .) by PI-Push alone (Theorem 2) and pi(., u) by SS-Push alone
+    (Theorem 1), each within [pi - eps, pi] of the dense solve; batches of
+    one (sparse steps) and of many give the same values."""
+    G, Pi = small["G"], small["Pi"]
+    src = small["sources"][:10]
+    for eps in (1e-4, 1e-7):
+        fwd, fst = G.query_hpp(src, eps, "forward")
+        bwd, bst = G.query_hpp(src, eps, "backward")
+        F, B = fwd.cpu().numpy(), bwd.cpu().numpy()
+        for i, u in enumerate(src):
+            u = int(u)
+            df = Pi[u, :] - F[i]
+            db = Pi[:, u] - B[i]
+            assert df.min() >= -1e-10 and df.max() <= eps + 1e-10, ("fwd", eps, u, df.min(), df.max())
+            assert db.min() >= -1e-10 and db.max() <= eps + 1e-10, ("bwd", eps, u, db.min(), db.max())
+            assert fst[i]["ss_sel_iters"] == 0 and bst[i]["pi_sel_iters"] == 0 and bst[i]["t"] == 0
+        one, _ = G.query_hpp(src[:1], eps, "backward")
+        assert np.abs(one.cpu().numpy()[0] - B[0]).max() <= 1e-12
+    with pytest.raises(bh.BhppError):
+        G.query_hpp(src, 1e-6, "forward", alpha=2.0)
