@@ -316,7 +316,7 @@ __global__ void k_ws_of(int32_t n, const double* inv_ws, float* ws) {
 
 // Structural self term of the prediction: the first two terms of the return
 // series of Eq. (hpp), alpha + alpha (1-alpha) P(x,x), with
-// P(x,x) = sum_v w(x,v)^2 / (ws(x) ws(v)) (Eq. (pmatrix)); one thread per row.
+// P(x,x) = sum_v w(x,v)^2 / (ws(x) ws(v)) (Eq. (pmatrix)); one wavefront per row.
 template <typename WT>
 __global__ __launch_bounds__(256) void k_self_prior(int32_t nu, const int64_t* rp_u, const WT* w_u, const int32_t* ci_u,
                                                     const double* inv_ws_u, const double* inv_ws_v, double alpha,
