@@ -51,6 +51,25 @@ def stored_traffic(kernel):
     return ent.get("bytes_per_launch")
 
 
+def copy_ceiling(torch):
+    """Read + write GB/s of a 1 GiB device-to-device copy (best of 5 timed on
+    the copy's own stream): the streaming rate the memory system sustains."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+
+
 def cpu_baseline(el, sources, wl, n_threads):
     import oracle
     g = oracle.Graph.from_edges(el)
@@ -336,6 +355,14 @@ def main():
                     kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
                                      gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
                              for i, k in enumerate(["gather_a", "gather_b", "update", "select"])})
+
+    copy_gbs = copy_ceiling(torch)
+    roofline["copy_gbs"] = round(copy_gbs, 1)
+    if roofline["traffic"]:
+        tgbs = roofline["traffic"] / (avg_ms * 1e-3) / 1e9
+        roofline["traffic_gbs"] = round(tgbs, 1)
+        roofline["traffic_frac_of_copy"] = round(tgbs / copy_gbs, 4)
+    log(f"device copy: {copy_gbs:.0f} GB/s read+write")
 
     # the eps split (Theorem 3 holds for any eps_b): tuned on 64 other sources,
     # then the benchmark's sources timed with it; the headline keeps Eq. (epsilon-b)

@@ -96,6 +96,26 @@ __device__ __forceinline__ int64_t rl(int64_t v, int j) {
 }
 __device__ __forceinline__ double rl(double v, int j) { return __longlong_as_double(rl((int64_t)__double_as_longlong(v), j)); }
 
+// Index of the calling wavefront in its block, as a wave-uniform (scalar)
+// value: tile indices derived from it then stay in scalar registers, so the
+// per-entry bounds tests are scalar branches instead of exec-masked regions.
+__device__ __forceinline__ int wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
+
+// A work tile read by a whole wavefront, broadcast from lane 0 so that its
+// fields are known to be wave-uniform (the loads themselves may be vector
+// loads, since the kernels also store to memory).
+__device__ __forceinline__ Tile load_tile(const Tile* tiles, int t) {
+    const Tile T = tiles[t];
+    Tile U;
+    U.row_begin = __builtin_amdgcn_readfirstlane(T.row_begin);
+    U.row_end = __builtin_amdgcn_readfirstlane(T.row_end);
+    U.e_begin = rl(T.e_begin, 0);
+    U.e_end = rl(T.e_end, 0);
+    U.slot = __builtin_amdgcn_readfirstlane(T.slot);
+    U.epar_log2 = __builtin_amdgcn_readfirstlane(T.epar_log2);
+    return U;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
 template <typename T>
@@ -145,12 +165,12 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
     __shared__ double sh[kPassThreads];
     if (*p.n_active == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    const int wid = wave_in_block();
     const int col = lane & (COLS - 1);
     double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
-        const Tile T = p.tiles[t];
+        const Tile T = load_tile(p.tiles, t);
         const int epar = min(1 << T.epar_log2, kWave / COLS);
         const int gl = epar * COLS;            // lanes per row
         const int ngroups = kWave / gl;
@@ -195,8 +215,63 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
 // neighbour ids, weights and the end offsets of the next 64 rows; it then
 // keeps INF row gathers in flight, taking each entry's neighbour id from its
 // lane with readlane. A row whose last entry is reached is flushed with a
-// store. Tiles hold no empty rows.
+// store. Tiles hold no empty rows. Tile bounds, chunk sizes and row ends are
+// wave-uniform (scalar registers); the live-column mask only guards the
+// stores.
 // ---------------------------------------------------------------------------
+template <typename VT, typename WT>
+struct Gather64State {
+    int row;          // current output row
+    int rend;         // its end, relative to the chunk start (> 64: later chunk)
+    int64_t rbeg;     // its first entry
+    VT acc;           // this lane's partial sum of the row
+    double np;        // this lane's push cost (gather A)
+};
+
+// One chunk of n entries starting at cb. FULL: n == 64, so no entry needs a
+// bounds test; otherwise loads past n re-read entry n-1 and are not used.
+template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL>
+__device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, const Tile& T, bool split, bool ns, bool on,
+                                               int col, int xcol, int64_t cb, int n, int32_t lx, VT lw, int mbase, int m_rel,
+                                               Gather64State<VT, WT>& st) {
+    constexpr int COLS = 64;
+    const int jend = FULL ? kWave : n;
+    for (int j0 = 0; j0 < jend; j0 += INF) {
+        VT v[INF];
+#pragma unroll
+        for (int jj = 0; jj < INF; ++jj) {
+            const int j = FULL ? j0 + jj : min(j0 + jj, n - 1);
+            v[jj] = p.X[(size_t)(uint32_t)rl(lx, j) * COLS + xcol];
+        }
+#pragma unroll
+        for (int jj = 0; jj < INF; ++jj) {
+            const int j = j0 + jj;
+            if (FULL || j < n) {
+                st.acc += rl(lw, j) * v[jj];
+                if (j + 1 == st.rend) {                 // last entry of the row: flush
+                    if (split) {
+                        if (on) {
+                            p.part[(size_t)T.slot * COLS + col] = st.acc;
+                            if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = st.acc != VT(0) ? 1 : 0;
+                        }
+                    } else {
+                        const size_t idx = (size_t)st.row * COLS + col;
+                        if (on) {
+                            if (ns) st_nt(&p.OUT[idx], st.acc); else p.OUT[idx] = st.acc;
+                        }
+                        const int64_t rend_abs = cb + st.rend;
+                        if (SIDE_A && st.acc != VT(0)) st.np += (double)(rend_abs - st.rbeg);
+                        st.rbeg = rend_abs;
+                    }
+                    st.acc = VT(0);
+                    ++st.row;
+                    st.rend = st.row - mbase < kWave ? rl(m_rel, st.row - mbase) : (1 << 30);
+                }
+            }
+        }
+    }
+}
+
 template <typename VT, typename WT, bool SIDE_A, int INF>
 __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p) {
     constexpr int COLS = 64;
@@ -204,64 +279,40 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     if (*p.n_active == 0) return;
     const bool ns = p.nt_stream != 0;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    const int wid = wave_in_block();
     const int col = lane;
     const bool on = col < live_cols(p.n_active, COLS);
-    double np = 0.0;
+    // lanes of unused columns read column 0 of the same row (lane 0's cache
+    // line, so no extra traffic and no divergent branch around the loads);
+    // their sums are never stored and their push cost is dropped
+    const int xcol = on ? col : 0;
+    Gather64State<VT, WT> st;
+    st.np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
-        const Tile T = p.tiles[t];
+        const Tile T = load_tile(p.tiles, t);
         const bool split = T.slot >= 0;
-        int row = T.row_begin;
-        int64_t rbeg = T.e_begin;
-        VT acc = VT(0);
+        st.row = T.row_begin;
+        st.rbeg = T.e_begin;
+        st.acc = VT(0);
         for (int64_t cb = T.e_begin; cb < T.e_end; cb += kWave) {
             const int n = (int)min((int64_t)kWave, T.e_end - cb);
             const int32_t lx = lane < n ? (ns ? ld_nt(&p.ci[cb + lane]) : p.ci[cb + lane]) : 0;
             const VT lw = lane < n ? (VT)(ns ? ld_nt(&p.w[cb + lane]) : p.w[cb + lane]) : VT(0);
-            const int mbase = row;
+            const int mbase = st.row;
             const int mr = mbase + lane;
             const int64_t m_end = split ? T.e_end : (mr < T.row_end ? p.rp[mr + 1] : T.e_end);
             // row ends relative to the chunk start (> 64: not in this chunk)
             const int m_rel = (int)min(m_end - cb, (int64_t)(1 << 30));
-            int rend = rl(m_rel, 0);
-            for (int j0 = 0; j0 < n; j0 += INF) {
-                VT v[INF];
-#pragma unroll
-                for (int jj = 0; jj < INF; ++jj) {
-                    const int j = j0 + jj;
-                    v[jj] = (j < n && on) ? p.X[(size_t)rl(lx, j) * COLS + col] : VT(0);
-                }
-#pragma unroll
-                for (int jj = 0; jj < INF; ++jj) {
-                    const int j = j0 + jj;
-                    if (j < n) {
-                        acc += rl(lw, j) * v[jj];
-                        if (j + 1 == rend) {                 // last entry of the row: flush
-                            if (split) {
-                                if (on) {
-                                    p.part[(size_t)T.slot * COLS + col] = acc;
-                                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc != VT(0) ? 1 : 0;
-                                }
-                            } else {
-                                const size_t idx = (size_t)row * COLS + col;
-                                if (on) {
-                                    if (ns) st_nt(&p.OUT[idx], acc); else p.OUT[idx] = acc;
-                                }
-                                const int64_t rend_abs = cb + rend;
-                                if (SIDE_A && acc != VT(0)) np += (double)(rend_abs - rbeg);
-                                rbeg = rend_abs;
-                            }
-                            acc = VT(0);
-                            ++row;
-                            rend = row - mbase < kWave ? rl(m_rel, row - mbase) : (1 << 30);
-                        }
-                    }
-                }
-            }
+            st.rend = rl(m_rel, 0);
+            if (n == kWave)
+                gather64_chunk<VT, WT, SIDE_A, INF, true>(p, T, split, ns, on, col, xcol, cb, n, lx, lw, mbase, m_rel, st);
+            else
+                gather64_chunk<VT, WT, SIDE_A, INF, false>(p, T, split, ns, on, col, xcol, cb, n, lx, lw, mbase, m_rel, st);
         }
     }
-    if (SIDE_A) block_column_sum<COLS>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
+    if (!on) st.np = 0.0;
+    if (SIDE_A) block_column_sum<COLS>(st.np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
                                        p.red_slot + blockIdx.x);
 }
 
@@ -279,12 +330,12 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
     __shared__ double sh[kPassThreads];
     if (*p.n_active == 0) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
+    const int wid = wave_in_block();
     const uint64_t lt_mask = lane ? (~0ull >> (kWave - lane)) : 0ull;   // lanes below this one
     double np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
-        const Tile T = p.tiles[t];
+        const Tile T = load_tile(p.tiles, t);
         const bool split = T.slot >= 0;
         int row = T.row_begin;
         int64_t open_begin = T.e_begin;   // first entry of the row still open
