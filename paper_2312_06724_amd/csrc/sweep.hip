@@ -116,6 +116,46 @@ __device__ __forceinline__ Tile load_tile(const Tile* tiles, int t) {
     return U;
 }
 
+// DPP move of v from another lane (0 where the source is outside the row or
+// the destination row is masked off): CTRL 0x111..0x118 shift right within a
+// row of 16 lanes, 0x142 broadcasts lane 15 of each row to the next row,
+// 0x143 broadcasts lane 31 to rows 2 and 3.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int64_t b = __double_as_longlong(v);
+    const int32_t lo = __builtin_amdgcn_update_dpp(0, (int32_t)(b & 0xFFFFFFFF), CTRL, ROWS, 0xF, true);
+    const int32_t hi = __builtin_amdgcn_update_dpp(0, (int32_t)(b >> 32), CTRL, ROWS, 0xF, true);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// Segmented inclusive sum across the wavefront: lane L returns the sum of
+// lanes start..L (start <= L is the first lane of L's segment), added in a
+// fixed order. Hillis-Steele steps of 1, 2, 4 and 8 lanes inside each row of
+// 16, then the lane-15 and lane-31 broadcasts carry row totals across rows;
+// every step adds only a source lane of the same segment.
+template <typename VT>
+__device__ __forceinline__ VT segmented_sum(VT v, int lane, int start) {
+    const int lr = lane & 15;
+    VT t;
+    t = dpp_mov<0x111, 0xF>(v);
+    if (lr >= 1 && lane - 1 >= start) v += t;
+    t = dpp_mov<0x112, 0xF>(v);
+    if (lr >= 2 && lane - 2 >= start) v += t;
+    t = dpp_mov<0x114, 0xF>(v);
+    if (lr >= 4 && lane - 4 >= start) v += t;
+    t = dpp_mov<0x118, 0xF>(v);
+    if (lr >= 8 && lane - 8 >= start) v += t;
+    t = dpp_mov<0x142, 0xA>(v);                       // rows 1 and 3 take lanes 15 and 47
+    if ((lane & 16) && start <= (lane & ~15) - 1) v += t;
+    t = dpp_mov<0x143, 0xC>(v);                       // rows 2 and 3 take lane 31
+    if ((lane & 32) && start <= 31) v += t;
+    return v;
+}
+
 template <typename T>
 __device__ __forceinline__ T ld_nt(const T* p) { return __builtin_nontemporal_load(p); }
 template <typename T>
@@ -378,12 +418,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
                 const uint64_t before = mask[u] & lt_mask;
                 const int seg = __popcll(before);                           // rows ended before this lane
                 const int start = before ? kWave - __clzll(before) : 0;      // first lane of this lane's row
-                VT sum = term;
-#pragma unroll
-                for (int d = 1; d < kWave; d <<= 1) {
-                    const VT up = __shfl_up(sum, d);
-                    if (lane - d >= start) sum += up;
-                }
+                VT sum = segmented_sum(term, lane, start);
                 if (seg == 0) sum += carry;
                 if ((mask[u] >> lane) & 1ull) {
                     p.OUT[(size_t)(row + seg)] = sum;
