@@ -52,14 +52,14 @@ def stored_traffic(kernel):
 
 
 def copy_ceiling(torch):
-    """Read + write GB/s of a 1 GiB device-to-device copy (best of 5 timed on
+    """Read + write GB/s of a 1 GiB device-to-device copy (best of 10 timed on
     the copy's own stream): the streaming rate the memory system sustains."""
     a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
     best = float("inf")
-    for _ in range(5):
+    for _ in range(10):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         b.copy_(a)
