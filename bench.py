@@ -79,7 +79,9 @@ def cpu_baseline(el, sources, wl, n_threads):
     t0 = time.perf_counter()
     _, st = g.approx_bhpp_many(sample, wl.alpha, wl.eps, eps_b, lam, nthreads=n_threads, keep=False)
     dt = time.perf_counter() - t0
+    per_thread = -(-len(sample) // n_threads)
     return dict(value=len(sample) / dt, unit="queries/s", cores=n_threads, kind="oracle",
+                ms_per_query_per_thread=round(dt * 1e3 / per_thread, 1),
                 sample=f"{len(sample)} of the {len(sources)} sources, one per thread, FP64 Approx-BHPP "
                        f"(Algorithms 1-5), lambda and eps_b precomputed; {dt:.1f} s wall")
 
