@@ -1837,12 +1837,19 @@ struct Server {
     int64_t admitted = 0, warm_started = 0, warm_fell_back = 0;
 };
 
+// Upload the column states, the number of unfinished requests and the column
+// bound: requests take the lowest free columns, so at light load the sweep
+// kernels skip the loads and stores of the columns above the highest one held.
 static bhpp_status server_upload(Server* sv) {
-    int32_t act = 0;
-    for (const ColState& c : sv->hs) act += c.mode != MODE_DONE ? 1 : 0;
+    int32_t act = 0, bound = 0;
+    for (int c = 0; c < sv->cols; ++c) {
+        act += sv->hs[c].mode != MODE_DONE ? 1 : 0;
+        if (sv->hs[c].qid >= 0) bound = c + 1;
+    }
     sv->ws.h_active[2] = act;
+    sv->ws.h_active[3] = bound < sv->cols ? bound : 0;   // 0: every column
     BHPP_HIP(hipMemcpyAsync(sv->ws.st, sv->hs.data(), sizeof(ColState) * sv->cols, hipMemcpyHostToDevice, sv->s));
-    BHPP_HIP(hipMemcpyAsync(sv->ws.n_active, &sv->ws.h_active[2], sizeof(int32_t), hipMemcpyHostToDevice, sv->s));
+    BHPP_HIP(hipMemcpyAsync(sv->ws.n_active, &sv->ws.h_active[2], 2 * sizeof(int32_t), hipMemcpyHostToDevice, sv->s));
     return BHPP_OK;
 }
 
