@@ -137,6 +137,13 @@ __global__ void k_degree_keys(int32_t n, const int64_t* rp, int reorder, uint64_
     const uint64_t d = (uint64_t)(rp[x + 1] - rp[x]);
     keys[x] = reorder ? (((uint64_t)0x7FFFFFFF - d) << 32) | (uint64_t)x : (uint64_t)x;
 }
+// out[i] = vals[idx[i]]
+template <typename T>
+__global__ void k_take(int64_t n, const int32_t* idx, const T* vals, T* out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = vals[idx[i]];
+}
+
 __global__ void k_perm_from_keys(int32_t n, const uint64_t* keys, int32_t* iperm, int32_t* perm) {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -239,7 +246,7 @@ void free_tiles(TileSet* ts) {
 
 void free_graph(Graph* g) {
     if (!g) return;
-    void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u, g->end_bits_u, g->end_bits_v,
+    void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->iw_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u, g->end_bits_u, g->end_bits_v,
                     g->inv_ws_u_d, g->inv_ws_v_d, g->perm_u, g->iperm_u, g->iperm_v, g->x_rp_u, g->x_ci_u, g->x_w_u,
                     g->x_rp_v, g->x_ci_v, g->x_w_v, g->x_ws_u, g->x_ws_v};
     for (void* p : ptrs) hipFree(p);
@@ -460,6 +467,12 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
         hipLaunchKernelGGL(k_inv_ws<float>, grid_for(nu), dim3(256), 0, s, nu, g->iperm_u, ws_u, g->inv_ws_u_f);
         hipLaunchKernelGGL(k_inv_ws<float>, grid_for(nv), dim3(256), 0, s, nv, iperm_v, ws_v, g->inv_ws_v_f);
     }
+    // 1/ws of each entry's U node along the rows of W^T, stored beside the
+    // adjacency: the 64-column V-side gather reads it with the indices when it
+    // applies the push rule itself
+    BHPP_HIP(hipMalloc(&g->iw_v, sizeof(WT) * std::max<int64_t>(m, 1)));
+    hipLaunchKernelGGL(k_take<WT>, grid_for(m), dim3(256), 0, s, m, g->ci_v,
+                       sizeof(WT) == 4 ? (const WT*)g->inv_ws_u_f : (const WT*)g->inv_ws_u_d, (WT*)g->iw_v);
     BHPP_HIP(hipGetLastError());
 
     // 6. external copies for export
@@ -562,7 +575,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
                         const void* ew, const bhpp_graph_opts& opts, hipStream_t s, Graph** out) {
     Graph* g = new (std::nothrow) Graph();
     if (!g) return BHPP_OUT_OF_MEMORY;
-    // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1"
+    // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=)
     if (const char* e = getenv("BHPP_TUNE")) {
         int v;
         const char* q;
@@ -573,6 +586,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "graphs=")) && sscanf(q, "graphs=%d", &v) == 1) g->use_graphs = v ? 1 : 0;
         if ((q = strstr(e, "sparse=")) && sscanf(q, "sparse=%d", &v) == 1) g->sparse_steps = v ? 1 : 0;
         if ((q = strstr(e, "narrow=")) && sscanf(q, "narrow=%d", &v) == 1) g->narrow = v ? 1 : 0;
+        if ((q = strstr(e, "fuse=")) && sscanf(q, "fuse=%d", &v) == 1) g->fuse_select = v ? 1 : 0;
     }
     if (opts.flags & BHPP_BUILD_DENSE_ONLY) g->sparse_steps = 0;
     if (opts.flags & BHPP_BUILD_FIXED_WIDTH) g->narrow = 0;

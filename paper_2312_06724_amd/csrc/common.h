@@ -157,6 +157,7 @@ struct Graph {
     // internal (degree-ordered) adjacency
     int64_t* rp_u = nullptr; int32_t* ci_u = nullptr; void* w_u = nullptr;   // w_u holds w(x,v)/ws(v)
     int64_t* rp_v = nullptr; int32_t* ci_v = nullptr; void* w_v = nullptr;   // w_v holds w(x,v)
+    void* iw_v = nullptr;            // per entry of W^T's rows: 1/ws of the entry's U node (graph dtype)
     float* inv_ws_u_f = nullptr; float* inv_ws_v_f = nullptr;     // F32 graphs
     double* inv_ws_u_d = nullptr; double* inv_ws_v_d = nullptr;   // both dtypes
     int32_t* deg_u = nullptr;    // degree of each internal U row
@@ -186,6 +187,7 @@ struct Graph {
     int inflight = 8;
     int nt_stream = 0;
     int use_graphs = 1;
+    int fuse_select = 1;             // 64-column blocks: gather A applies the push rule (no select pass)
     int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
     int narrow = 1;                  // batches narrow their block as sources finish
     double eps_b_paper = 0.5;        // eps_b / eps of Eq. (epsilon-b); info.eps_b_ratio is the one in use

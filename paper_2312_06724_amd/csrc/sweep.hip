@@ -178,6 +178,15 @@ struct GatherArgs {
     int n_part;
     int red_slot;           // first reduction slot of this launch
     int nt_stream;          // stream adjacency and row outputs past the caches
+    // k_gather64, gather A: when Yf is set the gather applies the push rule
+    // itself, S(x) = y(x)/ws(x) for the pushed x, reading Y, 1/ws of each
+    // entry's neighbour (iwf, stored beside the adjacency so that it arrives
+    // with the indices) and the column states (stf) instead of a selected copy
+    // S; a sweep in which a column starts a query (lazy reset) reads the S
+    // written by k_select
+    const VT* Yf = nullptr;
+    const VT* iwf = nullptr;     // per adjacency entry, beside ci and w
+    const ColState* stf = nullptr;
 };
 
 // Columns of a block in use: n_active[1] (0: all). A batch keeps its running
@@ -270,9 +279,10 @@ struct Gather64State {
 
 // One chunk of n entries starting at cb. FULL: n == 64, so no entry needs a
 // bounds test; otherwise loads past n re-read entry n-1 and are not used.
-template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL>
-__device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, const Tile& T, bool split, bool ns, bool on,
-                                               int col, int xcol, int64_t cb, int n, int32_t lx, VT lw, int mbase, int m_rel,
+template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL, bool FUSED>
+__device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, const VT* X, const PushTest<VT>& test,
+                                               const Tile& T, bool split, bool ns, bool on, int col, int xcol,
+                                               int64_t cb, int n, int32_t lx, VT lw, VT liw, int mbase, int m_rel,
                                                Gather64State<VT, WT>& st) {
     constexpr int COLS = 64;
     const int jend = FULL ? kWave : n;
@@ -281,13 +291,18 @@ __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, cons
 #pragma unroll
         for (int jj = 0; jj < INF; ++jj) {
             const int j = FULL ? j0 + jj : min(j0 + jj, n - 1);
-            v[jj] = p.X[(size_t)(uint32_t)rl(lx, j) * COLS + xcol];
+            v[jj] = X[(size_t)(uint32_t)rl(lx, j) * COLS + xcol];
         }
 #pragma unroll
         for (int jj = 0; jj < INF; ++jj) {
             const int j = j0 + jj;
             if (FULL || j < n) {
-                st.acc += rl(lw, j) * v[jj];
+                VT sv = v[jj];
+                if (FUSED) {   // the select pass's arithmetic: S = y/ws if pushed, else 0
+                    const VT yw = sv * rl(liw, j);
+                    sv = test(fabs(sv), fabs(yw)) ? yw : VT(0);
+                }
+                st.acc += rl(lw, j) * sv;
                 if (j + 1 == st.rend) {                 // last entry of the row: flush
                     if (split) {
                         if (on) {
@@ -326,6 +341,16 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     // line, so no extra traffic and no divergent branch around the loads);
     // their sums are never stored and their push cost is dropped
     const int xcol = on ? col : 0;
+    // gather A with the push rule applied here (see GatherArgs::Yf), unless a
+    // live column starts a query in this sweep
+    bool fused = false;
+    PushTest<VT> test(RULE_NONE, VT(0), VT(0));
+    if (SIDE_A && p.Yf != nullptr) {
+        const ColState& cs = p.stf[col];
+        fused = __ballot(on && cs.fresh != 0) == 0ull;
+        test = PushTest<VT>(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
+    }
+    const VT* X = fused ? p.Yf : p.X;
     Gather64State<VT, WT> st;
     st.np = 0.0;
     const int n_waves = gridDim.x * kWavesPerBlock;
@@ -339,16 +364,28 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
             const int n = (int)min((int64_t)kWave, T.e_end - cb);
             const int32_t lx = lane < n ? (ns ? ld_nt(&p.ci[cb + lane]) : p.ci[cb + lane]) : 0;
             const VT lw = lane < n ? (VT)(ns ? ld_nt(&p.w[cb + lane]) : p.w[cb + lane]) : VT(0);
+            const VT liw = fused && lane < n ? p.iwf[cb + lane] : VT(0);   // 1/ws of each entry's neighbour
             const int mbase = st.row;
             const int mr = mbase + lane;
             const int64_t m_end = split ? T.e_end : (mr < T.row_end ? p.rp[mr + 1] : T.e_end);
             // row ends relative to the chunk start (> 64: not in this chunk)
             const int m_rel = (int)min(m_end - cb, (int64_t)(1 << 30));
             st.rend = rl(m_rel, 0);
-            if (n == kWave)
-                gather64_chunk<VT, WT, SIDE_A, INF, true>(p, T, split, ns, on, col, xcol, cb, n, lx, lw, mbase, m_rel, st);
-            else
-                gather64_chunk<VT, WT, SIDE_A, INF, false>(p, T, split, ns, on, col, xcol, cb, n, lx, lw, mbase, m_rel, st);
+            if (fused) {
+                if (n == kWave)
+                    gather64_chunk<VT, WT, SIDE_A, INF, true, true>(p, X, test, T, split, ns, on, col, xcol, cb, n,
+                                                                    lx, lw, liw, mbase, m_rel, st);
+                else
+                    gather64_chunk<VT, WT, SIDE_A, INF, false, true>(p, X, test, T, split, ns, on, col, xcol, cb, n,
+                                                                     lx, lw, liw, mbase, m_rel, st);
+            } else {
+                if (n == kWave)
+                    gather64_chunk<VT, WT, SIDE_A, INF, true, false>(p, X, test, T, split, ns, on, col, xcol, cb, n,
+                                                                     lx, lw, liw, mbase, m_rel, st);
+                else
+                    gather64_chunk<VT, WT, SIDE_A, INF, false, false>(p, X, test, T, split, ns, on, col, xcol, cb,
+                                                                      n, lx, lw, liw, mbase, m_rel, st);
+            }
         }
     }
     if (!on) st.np = 0.0;
@@ -511,9 +548,15 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
 template <int COLS, typename VT>
 __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ Y, VT* __restrict__ S,
                                                         const VT* __restrict__ inv_ws, int32_t n_rows,
-                                                        const ColState* st, const int32_t* n_active) {
+                                                        const ColState* st, const int32_t* n_active, int only_fresh) {
     if (*n_active == 0) return;
     const int col = threadIdx.x & (COLS - 1);
+    if (only_fresh) {
+        // gather A applies the rule itself unless a live column starts a query
+        // (each wavefront covers all COLS == 64 columns, so this is uniform)
+        const bool fr = col < live_cols(n_active, COLS) && st[col].fresh != 0;
+        if (__ballot(fr) == 0ull) return;
+    }
     if (col >= live_cols(n_active, COLS)) return;   // no barrier below
     const ColState& cs = st[col];
     const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
@@ -955,7 +998,11 @@ static double launch_bytes(const Graph* g, int cols, int kind) {
     const double nu = (double)(g->nu - g->info.isolated_u), nv = (double)(g->nv - g->info.isolated_v);
     const double vt = sizeof(VT);
     const double visits = nnz * ((4.0 + sizeof(WT)) + cols * vt);
-    if (kind == 0) return visits + nv * (8.0 + cols * vt);
+    // gather A applying the push rule also reads 1/ws of each entry's
+    // neighbour; k_select then only runs in sweeps where a query starts
+    const bool fused = cols == 64 && g->fuse_select && vt == (double)g->elem;
+    if (kind == 0) return visits + (fused ? nnz * vt : 0.0) + nv * (8.0 + cols * vt);
+    if (kind == 3 && fused) return 0.0;
     if (kind == 1) return visits + nu * (8.0 + cols * vt);
     if (kind == 2)   // degrees, 1/ws_u; read Y, ACC, G; write Y, ACC
         return nu * 4.0 + nu * vt + 5.0 * nu * cols * vt;
@@ -998,9 +1045,15 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
         if (prof) prof_begin(g, s, kind, launch_bytes<VT, WT>(g, COLS, kind), ev);
     };
 
+    const bool fuse = COLS == 64 && g->fuse_select && sizeof(VT) == (size_t)g->elem;
+    if (fuse) {
+        A.Yf = as<VT>(b.Y);
+        A.iwf = reinterpret_cast<const VT*>(g->iw_v);
+        A.stf = b.st;
+    }
     pb(3);
     hipLaunchKernelGGL((k_select<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.S),
-                       inv_ws_u_of<VT>(g), g->nu, b.st, b.n_active);
+                       inv_ws_u_of<VT>(g), g->nu, b.st, b.n_active, fuse ? 1 : 0);
     prof_end(g, s, ev);
     pb(0);
     A.red_slot = G.offA;

@@ -89,3 +89,22 @@ def test_launch_settings_do_not_change_results(setup):
     S = G.query_batch(src, eps)["scores"].cpu().numpy()
     assert np.abs(S - base).max() <= 1e-6
     G.set_launch_config(cfg0)
+
+
+def test_fused_select_matches_select_pass(setup, monkeypatch):
+    """In 64-column blocks gather A applies the push rule itself (S = y/ws for
+    the pushed x) instead of reading a copy written by a select pass: same
+    products in the same order, so the same bits. 200 sources refill the
+    columns, so sweeps in which a column starts a query (where the select pass
+    still runs) are mixed in."""
+    s = setup
+    monkeypatch.setenv("BHPP_TUNE", "fuse=0")
+    G0 = s["bh"].Graph.from_edges(s["el"], dtype="f32", fixed_width=True)
+    monkeypatch.delenv("BHPP_TUNE")
+    G0.set_launch_config(s["Gf"].launch_config())
+    src, eps = s["src"], s["eps"]
+    a = s["Gf"].query_batch(src, eps, k=10)
+    b = G0.query_batch(src, eps, k=10)
+    assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
+    assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
+    assert a["stats"] == b["stats"]
