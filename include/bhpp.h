@@ -70,12 +70,19 @@ typedef struct {
    proportional to the frontier's edges) while the frontier's edges number
    under |E|/16. */
 #define BHPP_BUILD_DENSE_ONLY    4u
-/* A batch keeps its block width to the end. By default, once no source is
-   waiting and at most half of the block's columns are still running, the
-   block narrows to the next power of two above the running count (cheaper
-   sweeps); a source's result then depends, in its last bits, on when the
-   others finished. With this flag it does not: the same source gives the same
-   bits in any batch of the same width. */
+/* A batch keeps its sources in the columns they started in. By default, once
+   no source is waiting and at most 32 of a 64-column block's columns are still
+   running, the running columns are moved to the lowest columns and the sweeps
+   skip the others (cheaper sweeps). Every column is computed independently of
+   its position, so both give the same bits; the flag only turns the packing
+   off.
+   Launch settings can also be set at build time through the environment
+   variable BHPP_TUNE, a comma-separated list of tile=<entries per work tile>,
+   inflight=<4|8|16>, nt=<0|1> (non-temporal adjacency loads), graphs=<0|1>
+   (replay sweeps as HIP graphs), sparse=<0|1> (as BHPP_BUILD_DENSE_ONLY),
+   narrow=<0|1> (as BHPP_BUILD_FIXED_WIDTH) and fuse=<0|1> (64-column blocks:
+   the V-side gather applies the push rule itself instead of a separate
+   selection pass; same bits either way). */
 #define BHPP_BUILD_FIXED_WIDTH   8u
 
 typedef struct bhpp_graph bhpp_graph;  /* opaque; owns all of its device memory */

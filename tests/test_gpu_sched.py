@@ -58,20 +58,18 @@ def test_alone_and_in_mix_identical(setup):
 
 
 def test_narrowing_blocks_match_fixed_width(setup):
-    """A batch that narrows its block as sources finish gives every source the
-    same result as a fixed-width block, within the rounding of the narrower
-    kernels (both within eps of the exact scores: the other test)."""
+    """A batch that packs its running sources into the low columns as others
+    finish gives every source the bits of a block that never packs: each
+    column is computed independently of its position (a full queue-fed run,
+    one block that packs once, and a 40-source batch)."""
     s = setup
-    src, eps = s["src"][:64], s["eps"][:64]
-    a = s["G"].query_batch(src, eps, k=10)
-    b = s["Gf"].query_batch(src, eps, k=10)
-    Sa, Sb = a["scores"].cpu().numpy().astype(np.float64), b["scores"].cpu().numpy().astype(np.float64)
-    d = np.abs(Sa - Sb).max(axis=1)
-    assert np.all(d <= eps + 1e-6), d.max()
-    steps_a = np.array([x["steps"] for x in a["stats"]])
-    steps_b = np.array([x["steps"] for x in b["stats"]])
-    assert np.abs(steps_a - steps_b).max() <= 2
-    assert np.mean(d <= 1e-6) > 0.9
+    for sl in (slice(0, 64), slice(0, 200), slice(10, 50)):
+        src, eps = s["src"][sl], s["eps"][sl]
+        a = s["G"].query_batch(src, eps, k=10)
+        b = s["Gf"].query_batch(src, eps, k=10)
+        assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy()), sl
+        assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy()), sl
+        assert a["stats"] == b["stats"], sl
 
 
 def test_launch_settings_do_not_change_results(setup):

@@ -17,7 +17,7 @@ def setup():
     src = synth.sample_sources(el, 150, "degree", 12)
     eps = np.random.default_rng(5).choice([1e-5, 1e-6, 1e-7], size=src.size)
     print(f"[gpu] serve: graph 20k x 40k, 300k edges; {src.size} requests", flush=True)
-    # fixed width: the plain batched path then gives the bits a server gives
+    # the plain batched path gives the bits a server gives (columns keep their positions here)
     G = bh.Graph.from_edges(el, dtype="f32", fixed_width=True)
     return dict(bh=bh, el=el, src=src, eps=eps, G=G)
 
