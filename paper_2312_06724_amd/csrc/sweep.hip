@@ -667,7 +667,7 @@ __device__ void set_rules(ColState& s, int mode, int ra, int rb, int conv) {
     s.convert = conv;
 }
 
-// SS-Push returned: start PI-Push (Algorithm 5, line 3).
+// SS-Push returned: start PI-Push (Algorithm 5).
 __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
     s.np_ss = s.np;
     s.sum_r_ss = sum_r;
@@ -676,7 +676,7 @@ __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
         return;
     }
     s.gamma = R[RED_SUM_Y];     // Eq. (gamma): sum_x ws(x)/ws(u) |r(x)| = sum_x |y(x)|
-    s.np = 0.0;                 // Algorithm 4 repeats Algorithm 3 from its line 3 (n_p <- 0)
+    s.np = 0.0;                 // Algorithm 4 repeats Algorithm 3's push loop, which starts from n_p = 0
     s.snap = s.warm;            // a warm start keeps pi_b as it is now for the combine
     if (R[RED_CNT_PI] == 0.0) {
         // the first selective iteration would push nothing and Eq. (fwd-eps)
@@ -1157,7 +1157,7 @@ static void init_state(ColState& c, double alpha, double ws_src, double eps, dou
     c.ws_src = ws_src;
     c.eps = eps;
     c.target = target;
-    // Algorithm 5, line 2; one direction alone takes the whole eps
+    // Algorithm 5's split of eps; one direction alone takes the whole eps
     c.eps_b = target == 1 ? 0.0 : target == 2 ? eps : eps * eps_b_ratio;
     c.eps_f = eps - c.eps_b;
     c.k_ss = ws_src > 0 ? c.eps_b / ws_src : 0.0;
