@@ -194,8 +194,9 @@ bhpp_status bhpp_query_batch(bhpp_graph* g, int32_t n_src, const int32_t* source
  *   exclude_ids  device int32[n_rows] id to leave out per row (-1 none), or NULL
  *   ids_out      device int32[n_rows][k]
  *   vals_out     device [n_rows][k] of dtype
- * Requires 1 <= k <= n (k <= n-1 for a row with an exclusion). Scores must
- * not be NaN (the order of NaN is unspecified). Does not synchronise.
+ * Requires 1 <= k <= n (k <= n-1 for a row with an exclusion); k above 4096
+ * returns NOT_SUPPORTED. Scores must not be NaN (the order of NaN is
+ * unspecified). Does not synchronise.
  * Errors: INVALID_ARG, NOT_SUPPORTED, OUT_OF_MEMORY, DEVICE_ERROR.
  */
 bhpp_status bhpp_topk(const void* scores, int32_t n_rows, int32_t n, int32_t k,
@@ -370,8 +371,10 @@ bhpp_status bhpp_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, i
  * stream: width is the largest power of two <= max_width (1..64) whose
  * device workspace fits in mem_budget_bytes (<= 0: no cap); the workspace of
  * width 64 on a 1M x 2M graph is about 1.6 GB in FP32 (plus about 3 GB with a
- * model, for the warm starts). Admission: a request enters the block when a
- * column is free, at the next poll. With a model (nullable; it must have
+ * model, for the warm starts). k: 1 <= k <= min(4096, n_u - (exclude_self
+ * != 0)). Admission: a request enters the block at the next poll, in the
+ * lowest free column (the sweeps skip the columns above the highest one
+ * held). With a model (nullable; it must have
  * embeddings) admitted requests are warm-started as in bhpp_query_batch_warm
  * (warm_out of the poll, nullable, reports it); once the model's recent
  * starts fall back in 90% of cases (after 32 tries) only every 16th admission

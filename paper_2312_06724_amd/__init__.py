@@ -287,7 +287,7 @@ class Graph:
         ids = torch.empty((n, k), dtype=torch.int32, device="cuda") if k else None
         vals = torch.empty((n, k), dtype=self._tdtype, device="cuda") if k else None
         st = (QueryStats * max(1, n))()
-        common = (n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha, float(eps_arr[0]),
+        common = (n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha, (float(eps_arr[0]) if n else 0.0),
                   sc.data_ptr() if sc is not None else None, int(k), 1 if exclude_self else 0,
                   ids.data_ptr() if ids is not None else None, vals.data_ptr() if vals is not None else None,
                   ctypes.cast(st, ctypes.c_void_p) if stats else None)
@@ -362,7 +362,7 @@ class Graph:
         st = (QueryStats * max(1, n))()
         d = {"forward": 0, "backward": 1}[direction]
         rc = load_library().bhpp_query_hpp(self._h, n, src.ctypes.data, eps_arr.ctypes.data, alpha or self.alpha,
-                                           float(eps_arr[0]), d, out.data_ptr(),
+                                           (float(eps_arr[0]) if n else 0.0), d, out.data_ptr(),
                                            ctypes.cast(st, ctypes.c_void_p) if stats else None, _stream())
         _check(rc, "bhpp_query_hpp")
         return out, ([st[i].as_dict() for i in range(n)] if stats else None)

@@ -109,7 +109,7 @@ static bhpp_status query_batch_impl(bhpp_graph* h, bhpp_model* model, const void
     if (n_src < 0 || (n_src > 0 && !sources) || !valid_alpha(alpha)) return BHPP_INVALID_ARG;
     if (model && (model->h != h || !bhpp::model_ready(model->m))) return BHPP_INVALID_ARG;
     if (n_src == 0) return BHPP_OK;
-    if (k < 0 || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
+    if (k < 0 || k > bhpp::kTopkTmpK || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
     if (k > 0 && (!topk_ids || !topk_vals)) return BHPP_INVALID_ARG;
     std::vector<double> e((size_t)n_src);
     for (int32_t i = 0; i < n_src; ++i) {

@@ -119,6 +119,36 @@ def test_error_codes(small, bh):
     assert e.value.code == -1
 
 
+def test_degenerate_inputs(small, bh):
+    """An empty batch; a graph of one edge, where P = [1], so pi(u, u) = 1 and
+    beta(u, u) = 2; a graph without edges (every node isolated); and the
+    largest k (every other node, in (score, id) order)."""
+    G, g = small["G"], small["g"]
+    out = G.query_batch(np.array([], np.int32), 1e-6, k=5)
+    assert tuple(out["scores"].shape) == (0, g.n_u) and tuple(out["ids"].shape) == (0, 5)
+    assert out["stats"] == []
+    one = np.array([0], np.int32)
+    for dt, tol in (("f64", 1e-12), ("f32", 1e-6)):
+        G1 = bh.Graph(1, 1, one, one, np.array([2.5]), dtype=dt)
+        s = G1.query(0, 1e-6)[0].double().cpu().numpy()
+        assert 2.0 - 1e-6 - tol <= s[0] <= 2.0 + tol, (dt, s)
+        b = G1.query_batch([0, 0], 1e-6, k=1, exclude_self=False)
+        assert np.array_equal(b["ids"].cpu().numpy(), [[0], [0]])
+        assert np.array_equal(b["scores"].double().cpu().numpy()[:, 0], [s[0], s[0]])
+    G0 = bh.Graph(3, 2, np.array([], np.int32), np.array([], np.int32), np.array([]))
+    info = G0.info()
+    assert info["n_edges"] == 0 and info["isolated_u"] == 3 and info["isolated_v"] == 2
+    with pytest.raises(bh.BhppError) as e:
+        G0.query(1, 1e-6)
+    assert e.value.code == -3
+    u = int(small["sources"][0])
+    out = G.query_batch([u], 1e-7, k=g.n_u - 1, exclude_self=True)
+    S = out["scores"].cpu().numpy()[0]
+    rid, rval = oracle.topk_bruteforce(S, g.n_u - 1, exclude=u)
+    assert np.array_equal(out["ids"].cpu().numpy()[0], rid)
+    assert np.array_equal(out["vals"].cpu().numpy()[0], rval)
+
+
 def test_build_rejects_bad_input(bh):
     eu = np.array([0, 1], np.int32)
     ev = np.array([0, 1], np.int32)
