@@ -109,7 +109,6 @@ struct Workspace {
     void* S = nullptr;           // [n_u][cols] y/ws of the nodes pushed in the current sweep
     void* Q = nullptr;           // [n_v][cols] V-side residue of the current sweep
     void* partA = nullptr;       // [slots_v][cols] split-row partial sums
-    int32_t* partA_any = nullptr;
     void* partB = nullptr;       // [slots_u][cols]
     double* red = nullptr;       // [kNumRed][cols][n_part] per-block reductions
     int n_part = 0;
@@ -126,7 +125,6 @@ struct Workspace {
     // predictions of newly admitted queries (allocated on demand)
     int wcols = 0;
     void *wY = nullptr, *wS = nullptr, *wG = nullptr, *wQ = nullptr, *wpartA = nullptr, *wpartB = nullptr;
-    int32_t* wpartA_any = nullptr;
     double* wred = nullptr;
     ColState* wst = nullptr;
     int32_t* wn_active = nullptr;

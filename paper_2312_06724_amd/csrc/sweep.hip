@@ -42,6 +42,7 @@ namespace bhpp {
 // launch geometry
 // ---------------------------------------------------------------------------
 constexpr int kWavesPerBlock = kPassThreads / kWave;
+constexpr int kFixThreads = 1024;   // split-row fix-ups: 16 slot groups of 64 columns
 constexpr int kMaxPassBlocks = 2048;
 constexpr int kMaxFixBlocks = 1024;
 constexpr int kUpdateBlocks = 2048;
@@ -71,7 +72,7 @@ static Geometry geometry(const Graph* g) {
 // ---------------------------------------------------------------------------
 // Sum `v` over the lanes of the block that serve the same column and store
 // it at out[col * n_part + slot] (fixed order, so results are deterministic).
-template <int COLS>
+template <int COLS, int NW = kWavesPerBlock>
 __device__ __forceinline__ void block_column_sum(double v, double* sh, double* out, int n_part, int slot) {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
 #pragma unroll
@@ -80,7 +81,7 @@ __device__ __forceinline__ void block_column_sum(double v, double* sh, double* o
     __syncthreads();
     if ((int)threadIdx.x < COLS) {
         double s = 0.0;
-        for (int w = 0; w < kWavesPerBlock; ++w) s += sh[w * kWave + threadIdx.x];
+        for (int w = 0; w < NW; ++w) s += sh[w * kWave + threadIdx.x];
         out[(size_t)threadIdx.x * n_part + slot] = s;
     }
     __syncthreads();
@@ -171,7 +172,6 @@ struct GatherArgs {
     const VT* X;            // gathered vector: gather A S (over U), gather B Q (over V)
     VT* OUT;                // gather A: Q, gather B: G
     VT* part;               // split-row partial sums [slots][COLS]
-    int32_t* part_any;      // gather A: whether any neighbour was pushed
     const uint64_t* end_bits;  // bit e set iff entry e is the last of its row
     const int32_t* n_active;
     double* red;            // [kNumRed][COLS][n_part]
@@ -246,7 +246,6 @@ __global__ __launch_bounds__(kPassThreads) void k_gather(GatherArgs<VT, WT> p) {
             if (slot == 0 && valid) {
                 if (T.slot >= 0) {
                     p.part[(size_t)T.slot * COLS + col] = acc;
-                    if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = acc != VT(0) ? 1 : 0;
                 } else {
                     p.OUT[(size_t)row * COLS + col] = acc;
                     if (SIDE_A && acc != VT(0)) np += (double)(e1 - e0);
@@ -305,10 +304,7 @@ __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, cons
                 st.acc += rl(lw, j) * sv;
                 if (j + 1 == st.rend) {                 // last entry of the row: flush
                     if (split) {
-                        if (on) {
-                            p.part[(size_t)T.slot * COLS + col] = st.acc;
-                            if (SIDE_A) p.part_any[(size_t)T.slot * COLS + col] = st.acc != VT(0) ? 1 : 0;
-                        }
+                        if (on) p.part[(size_t)T.slot * COLS + col] = st.acc;
                     } else {
                         const size_t idx = (size_t)st.row * COLS + col;
                         if (on) {
@@ -478,25 +474,22 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
         if (split) {
 #pragma unroll
             for (int m = 1; m < kWave; m <<= 1) part += __shfl_xor(part, m);
-            if (lane == 0) {
-                p.part[T.slot] = part;
-                if (SIDE_A) p.part_any[T.slot] = part != VT(0) ? 1 : 0;
-            }
+            if (lane == 0) p.part[T.slot] = part;
         }
     }
     if (SIDE_A) block_column_sum<1>(np, sh, p.red + (size_t)RED_NP * p.n_part, p.n_part, p.red_slot + blockIdx.x);
 }
 
 // Fix-up of split rows, one block per row: thread (sl, col) adds the pieces
-// sl, sl + L, sl + 2L, ... (L = threads / COLS) in order, the block then adds
-// the L partial sums in a fixed tree, and writes the row like the gather.
+// sl, sl + L, sl + 2L, ... (L = threads / COLS) into eight running sums (eight
+// loads in flight: a hub row has hundreds of pieces), the block then adds the
+// L partial sums in a fixed tree, and writes the row like the gather.
 template <int COLS, typename VT, typename WT, bool SIDE_A>
-__global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, const SplitRow* split, int n_split) {
-    __shared__ double sh[kPassThreads];
-    __shared__ VT sv[kPassThreads];
-    __shared__ int32_t sa[kPassThreads];
+__global__ __launch_bounds__(kFixThreads) void k_fixup(GatherArgs<VT, WT> p, const SplitRow* split, int n_split) {
+    __shared__ double sh[kFixThreads];
+    __shared__ VT sv[kFixThreads];
     if (*p.n_active == 0) return;
-    constexpr int L = kPassThreads / COLS;
+    constexpr int L = kFixThreads / COLS;
     const int tid = threadIdx.x;
     const int col = tid & (COLS - 1);
     const int sl = tid / COLS;
@@ -504,41 +497,34 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup(GatherArgs<VT, WT> p, co
     double np = 0.0;
     for (int i = blockIdx.x; i < n_split; i += gridDim.x) {
         const SplitRow S = split[i];
-        VT a0 = VT(0), a1 = VT(0), a2 = VT(0), a3 = VT(0);
-        int any = 0;
+        VT a[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = VT(0);
         int s = on ? S.slot_begin + sl : S.slot_end;
-        for (; s + 3 * L < S.slot_end; s += 4 * L) {   // four independent loads in flight
-            a0 += p.part[(size_t)s * COLS + col];
-            a1 += p.part[(size_t)(s + L) * COLS + col];
-            a2 += p.part[(size_t)(s + 2 * L) * COLS + col];
-            a3 += p.part[(size_t)(s + 3 * L) * COLS + col];
-            if (SIDE_A)
-                any |= p.part_any[(size_t)s * COLS + col] | p.part_any[(size_t)(s + L) * COLS + col] |
-                       p.part_any[(size_t)(s + 2 * L) * COLS + col] | p.part_any[(size_t)(s + 3 * L) * COLS + col];
+        for (; s + 7 * L < S.slot_end; s += 8 * L) {   // eight independent loads in flight
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] += p.part[(size_t)(s + j * L) * COLS + col];
         }
-        for (; s < S.slot_end; s += L) {
-            a0 += p.part[(size_t)s * COLS + col];
-            if (SIDE_A) any |= p.part_any[(size_t)s * COLS + col];
-        }
-        sv[tid] = (a0 + a1) + (a2 + a3);
-        sa[tid] = any;
+        for (; s < S.slot_end; s += L) a[0] += p.part[(size_t)s * COLS + col];
+        sv[tid] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         __syncthreads();
         for (int h = L / 2; h > 0; h >>= 1) {
-            if (sl < h) {
-                sv[tid] += sv[tid + h * COLS];
-                sa[tid] |= sa[tid + h * COLS];
-            }
+            if (sl < h) sv[tid] += sv[tid + h * COLS];
             __syncthreads();
         }
         if (sl == 0 && on) {
             const int row = S.row;
-            p.OUT[(size_t)row * COLS + col] = sv[tid];
-            if (SIDE_A && sa[tid]) np += (double)(p.rp[row + 1] - p.rp[row]);
+            const VT q = sv[tid];
+            p.OUT[(size_t)row * COLS + col] = q;
+            // gather A: the V node is pushed (its cost counted) when its residue is
+            // non-zero, the rule the unsplit rows apply to their sums
+            if (SIDE_A && q != VT(0)) np += (double)(p.rp[row + 1] - p.rp[row]);
         }
         __syncthreads();
     }
-    if (SIDE_A) block_column_sum<COLS>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
-                                       p.red_slot + blockIdx.x);
+    if (SIDE_A)
+        block_column_sum<COLS, kFixThreads / kWave>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
+                                                    p.red_slot + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -943,7 +929,6 @@ struct Block {
     void* G;
     void* Q;
     void* partA;
-    int32_t* partA_any;
     void* partB;
     double* red;
     ColState* st;
@@ -1023,7 +1008,6 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     A.X = as<VT>(b.S);
     A.OUT = as<VT>(b.Q);
     A.part = as<VT>(b.partA);
-    A.part_any = b.partA_any;
     A.end_bits = g->end_bits_v;
     A.n_active = b.n_active;
     A.red = b.red;
@@ -1038,7 +1022,6 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     B.X = as<VT>(b.Q);
     B.OUT = as<VT>(b.G);
     B.part = as<VT>(b.partB);
-    B.part_any = nullptr;
     B.end_bits = g->end_bits_u;
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto pb = [&](int kind) {
@@ -1066,7 +1049,7 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     prof_end(g, s, ev);
     // the fix-up always runs: its blocks also write their reduction slots
     A.red_slot = G.offFA;
-    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kPassThreads), 0, s, A,
+    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kFixThreads), 0, s, A,
                        g->tiles_v.split, g->tiles_v.n_split);
     pb(1);
     B.red_slot = 0;
@@ -1078,7 +1061,7 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
         hipLaunchKernelGGL((k_gather<COLS, VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
     prof_end(g, s, ev);
     if (g->tiles_u.n_split > 0)
-        hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
+        hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
                            g->tiles_u.split, g->tiles_u.n_split);
 }
 
@@ -1216,7 +1199,7 @@ static bhpp_status ensure_warm(Graph* g, Workspace& w, int ct, hipStream_t s) {
         w.bytes += (size_t)g->nu * w.cols * w.elem;
     }
     if (w.wcols >= ct) return BHPP_OK;
-    void* old[] = {w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB, w.wpartA_any, w.wred, w.wst, w.wn_active, w.wP,
+    void* old[] = {w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB, w.wred, w.wst, w.wn_active, w.wP,
                    w.wres, w.wcol_ids};
     for (void* p : old) hipFree(p);
     w.wcols = 0;
@@ -1225,7 +1208,6 @@ static bhpp_status ensure_warm(Graph* g, Workspace& w, int ct, hipStream_t s) {
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
     const bool ok = A(&w.wY, nu * c * 8) && A(&w.wS, nu * c * 8) && A(&w.wG, nu * c * 8) && A(&w.wQ, nv * c * 8) &&
                     A(&w.wpartA, (size_t)g->tiles_v.n_slots * c * 8) &&
-                    A((void**)&w.wpartA_any, (size_t)g->tiles_v.n_slots * c * 4) &&
                     A(&w.wpartB, (size_t)g->tiles_u.n_slots * c * 8) &&
                     A((void**)&w.wred, (size_t)kNumRed * c * G.n_part * 8) &&
                     A((void**)&w.wst, sizeof(ColState) * c) && A((void**)&w.wn_active, 64) &&
@@ -1242,7 +1224,7 @@ static bhpp_status ensure_warm(Graph* g, Workspace& w, int ct, hipStream_t s) {
 
 template <int CT, typename WT>
 static void warm_front(Graph* g, Workspace& w, hipStream_t s) {
-    const Block tb{w.wY, nullptr, w.wS, w.wG, w.wQ, w.wpartA, w.wpartA_any, w.wpartB, w.wred, w.wst, w.wn_active,
+    const Block tb{w.wY, nullptr, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB, w.wred, w.wst, w.wn_active,
                    nullptr, nullptr};
     launch_front<CT, double, WT>(g, tb, geometry(g), s, false);
 }
@@ -1348,7 +1330,6 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
     B.X = as<VT>(w.fQ);
     B.OUT = as<VT>(w.scores);
     B.part = as<VT>(w.partB);
-    B.part_any = nullptr;
     B.end_bits = g->end_bits_u;
     B.n_active = w.n_active;
     B.red = w.red;
@@ -1366,7 +1347,7 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
         if (!io.done) break;
         hipLaunchKernelGGL((k_gather1<VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
         if (g->tiles_u.n_split > 0)
-            hipLaunchKernelGGL((k_fixup<1, VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
+            hipLaunchKernelGGL((k_fixup<1, VT, WT, false>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
                                g->tiles_u.split, g->tiles_u.n_split);
         rc = sparse_finish(g, w, io, w.scores, s);
         if (rc) return rc;
@@ -1391,7 +1372,7 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
                              int exclude_self, int32_t* ids_out, void* vals_out, bhpp_query_stats* stats,
                              hipStream_t s) {
     Workspace& w = g->ws;
-    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.h_active,
                   w.SNAP};
     const Geometry G = geometry(g);
     const size_t nu = (size_t)g->nu, e = (size_t)g->elem;
@@ -1584,9 +1565,9 @@ void free_workspace(Workspace& w) {
             hipGraphExecDestroy(x);
             x = nullptr;
         }
-    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.scores,
+    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.scores,
                     w.ids_tmp, w.vals_tmp, w.ex_tmp, w.SNAP, w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB,
-                    w.wpartA_any, w.wred, w.wst, w.wn_active, w.wP, w.wres, w.wcol_ids, w.fF, w.fS, w.fDeg,
+                    w.wred, w.wst, w.wn_active, w.wP, w.wres, w.wcol_ids, w.fF, w.fS, w.fDeg,
                     w.fOffs, w.fTV, w.fQ, w.fMark, w.fCnt, w.fScanTmp};
     for (void* p : ptrs) hipFree(p);
     if (w.h_active) hipHostFree(w.h_active);
@@ -1601,7 +1582,7 @@ void free_workspace(Workspace& w) {
 size_t workspace_bytes(const Graph* g, int cols) {
     const Geometry G = geometry(g);
     const size_t e = (size_t)g->elem, c = (size_t)cols;
-    return (size_t)g->nu * c * e * 4 + (size_t)g->nv * c * e + (size_t)g->tiles_v.n_slots * c * (e + 4) +
+    return (size_t)g->nu * c * e * 4 + (size_t)g->nv * c * e + (size_t)g->tiles_v.n_slots * c * e +
            (size_t)g->tiles_u.n_slots * c * e + (size_t)kNumRed * c * G.n_part * 8 + sizeof(ColState) * c +
            (size_t)kMaxCols * kTopkTmpK * (4 + e) + 4096;
 }
@@ -1622,7 +1603,6 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
     bool ok = alloc(&w.Y, (size_t)g->nu * c * e) && alloc(&w.ACC, (size_t)g->nu * c * e) &&
               alloc(&w.S, (size_t)g->nu * c * e) &&
               alloc(&w.Q, (size_t)g->nv * c * e) && alloc(&w.partA, (size_t)g->tiles_v.n_slots * c * e) &&
-              alloc((void**)&w.partA_any, (size_t)g->tiles_v.n_slots * c * 4) &&
               alloc(&w.partB, (size_t)g->tiles_u.n_slots * c * e) &&
               alloc((void**)&w.red, (size_t)kNumRed * c * G.n_part * 8 + 64 * 4) &&
               alloc((void**)&w.st, sizeof(ColState) * c) && alloc((void**)&w.n_active, 64) &&
@@ -1697,7 +1677,7 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
     const size_t nU = (size_t)g->nu, nV = (size_t)g->nv;
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
     bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.S, nU * 8) && A(&b.G, nU * 8) && A(&b.Q, nV * 8) &&
-              A(&b.partA, (size_t)g->tiles_v.n_slots * 8) && A((void**)&b.partA_any, (size_t)g->tiles_v.n_slots * 4) &&
+              A(&b.partA, (size_t)g->tiles_v.n_slots * 8) &&
               A(&b.partB, (size_t)g->tiles_u.n_slots * 8) && A((void**)&b.red, (size_t)kNumRed * G.n_part * 8) &&
               A((void**)&b.st, sizeof(ColState)) && A((void**)&b.n_active, 64) &&
               hipHostMalloc((void**)&b.h_active, 64) == hipSuccess;
@@ -1736,7 +1716,7 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
         }
     }
     g->prof_on = saved_prof;
-    void* ptrs[] = {b.Y, b.ACC, b.S, b.G, b.Q, b.partA, b.partA_any, b.partB, b.red, b.st, b.n_active};
+    void* ptrs[] = {b.Y, b.ACC, b.S, b.G, b.Q, b.partA, b.partB, b.red, b.st, b.n_active};
     for (void* p : ptrs) hipFree(p);
     if (b.h_active) hipHostFree(b.h_active);
     return rc;
@@ -1759,7 +1739,7 @@ static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out
     bhpp_status rc = ensure_workspace(g, COLS_T, s);
     if (rc) return rc;
     Workspace& w = g->ws;
-    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.h_active,
                   w.SNAP};
     const Geometry G = geometry(g);
     std::vector<ColState> hs(COLS_T);
@@ -1911,7 +1891,7 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
                                     bhpp_warm_stats* wst, int32_t* n_out) {
     Graph* g = sv->g;
     Workspace& w = sv->ws;
-    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partA_any, w.partB, w.red, w.st, w.n_active, w.h_active,
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.h_active,
                   w.SNAP};
     std::vector<int32_t> newcols;
     const Geometry G = geometry(g);
@@ -2041,7 +2021,7 @@ void server_destroy(Server* sv) {
 static size_t warm_bytes(const Graph* g, int cols) {
     const Geometry G = geometry(g);
     const size_t c = (size_t)cols, nu = (size_t)g->nu, nv = (size_t)g->nv;
-    return nu * c * g->elem + nu * c * (3 * 8 + 4) + nv * c * 8 + (size_t)g->tiles_v.n_slots * c * 12 +
+    return nu * c * g->elem + nu * c * (3 * 8 + 4) + nv * c * 8 + (size_t)g->tiles_v.n_slots * c * 8 +
            (size_t)g->tiles_u.n_slots * c * 8 + (size_t)kNumRed * c * G.n_part * 8 + 2 * c * kUpdateBlocks * 8 + 4096;
 }
 
