@@ -480,6 +480,39 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
     if (SIDE_A) block_column_sum<1>(np, sh, p.red + (size_t)RED_NP * p.n_part, p.n_part, p.red_slot + blockIdx.x);
 }
 
+// Fix-up of split rows for one source: one wavefront per row, lane l adding
+// pieces l, l + 64, ... (four loads in flight), then a butterfly across the
+// lanes (every lane ends with the same bits: each step adds two equal pairs).
+template <typename VT, typename WT, bool SIDE_A>
+__global__ __launch_bounds__(kPassThreads) void k_fixup1(GatherArgs<VT, WT> p, const SplitRow* split, int n_split) {
+    __shared__ double sh[kPassThreads];
+    if (*p.n_active == 0) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = wave_in_block();
+    double np = 0.0;
+    for (int i = blockIdx.x * kWavesPerBlock + wid; i < n_split; i += gridDim.x * kWavesPerBlock) {
+        const SplitRow S = split[i];
+        VT a0 = VT(0), a1 = VT(0), a2 = VT(0), a3 = VT(0);
+        int sl = S.slot_begin + lane;
+        for (; sl + 3 * kWave < S.slot_end; sl += 4 * kWave) {
+            a0 += p.part[sl];
+            a1 += p.part[sl + kWave];
+            a2 += p.part[sl + 2 * kWave];
+            a3 += p.part[sl + 3 * kWave];
+        }
+        for (; sl < S.slot_end; sl += kWave) a0 += p.part[sl];
+        VT v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+        for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m);
+        if (lane == 0) {
+            p.OUT[S.row] = v;
+            // gather A: the V node's push cost counts when its residue is non-zero
+            if (SIDE_A && v != VT(0)) np += (double)(p.rp[S.row + 1] - p.rp[S.row]);
+        }
+    }
+    if (SIDE_A) block_column_sum<1>(np, sh, p.red + (size_t)RED_NP * p.n_part, p.n_part, p.red_slot + blockIdx.x);
+}
+
 // Fix-up of split rows, one block per row: thread (sl, col) adds the pieces
 // sl, sl + L, sl + 2L, ... (L = threads / COLS) into eight running sums (eight
 // loads in flight: a hub row has hundreds of pieces), the block then adds the
@@ -738,30 +771,39 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
 
 // Reduction slots [0, off_u) carry only n_p (gather A and its fix-up);
 // [off_u, n_part) carry all reductions (update).
-constexpr int kControlThreads = kNumRed * kWave;   // one wavefront per reduction
-
+constexpr int kControlWaves = 3;                                    // wavefronts per reduction
+constexpr int kControlThreads = kNumRed * kControlWaves * kWave;
 template <int COLS>
 __global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const double* red, int n_part, int off_u,
                                                              int32_t* n_active) {
+    __shared__ double P[kNumRed][kControlWaves];
     __shared__ double R[kNumRed];
     if (*n_active == 0) return;
     const int col = blockIdx.x;
     if (col >= live_cols(n_active, COLS)) return;   // whole block
-    const int k = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    const int k = wv / kControlWaves, sub = wv % kControlWaves;
     const double* src = red + ((size_t)k * COLS + col) * n_part;
+    constexpr int stride = kControlWaves * kWave;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int i = (k == RED_NP ? 0 : off_u) + lane;
-    for (; i + 3 * kWave < n_part; i += 4 * kWave) {
+    int i = (k == RED_NP ? 0 : off_u) + sub * kWave + lane;
+    for (; i + 3 * stride < n_part; i += 4 * stride) {
         a0 += src[i];
-        a1 += src[i + kWave];
-        a2 += src[i + 2 * kWave];
-        a3 += src[i + 3 * kWave];
+        a1 += src[i + stride];
+        a2 += src[i + 2 * stride];
+        a3 += src[i + 3 * stride];
     }
-    for (; i < n_part; i += kWave) a0 += src[i];
+    for (; i < n_part; i += stride) a0 += src[i];
     double v = (a0 + a1) + (a2 + a3);
 #pragma unroll
     for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
-    if (lane == 0) R[k] = v;
+    if (lane == 0) P[k][sub] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < kNumRed) {
+        double t = 0.0;
+        for (int j = 0; j < kControlWaves; ++j) t += P[threadIdx.x][j];
+        R[threadIdx.x] = t;
+    }
     __syncthreads();
     if (threadIdx.x == 0) control_update(st[col], R, n_active);
 }
@@ -1049,8 +1091,12 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     prof_end(g, s, ev);
     // the fix-up always runs: its blocks also write their reduction slots
     A.red_slot = G.offFA;
-    hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kFixThreads), 0, s, A,
-                       g->tiles_v.split, g->tiles_v.n_split);
+    if (COLS == 1)
+        hipLaunchKernelGGL((k_fixup1<VT, WT, true>), dim3(G.blkFA), dim3(kPassThreads), 0, s, A, g->tiles_v.split,
+                           g->tiles_v.n_split);
+    else
+        hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kFixThreads), 0, s, A,
+                           g->tiles_v.split, g->tiles_v.n_split);
     pb(1);
     B.red_slot = 0;
     if (COLS == 64)
@@ -1060,9 +1106,14 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     else
         hipLaunchKernelGGL((k_gather<COLS, VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
     prof_end(g, s, ev);
-    if (g->tiles_u.n_split > 0)
-        hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
-                           g->tiles_u.split, g->tiles_u.n_split);
+    if (g->tiles_u.n_split > 0) {
+        if (COLS == 1)
+            hipLaunchKernelGGL((k_fixup1<VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
+                               g->tiles_u.split, g->tiles_u.n_split);
+        else
+            hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
+                               g->tiles_u.split, g->tiles_u.n_split);
+    }
 }
 
 template <int COLS, typename VT, typename WT>
@@ -1347,7 +1398,7 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
         if (!io.done) break;
         hipLaunchKernelGGL((k_gather1<VT, WT, false>), dim3(G.blkB), dim3(kPassThreads), 0, s, B);
         if (g->tiles_u.n_split > 0)
-            hipLaunchKernelGGL((k_fixup<1, VT, WT, false>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
+            hipLaunchKernelGGL((k_fixup1<VT, WT, false>), dim3(G.blkFB), dim3(kPassThreads), 0, s, B,
                                g->tiles_u.split, g->tiles_u.n_split);
         rc = sparse_finish(g, w, io, w.scores, s);
         if (rc) return rc;
