@@ -22,8 +22,9 @@ def test_benchmark_configuration_sampled_parity():
     S = out["scores"]
     ids = out["ids"].cpu().numpy()
     g = oracle.Graph.from_edges(el)
-    # exact beta for two sampled sources (truncated series, dropped terms <= 2e-10)
-    pick = [0, 37]
+    # exact beta for eight sampled sources across the block's columns (truncated
+    # series, dropped terms <= 2e-10; one host thread per source)
+    pick = [0, 9, 18, 27, 37, 46, 55, 63]
     print("[gpu] oracle exact rows for sampled sources", flush=True)
     ex = g.exact_beta_many(src[pick], wl.alpha, tail=1e-10, nthreads=len(pick))
     for j, i in enumerate(pick):
