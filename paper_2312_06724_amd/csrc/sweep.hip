@@ -46,9 +46,10 @@ constexpr int kFixThreads = 1024;   // split-row fix-ups: 16 slot groups of 64 c
 constexpr int kMaxPassBlocks = 2048;
 constexpr int kMaxFixBlocks = 1024;
 constexpr int kUpdateBlocks = 2048;
+constexpr int kUpdateBlocks1 = 512;   // one-column blocks: 1/64 of the work, fewer partial sums
 
 struct Geometry {
-    int blkA, blkFA, blkB, blkFB, blkU;
+    int blkA, blkFA, blkB, blkFB, blkU, blkU1;
     int offA, offFA, offU, n_part;   // reduction slots: gather A, fix-up A, update
 };
 
@@ -60,6 +61,7 @@ static Geometry geometry(const Graph* g) {
     G.blkFA = clampi(g->tiles_v.n_split, 1, kMaxFixBlocks);
     G.blkFB = clampi(g->tiles_u.n_split, 1, kMaxFixBlocks);
     G.blkU = kUpdateBlocks;
+    G.blkU1 = kUpdateBlocks1;
     G.offA = 0;
     G.offFA = G.blkA;
     G.offU = G.offFA + G.blkFA;
@@ -770,12 +772,13 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
 }
 
 // Reduction slots [0, off_u) carry only n_p (gather A and its fix-up);
-// [off_u, n_part) carry all reductions (update).
+// [off_u, n_used) carry all reductions (the update's blocks); n_part is the
+// stride of the slot arrays.
 constexpr int kControlWaves = 3;                                    // wavefronts per reduction
 constexpr int kControlThreads = kNumRed * kControlWaves * kWave;
 template <int COLS>
-__global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const double* red, int n_part, int off_u,
-                                                             int32_t* n_active) {
+__global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const double* red, int n_part, int n_used,
+                                                             int off_u, int32_t* n_active) {
     __shared__ double P[kNumRed][kControlWaves];
     __shared__ double R[kNumRed];
     if (*n_active == 0) return;
@@ -787,13 +790,13 @@ __global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const
     constexpr int stride = kControlWaves * kWave;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int i = (k == RED_NP ? 0 : off_u) + sub * kWave + lane;
-    for (; i + 3 * stride < n_part; i += 4 * stride) {
+    for (; i + 3 * stride < n_used; i += 4 * stride) {
         a0 += src[i];
         a1 += src[i + stride];
         a2 += src[i + 2 * stride];
         a3 += src[i + 3 * stride];
     }
-    for (; i < n_part; i += stride) a0 += src[i];
+    for (; i < n_used; i += stride) a0 += src[i];
     double v = (a0 + a1) + (a2 + a3);
 #pragma unroll
     for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
@@ -1121,12 +1124,13 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     launch_front<COLS, VT, WT>(g, b, G, s, true);
     hipEvent_t ev[2] = {nullptr, nullptr};
     prof_begin(g, s, 2, launch_bytes<VT, WT>(g, COLS, 2), ev);
-    hipLaunchKernelGGL((k_update<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.ACC),
+    const int blkU = COLS == 1 ? G.blkU1 : G.blkU;   // its blocks fill reduction slots [offU, offU + blkU)
+    hipLaunchKernelGGL((k_update<COLS, VT>), dim3(blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.ACC),
                        as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part, G.offU,
                        as<VT>(b.SNAP));
     prof_end(g, s, ev);
-    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(kControlThreads), 0, s, b.st, b.red, G.n_part, G.offU,
-                       b.n_active);
+    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(kControlThreads), 0, s, b.st, b.red, G.n_part,
+                       G.offU + blkU, G.offU, b.n_active);
     BHPP_HIP(hipGetLastError());
     return BHPP_OK;
 }
@@ -1390,7 +1394,7 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
     for (int it = 0; it < kMaxSteps; ++it) {
         SparseStep io;
         io.max_work = g->ne / 16;
-        io.red_blocks = G.n_part - G.offU;
+        io.red_blocks = G.blkU1;   // as the one-column update: slots [offU, offU + blkU1)
         io.n_part = G.n_part;
         io.off_u = G.offU;
         rc = sparse_front(g, w, io, s);
@@ -1402,8 +1406,8 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
                                g->tiles_u.split, g->tiles_u.n_split);
         rc = sparse_finish(g, w, io, w.scores, s);
         if (rc) return rc;
-        hipLaunchKernelGGL((k_control<1>), dim3(1), dim3(kControlThreads), 0, s, w.st, w.red, G.n_part, G.offU,
-                           w.n_active);
+        hipLaunchKernelGGL((k_control<1>), dim3(1), dim3(kControlThreads), 0, s, w.st, w.red, G.n_part,
+                           G.offU + G.blkU1, G.offU, w.n_active);
         BHPP_HIP(hipGetLastError());
         BHPP_HIP(hipMemcpyAsync(hs.data(), w.st, sizeof(ColState), hipMemcpyDeviceToHost, s));
         BHPP_HIP(hipStreamSynchronize(s));
