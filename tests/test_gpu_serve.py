@@ -152,3 +152,42 @@ def test_server_stops_using_a_useless_model(setup):
     assert inf["warm_fell_back"] >= 32 and inf["warm_started"] < 300
     S.close()
     M1.close()
+
+
+def test_submit_from_another_thread(setup):
+    """Requests submitted by a second thread while the first one polls (the
+    server's queue takes submits beside a running poll): each request is
+    answered once, with the bits of the plain batched path."""
+    import threading
+    import time
+    s = setup
+    bh, G, src, eps = s["bh"], s["G"], s["src"], s["eps"]
+    k = 10
+    S = bh.Server(G, k=k)
+    done = threading.Event()
+
+    def feeder():
+        rng = np.random.default_rng(8)
+        for i in range(src.size):
+            S.submit(int(src[i]), float(eps[i]), i)
+            if rng.random() < 0.3:
+                time.sleep(0.002)
+        done.set()
+
+    t = threading.Thread(target=feeder)
+    t.start()
+    res, polls = {}, 0
+    while not (done.is_set() and len(res) == src.size):
+        for tag, ids, vals, st in S.poll(stats=True):
+            assert tag not in res
+            res[tag] = (ids, vals, st)
+        polls += 1
+        assert polls < 1000000
+    t.join()
+    assert S.info()["completed"] == src.size
+    b = G.query_batch(src, eps, k=k, scores=False)
+    bi, bv = b["ids"].cpu().numpy(), b["vals"].cpu().numpy()
+    for i in range(src.size):
+        assert np.array_equal(res[i][0], bi[i]), i
+        assert np.array_equal(res[i][1], bv[i]), i
+    S.close()
