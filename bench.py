@@ -38,8 +38,9 @@ def source_digest(path):
 
 
 def stored_traffic(kernel):
-    """HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if the
-    counters were taken on the current kernel source."""
+    """HBM bytes per launch (mean over the dispatches of a bench step and its
+    statistics batch) from rocprofv3 FETCH_SIZE/WRITE_SIZE, if the counters
+    were taken on the current kernel source."""
     p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(p):
         return None
@@ -334,30 +335,49 @@ def main():
         single_qps = args.single / (time.perf_counter() - t1)
         log(f"single-source: {single_qps:.2f} q/s")
 
-    # roofline of the dominant kernel
-    names = ["V-side gather with the push rule (k_gather64, SIDE_A)", "U-side gather (k_gather64)", "U-side update (k_update)",
-             "push selection (k_select)"]
+    # roofline of the dominant kernel. A launch's algorithmic bytes follow the
+    # columns that run in it: the adjacency (index, weight and, for gather A,
+    # 1/ws of the neighbour) and the row offsets once per launch in which a
+    # source still runs, and one 4-byte value per entry and per output row for
+    # each running column. Over the timed steps that is
+    #     fixed x (launches with a running source) + per_column x (column sweeps),
+    # the column sweeps being the sum of the sources' sweeps and the launches
+    # with a running source the slowest source's sweeps, per step (the last
+    # chunk of a step can hold launches that find no running column and return
+    # at once). The select pass does no work in the timed sweeps but the first
+    # of each query (gather A applies the push rule), so it is counted as 0.
+    names = ["V-side gather with the push rule (k_gather64, SIDE_A)", "U-side gather (k_gather64)",
+             "U-side update (k_update)", "push selection (k_select)"]
+    kids = ["gather_a", "gather_b", "update", "select"]
+    steps_q = np.array([s["steps"] for s in stats], dtype=np.float64)
+    live_launches = args.steps * steps_q.max()
+    col_sweeps = args.steps * steps_q.sum()
+    nu1, nv1, E = el.n_u - info["isolated_u"], el.n_v - info["isolated_v"], el.n_e
+    fixed = [12 * E + 8 * nv1, 8 * E + 8 * nu1, 8 * nu1, 0]
+    per_col = [4 * E + 4 * nv1, 4 * E + 4 * nu1, 20 * nu1, 0]
+    # lower bound for comparison: the adjacency read once, each dense row read
+    # or written once per running column
+    comp_fixed = [12 * E + 8 * nv1, 8 * E + 8 * nu1, 8 * nu1, 0]
+    comp_per_col = [4 * (nu1 + nv1), 4 * (nu1 + nv1), 20 * nu1, 0]
+    alg = [fixed[i] * live_launches + per_col[i] * col_sweeps for i in range(4)]
+    comp = [comp_fixed[i] * live_launches + comp_per_col[i] * col_sweeps for i in range(4)]
     dom = int(np.argmax(prof["ms"]))
-    avg_ms = prof["ms"][dom] / max(1, prof["launches"][dom])
-    bytes_per_launch = prof["bytes"][dom] / max(1, prof["launches"][dom])
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kernel_id = ["gather_a", "gather_b", "update", "select"][dom]
-    # lower bound for comparison: adjacency read once, each dense row read or written once
-    nu1, nv1, C = el.n_u - info["isolated_u"], el.n_v - info["isolated_v"], 64
-    # (gather A also streams 1/ws of each entry's neighbour: it applies the push rule itself)
-    compulsory = [12 * el.n_e + 8 * nv1 + 4 * C * (nu1 + nv1), 8 * el.n_e + 8 * nu1 + 4 * C * (nu1 + nv1),
-                  8 * nu1 + 20 * C * nu1, el.n_u * (4 + 8 * C)][dom]
+    sec = prof["ms"][dom] * 1e-3
+    launches = max(1, prof["launches"][dom])
+    avg_ms = prof["ms"][dom] / launches
+    achieved = alg[dom] / sec / 1e9
     roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=stored_traffic(kernel_id),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=stored_traffic(kids[dom]),
                     avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom],
-                    algorithmic_bytes_per_launch=int(bytes_per_launch),
-                    compulsory=dict(bytes_per_launch=int(compulsory),
-                                    achieved=round(compulsory / (avg_ms * 1e-3) / 1e9, 1),
-                                    frac=round(compulsory / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+                    algorithmic_bytes_per_launch=int(alg[dom] / launches),
+                    launches_with_running_sources=int(live_launches), column_sweeps=int(col_sweeps),
+                    compulsory=dict(bytes_per_launch=int(comp[dom] / launches),
+                                    achieved=round(comp[dom] / sec / 1e9, 1),
+                                    frac=round(comp[dom] / sec / 1e9 / HBM_PEAK_GBS, 4)),
                     share_of_step=round(sum(prof["ms"]) / (dt * 1e3), 3),
                     kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
-                                     gbs=round(prof["bytes"][i] / max(1e-9, prof["ms"][i] * 1e-3) / 1e9, 1))
-                             for i, k in enumerate(["gather_a", "gather_b", "update", "select"])})
+                                     gbs=round(alg[i] / max(1e-12, prof["ms"][i] * 1e-3) / 1e9, 1))
+                             for i, k in enumerate(kids)})
 
     copy_gbs = copy_ceiling(torch)
     roofline["copy_gbs"] = round(copy_gbs, 1)
