@@ -113,7 +113,14 @@ def run_large(bh, torch, np):
     steps = np.array([s["steps"] for s in out["stats"]])
     dom = int(np.argmax(prof["ms"]))
     avg = prof["ms"][dom] / max(1, prof["launches"][dom])
-    ach = prof["bytes"][dom] / max(1, prof["launches"][dom]) / (avg * 1e-3) / 1e9
+    # bytes charged as in the main roofline: the adjacency once per launch (the
+    # queue keeps the block full until its last chunk) and the rows once per
+    # column-sweep (the sum of the sources' sweeps)
+    E, nu1, nv1 = info["n_edges"], info["n_u"] - info["isolated_u"], info["n_v"] - info["isolated_v"]
+    fixed = [12 * E + 8 * nv1, 8 * E + 8 * nu1, 8 * nu1, 0][dom]
+    per_col = [4 * E + 4 * nv1, 4 * E + 4 * nu1, 20 * nu1, 0][dom]
+    alg = fixed * prof["launches"][dom] + per_col * float(steps.sum())
+    ach = alg / max(1e-12, prof["ms"][dom] * 1e-3) / 1e9
     res = dict(workload=wl.name, sources=int(src.size), source_sampling="degree-proportional",
                queries_per_s=round(src.size / dt, 3), wall_s=round(dt, 3), launch_config=cfg,
                sweeps_per_query=dict(min=int(steps.min()), median=float(np.median(steps)), max=int(steps.max())),

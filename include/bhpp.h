@@ -227,7 +227,10 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
  * elapsed times are accumulated; bhpp_profile_read synchronises and returns,
  * per kind, the total milliseconds, the number of launches and the
  * algorithmic bytes those launches moved in total (per launch: the adjacency
- * read once plus each dense vector read or written once). enable = 0 stops
+ * read once plus each dense vector read or written once, for every column of
+ * the block whether its source still runs or not: an upper bound when some
+ * columns have finished; the query statistics give the sweeps each source
+ * ran, from which the bytes of the running columns follow). enable = 0 stops
  * recording; enable = 1 also clears the totals. Errors: INVALID_ARG,
  * DEVICE_ERROR.
  */
