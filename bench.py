@@ -1,17 +1,22 @@
 """Benchmark: approximate BHPP queries per second on one MI355X.
 
-Workload (one "step"): 64 query sources drawn uniformly from the non-isolated
-U nodes of a seeded Chung-Lu bipartite graph with |U| = 1M, |V| = 2M, 20M
-edges, degree exponent 2.1, lognormal(0,1) weights (a Last.fm-sized stand-in
-for the paper's datasets); alpha = 0.15, eps = 1e-6; each query returns
-beta'(u, x) for all x in U plus its top-100 (Algorithm 5, then top-k). The 64
-sources run together as 64 columns of one dense residue block, in FP32 with
-FP32 accumulation. Inputs are resident in HBM before timing starts.
+Headline workload (one "step"): 256 query sources run as one batch through
+the queue-fed 64-column residue block, on a seeded Chung-Lu bipartite graph
+with |U| = 5M, |V| = 10M, 100M edges, degree exponent 2.1, lognormal(0,1)
+weights. The sources are a fixed set of 1,024 non-isolated U nodes drawn with
+probability proportional to degree (their frontiers differ by more than
+1000x); step i runs quarter (i mod 4) of the set, so every four steps cover
+all 1,024. alpha = 0.15, eps = 1e-6; each query runs Algorithm 5 and returns
+its top-100 (FP32 values and accumulation). Inputs are resident in HBM before
+timing starts.
 
-Prints ONE JSON line. Extra fields: the same graph queried one source at a
-time ("single_source_qps"), the roofline of the dominant kernel measured with
-HIP events on the query stream, and the FP64 CPU oracle timed on a bounded
-sample of the same queries.
+Prints ONE JSON line. Besides the headline it reports the roofline of the
+dominant kernel (HIP events on the query stream over the timed steps, bytes
+counted in edge visits from the queries' own counters), the FP64 CPU oracle
+timed on a bounded sample of the same queries, the plain single-source GPU
+path on the same graph, and, on the 1M x 2M graph (the learned start's and
+the serving workload's graph): plain batched and single-source queries, the
+eps_b split tuning, the learned warm start and continuous-batching serving.
 """
 from __future__ import annotations
 
@@ -26,6 +31,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+KINDS = ["gather_a", "gather_b", "update", "select"]
+KIND_NAMES = ["V-side gather with the push rule (k_gather64, SIDE_A)", "U-side gather (k_gather64)",
+              "U-side update (k_update)", "push selection (k_select)"]
 
 
 def log(*a):
@@ -37,16 +45,32 @@ def source_digest(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def stored_traffic(kernel):
-    """HBM bytes per launch (mean over the dispatches of a bench step and its
-    statistics batch) from rocprofv3 FETCH_SIZE/WRITE_SIZE, if the counters
-    were taken on the current kernel source."""
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    threads = int(omp) if omp and omp.isdigit() and int(omp) > 0 else aff
+    return dict(cpu_model=model, nproc=os.cpu_count(), affinity=aff, threads=min(threads, aff))
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch (mean over the profiled dispatches) from rocprofv3
+    FETCH_SIZE/WRITE_SIZE, if the counters were taken on the current kernel
+    source for this workload."""
     p = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     cur = source_digest(os.path.join(ROOT, "paper_2312_06724_amd", "csrc", "sweep.hip"))
-    ent = d.get(kernel)
+    ent = d.get(workload, {}).get(kernel)
     if not ent or ent.get("sweep_hip_sha") != cur:
         return None
     return ent.get("bytes_per_launch")
@@ -71,72 +95,156 @@ def copy_ceiling(torch):
     return 2.0 * (1 << 30) / (best * 1e-3) / 1e9
 
 
-def cpu_baseline(el, sources, wl, n_threads):
+def roofline(prof, stats, info, workload):
+    """Roofline of the dominant sweep kernel over the timed steps.
+
+    Unit of work: the edge visit, the increment of the push cost n_p in
+    Algorithms 3 and 4, counted by the queries themselves over every sweep
+    (visits_u: edges of the pushed U nodes, the entries the V-side gather
+    reads with a non-zero value; visits_v: edges of the V nodes with a
+    non-zero residue, read by the U-side gather). Algorithmic bytes:
+      structure: 8 B per adjacency entry (index + weight) and 8 B per row
+                 (offsets) for every sweep in which a query ran (the block
+                 shares one adjacency read among its columns);
+      visits:    4 B per visit (the neighbour's value);
+      outputs:   4 B per output row and running column (column-sweeps).
+    The update reads degree and 1/ws once per sweep (8 B per node) and per
+    node and running column reads y, ACC, G and writes y, ACC (20 B).
+    Each gather read counts as a memory read (no reuse); the per-entry 1/ws
+    the V-side gather streams beside the adjacency is overhead, not counted.
+    """
+    import numpy as np
+    E = float(info["n_edges"])
+    U1 = float(info["n_u"] - info["isolated_u"])
+    V1 = float(info["n_v"] - info["isolated_v"])
+    L = float(prof["live_sweeps"])
+    CS = float(sum(s["steps"] for s in stats))
+    VU = float(sum(s["visits_u"] for s in stats))
+    VV = float(sum(s["visits_v"] for s in stats))
+    alg = [L * (8 * E + 8 * V1) + 4 * VU + 4 * V1 * CS,
+           L * (8 * E + 8 * U1) + 4 * VV + 4 * U1 * CS,
+           L * 8 * U1 + 20 * U1 * CS,
+           0.0]
+    comp = [L * (8 * E + 8 * V1) + 4 * (U1 + V1) * CS,
+            L * (8 * E + 8 * U1) + 4 * (U1 + V1) * CS,
+            L * 8 * U1 + 20 * U1 * CS,
+            0.0]
+    dom = int(np.argmax(prof["ms"]))
+    sec = prof["ms"][dom] * 1e-3
+    launches = max(1, prof["launches"][dom])
+    avg_ms = prof["ms"][dom] / launches
+    achieved = alg[dom] / sec / 1e9
+    paper_units = sum(s["np_ss"] + s["np_pi"] + 2 * E * s["t"] for s in stats)
+    traffic = stored_traffic(workload, KINDS[dom])
+    out = dict(bound="hbm", kernel=KIND_NAMES[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+               avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom], live_sweeps=int(L),
+               algorithmic_bytes_per_launch=int(alg[dom] / launches),
+               counts=dict(column_sweeps=int(CS), visits_u=VU, visits_v=VV, edge_visits=VU + VV,
+                           paper_work_units=paper_units),
+               compulsory=dict(bytes_per_launch=int(comp[dom] / launches), achieved=round(comp[dom] / sec / 1e9, 1),
+                               frac=round(comp[dom] / sec / 1e9 / HBM_PEAK_GBS, 4)),
+               kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
+                                launches=prof["launches"][i],
+                                gbs=round(alg[i] / max(1e-12, prof["ms"][i] * 1e-3) / 1e9, 1))
+                        for i, k in enumerate(KINDS)})
+    if traffic:
+        out["traffic_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+    return out
+
+
+def cpu_baseline(el, sources, wl, threads):
+    """The FP64 oracle (Algorithms 1-5, one query per thread) on the first
+    `threads` sources of the set."""
     import oracle
+    t0 = time.perf_counter()
     g = oracle.Graph.from_edges(el)
     lam = g.lambda_(wl.alpha)
     eps_b = g.eps_b(wl.eps)
-    sample = sources[:n_threads]
+    t_pre = time.perf_counter() - t0
+    sample = sources[:threads]
     t0 = time.perf_counter()
-    _, st = g.approx_bhpp_many(sample, wl.alpha, wl.eps, eps_b, lam, nthreads=n_threads, keep=False)
+    _, st = g.approx_bhpp_many(sample, wl.alpha, wl.eps, eps_b, lam, nthreads=threads, keep=False)
     dt = time.perf_counter() - t0
-    per_thread = -(-len(sample) // n_threads)
-    return dict(value=len(sample) / dt, unit="queries/s", cores=n_threads, kind="oracle",
-                ms_per_query_per_thread=round(dt * 1e3 / per_thread, 1),
-                sample=f"{len(sample)} of the {len(sources)} sources, one per thread, FP64 Approx-BHPP "
-                       f"(Algorithms 1-5), lambda and eps_b precomputed; {dt:.1f} s wall")
+    return dict(value=len(sample) / dt, unit="queries/s", cores=threads, kind="oracle",
+                ms_per_query_per_thread=round(dt * 1e3, 1),
+                sample=f"{len(sample)} of the {len(sources)} sources of {wl.name}, one query per thread, FP64 "
+                       f"Approx-BHPP (Algorithms 1-5); graph build, lambda and eps_b ({t_pre:.1f} s) not timed; "
+                       f"{dt:.1f} s wall")
 
 
-def run_large(bh, torch, np):
-    """1024 degree-proportional sources on the 5M x 10M, 100M-edge graph, one
-    timed pass through the queue-fed 64-column block (top-100 each)."""
+def run_headline(bh, torch, np, args, hinfo):
     import synth
     wl = synth.LARGE
     t0 = time.perf_counter()
     el = wl.graph()
     src = wl.sources(el)
-    log(f"large graph {wl.name} generated in {time.perf_counter() - t0:.1f}s")
+    log(f"graph {wl.name}: {el.n_e} edges generated in {time.perf_counter() - t0:.1f}s")
     G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
-    del el
     info = G.info()
     cfg = G.autotune()
-    log(f"large: built in {info['build_ms']:.0f} ms, lambda={info['lambda']:.1f}, autotuned {cfg}")
-    G.query_batch(src[:64], wl.eps, k=wl.k, scores=False, stats=False)   # warm-up (graph capture)
-    torch.cuda.synchronize()
+    log(f"built on GPU in {info['build_ms']:.0f} ms; lambda={info['lambda']:.1f} "
+        f"eps_b/eps={info['eps_b_ratio']:.4f}; autotuned {cfg}")
+    per = args.sources_per_step
+    parts = max(1, src.size // per)
+
+    def step(i):
+        part = src[(i % parts) * per:(i % parts + 1) * per]
+        return G.query_batch(part, wl.eps, k=wl.k, exclude_self=True, scores=False, stats=True)
+
     G.profile(True)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    G.profile(True)            # clears the totals
+    stats = []
     t0 = time.perf_counter()
-    out = G.query_batch(src, wl.eps, k=wl.k, scores=False, stats=True)
+    for i in range(args.steps):
+        stats += step(i)["stats"]
+        log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = G.profile_read()
     G.profile(False)
-    steps = np.array([s["steps"] for s in out["stats"]])
-    dom = int(np.argmax(prof["ms"]))
-    avg = prof["ms"][dom] / max(1, prof["launches"][dom])
-    # bytes charged as in the main roofline: the adjacency once per launch (the
-    # queue keeps the block full until its last chunk) and the rows once per
-    # column-sweep (the sum of the sources' sweeps)
-    E, nu1, nv1 = info["n_edges"], info["n_u"] - info["isolated_u"], info["n_v"] - info["isolated_v"]
-    fixed = [12 * E + 8 * nv1, 8 * E + 8 * nu1, 8 * nu1, 0][dom]
-    per_col = [4 * E + 4 * nv1, 4 * E + 4 * nu1, 20 * nu1, 0][dom]
-    alg = fixed * prof["launches"][dom] + per_col * float(steps.sum())
-    ach = alg / max(1e-12, prof["ms"][dom] * 1e-3) / 1e9
-    res = dict(workload=wl.name, sources=int(src.size), source_sampling="degree-proportional",
-               queries_per_s=round(src.size / dt, 3), wall_s=round(dt, 3), launch_config=cfg,
-               sweeps_per_query=dict(min=int(steps.min()), median=float(np.median(steps)), max=int(steps.max())),
-               roofline=dict(kernel=["gather_a", "gather_b", "update", "select"][dom], avg_launch_ms=round(avg, 4),
-                             achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4)))
-    log(f"large: {res['queries_per_s']} q/s")
+    qps = per * args.steps / dt
+    roof = roofline(prof, stats, info, wl.name)
+    roof["copy_gbs"] = round(copy_ceiling(torch), 1)
+    if roof.get("traffic_gbs"):
+        roof["traffic_frac_of_copy"] = round(roof["traffic_gbs"] / roof["copy_gbs"], 4)
+    roof["share_of_step"] = round(sum(prof["ms"]) / (dt * 1e3), 3)
+    log(f"headline {qps:.2f} q/s; dominant kernel {roof['kernel']} {roof['avg_launch_ms']} ms, "
+        f"{roof['achieved']} GB/s (frac {roof['frac']}); copy {roof['copy_gbs']} GB/s")
+    steps_q = np.array([s["steps"] for s in stats])
+    single = None
+    if args.single > 0:
+        G.query(int(src[0]), wl.eps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for u in src[:args.single]:
+            G.query(int(u), wl.eps, with_stats=False)
+        torch.cuda.synchronize()
+        single = args.single / (time.perf_counter() - t1)
+        log(f"single-source on {wl.name}: {single:.2f} q/s")
     G.close()
-    return res
+    head = dict(value=qps, dt=dt, steps_q=steps_q, wl=wl, info=info, cfg=cfg, roof=roof, single=single,
+                parts=parts)
+    cpu = None
+    if not args.no_cpu_baseline:
+        n = args.cpu_threads or hinfo["threads"]
+        log(f"CPU oracle baseline on {n} threads ...")
+        cpu = cpu_baseline(el, src, wl, n)
+        cpu.update(cpu_model=hinfo["cpu_model"], nproc=hinfo["nproc"], affinity=hinfo["affinity"])
+        log(f"CPU oracle: {cpu['value']:.4f} q/s")
+    head["cpu"] = cpu
+    return head
 
 
 def run_learned(bh, torch, np, G, el, wl, src, n_train, steps, reps):
-    """Learned warm start on the same graph: training data from the plain GPU
-    path (top-64 of beta' plus 64 random entries per source, for n_train
-    uniform sources disjoint from the benchmark's), GPU training, then the
-    benchmark's 64 sources batched and warm-started, beside the no-network
-    ablation (the structural self term alone)."""
+    """Learned warm start: training data from the plain GPU path (top-64 of
+    beta' plus 64 random entries per source, for n_train uniform sources
+    disjoint from the evaluation sources), GPU training, then the evaluation
+    sources batched and warm-started, beside the no-network ablation (the
+    structural self term alone)."""
     import synth
     live = np.nonzero(el.degrees_u() > 0)[0]
     rng = np.random.default_rng(77)
@@ -201,15 +309,23 @@ def run_learned(bh, torch, np, G, el, wl, src, n_train, steps, reps):
 def run_serving(bh, G, el, wl, rates, duration, np, model=None):
     """Continuous batching on the resident graph: Poisson arrivals at each rate
     for `duration` seconds, degree-proportional sources, eps uniform on
-    {1e-5, 1e-6, 1e-7}, top-k per request. Latency = arrival to result."""
+    {1e-5, 1e-6, 1e-7}, top-k per request. Latency = arrival to result. When
+    a rate overloads the device, results stop being collected `duration` + 6 s
+    after the start; the latencies of the requests still unfinished then are
+    at least the time they have waited, which the *_all percentiles use (lower
+    bounds)."""
     import synth
-    S = bh.Server(G, k=wl.k, model=model)
-    # warm-up: capture the sweep chunk once
-    warm = synth.sample_sources(el, 4, "degree", 90)
-    for i, u in enumerate(warm):
-        S.submit(int(u), 1e-5, -1 - i)
-    while S.info()["completed"] < warm.size:
-        S.poll()
+
+    def new_server():
+        S = bh.Server(G, k=wl.k, model=model)
+        warm = synth.sample_sources(el, 4, "degree", 90)   # capture the sweep chunk once
+        for i, u in enumerate(warm):
+            S.submit(int(u), 1e-5, -1 - i)
+        while S.info()["completed"] < warm.size:
+            S.poll()
+        return S
+
+    S = new_server()
     out = []
     for j, rate in enumerate(rates):
         rng = np.random.default_rng(1000 + j)
@@ -218,10 +334,11 @@ def run_serving(bh, G, el, wl, rates, duration, np, model=None):
         src = synth.sample_sources(el, n, "degree", 2000 + j)
         eps = rng.choice([1e-5, 1e-6, 1e-7], size=n)
         lat = np.full(n, np.nan)
-        sweeps0 = S.info()["sweeps"]
+        inf0 = S.info()
         t0 = time.perf_counter()
         i = done = 0
-        cap = duration + 6.0                      # stop admitting results after this (overload)
+        cap = duration + 6.0
+        t = 0.0
         while done < n:
             now = time.perf_counter() - t0
             while i < n and arr[i] <= now:
@@ -241,23 +358,101 @@ def run_serving(bh, G, el, wl, rates, duration, np, model=None):
         wall = time.perf_counter() - t0
         ok = lat[~np.isnan(lat)]
         inf = S.info()
-        out.append(dict(offered_qps=rate, requests=n, completed=int(ok.size), wall_s=round(wall, 2),
-                        served_qps=round(ok.size / wall, 2),
-                        p50_ms=round(float(np.percentile(ok, 50)) * 1e3, 1) if ok.size else None,
-                        p99_ms=round(float(np.percentile(ok, 99)) * 1e3, 1) if ok.size else None,
-                        backlog=int(n - ok.size), sweeps=int(inf["sweeps"] - sweeps0)))
-        log(f"serve {rate} q/s: {out[-1]}")
+        rec = dict(offered_qps=rate, requests=n, completed=int(ok.size), completion=round(ok.size / n, 4),
+                   wall_s=round(wall, 2), served_qps=round(ok.size / wall, 2),
+                   p50_ms=round(float(np.percentile(ok, 50)) * 1e3, 1) if ok.size else None,
+                   p99_ms=round(float(np.percentile(ok, 99)) * 1e3, 1) if ok.size else None,
+                   backlog=int(n - ok.size), sweeps=int(inf["sweeps"] - inf0["sweeps"]),
+                   warm_started=int(inf["warm_started"] - inf0["warm_started"]),
+                   warm_fell_back=int(inf["warm_fell_back"] - inf0["warm_fell_back"]))
+        if ok.size < n:
+            # unfinished requests: latency at least (cutoff - arrival); never-submitted ones count from arrival too
+            lb = lat.copy()
+            miss = np.isnan(lb)
+            lb[miss] = np.maximum(0.0, t - arr[miss])
+            rec["p50_ms_all"] = round(float(np.percentile(lb, 50)) * 1e3, 1)
+            rec["p99_ms_all"] = round(float(np.percentile(lb, 99)) * 1e3, 1)
+            rec["all_percentiles"] = "lower bounds: unfinished requests counted at the time waited"
+        out.append(rec)
+        log(f"serve {rate} q/s: {rec}")
         if ok.size < n:   # overloaded: drop what is left before the next rate
             S.close()
-            S = bh.Server(G, k=wl.k, model=model)
-    inf = S.info()
-    res = dict(width=S.width, k=wl.k, resident_bytes=int(inf["resident_bytes"]),
-               learned_warm_start=model is not None, warm_started=int(inf["warm_started"]),
-               warm_fell_back=int(inf["warm_fell_back"]),
-               eps_mix=[1e-5, 1e-6, 1e-7], source_sampling="degree-proportional", duration_s=duration,
-               rates=out)
+            S = new_server()
+    res = dict(width=S.width, k=wl.k, resident_bytes=int(S.info()["resident_bytes"]),
+               learned_warm_start=model is not None, eps_mix=[1e-5, 1e-6, 1e-7],
+               source_sampling="degree-proportional", duration_s=duration, rates=out)
     S.close()
     return res
+
+
+def run_medium(bh, torch, np, args):
+    """The 1M x 2M graph: plain batched (64 uniform sources per batch) and
+    single-source queries, eps_b tuning, learned warm start, serving."""
+    import synth
+    wl = synth.MEDIUM
+    t0 = time.perf_counter()
+    el = wl.graph()
+    src = wl.sources(el)
+    log(f"graph {wl.name}: {el.n_e} edges generated in {time.perf_counter() - t0:.1f}s")
+    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
+    info = G.info()
+    out = dict(workload=wl.name, sources=int(src.size), source_sampling="uniform non-isolated",
+               lambda_=round(info["lambda"], 3))
+
+    def batch():
+        return G.query_batch(src, wl.eps, k=wl.k, exclude_self=True, scores=True, stats=True)
+
+    batch()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps = max(1, args.medium_reps)
+    for _ in range(reps):
+        o = batch()
+    torch.cuda.synchronize()
+    out["batched_qps"] = round(src.size * reps / (time.perf_counter() - t1), 3)
+    out["mean_sweeps_per_query"] = float(np.mean([x["steps"] for x in o["stats"]]))
+    log(f"{wl.name}: plain batched {out['batched_qps']} q/s")
+    if args.single > 0:
+        G.query(int(src[0]), wl.eps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for u in src[:args.single]:
+            G.query(int(u), wl.eps, with_stats=False)
+        torch.cuda.synchronize()
+        out["single_source_qps"] = round(args.single / (time.perf_counter() - t1), 3)
+        log(f"{wl.name}: single-source {out['single_source_qps']} q/s")
+    if not args.no_tune_eps_b:
+        paper = info["eps_b_ratio"]
+        sample = np.setdiff1d(synth.sample_sources(el, 128, "uniform", 9090), src)[:64]
+        ratios = [0.01, 0.03, 0.1, 0.2, paper]
+        best, ms, gm, swc = G.tune_eps_b(sample, wl.eps, ratios, curve=True)
+        batch()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            o = batch()
+        torch.cuda.synchronize()
+        tq = src.size * reps / (time.perf_counter() - t1)
+        sw = float(np.mean([x["steps"] for x in o["stats"]]))
+        G.set_eps_b_ratio(0.0)
+        out["tuned_eps_b"] = dict(candidates=[round(r, 4) for r in ratios], sample_ms=[round(m, 1) for m in ms],
+                                  gamma_curve=[round(float(x), 5) for x in gm],
+                                  sample_sweeps=[round(float(x), 1) for x in swc], best_ratio=round(best, 4),
+                                  paper_ratio=round(paper, 4), queries_per_s=round(tq, 3), mean_sweeps_per_query=sw)
+        log(f"tuned eps_b ratio {best:.3f}: {tq:.1f} q/s, {sw:.1f} sweeps per query")
+    model = None
+    if not args.no_learned:
+        model, out["learned"] = run_learned(bh, torch, np, G, el, wl, src, args.train_sources, args.train_steps, 2)
+        if out.get("single_source_qps"):
+            out["learned"]["gain_over_single_source"] = round(
+                out["learned"]["batched_learned"]["queries_per_s"] / out["single_source_qps"], 2)
+    rates = [float(x) for x in args.serve.split(",") if x.strip()]
+    if rates:
+        out["serving"] = run_serving(bh, G, el, wl, rates, args.serve_seconds, np, model)
+    if model is not None:
+        model.close()
+    G.close()
+    return out
 
 
 def main():
@@ -265,18 +460,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--single", type=int, default=8, help="sources timed one at a time")
+    ap.add_argument("--sources-per-step", type=int, default=256,
+                    help="sources per step, a slice of the 1024-source set (1024 = the whole set)")
+    ap.add_argument("--single", type=int, default=4, help="sources timed one at a time on each graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--large", action="store_true",
-                    help="also run the 100M-edge workload: 1024 degree-proportional sources in one queue-fed block")
+    ap.add_argument("--no-medium", action="store_true", help="skip the 1M x 2M graph's measurements")
+    ap.add_argument("--medium-reps", type=int, default=5)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start")
     ap.add_argument("--no-tune-eps-b", action="store_true", help="skip the eps_b split tuning")
     ap.add_argument("--train-sources", type=int, default=2048)
     ap.add_argument("--train-steps", type=int, default=2000)
-    ap.add_argument("--serve", default="150,250,2000",
+    ap.add_argument("--serve", default="150,300,2000,20000",
                     help="Poisson arrival rates (q/s) for the serving run; empty to skip")
-    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device-to-device copy first (known-size kernel for scaling HBM counters)")
     args = ap.parse_args()
@@ -289,17 +486,8 @@ def main():
     import torch
 
     import paper_2312_06724_amd as bh
-    import synth
 
-    wl = synth.MEDIUM
-    t0 = time.perf_counter()
-    el = wl.graph()
-    src = wl.sources(el)
-    log(f"graph {wl.name}: {el.n_e} edges generated in {time.perf_counter() - t0:.1f}s")
-    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
-    info = G.info()
-    log(f"built on GPU in {info['build_ms']:.1f} ms; lambda={info['lambda']:.3f} eps_b/eps={info['eps_b_ratio']:.4f}")
-
+    hinfo = host_info()
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
@@ -309,156 +497,33 @@ def main():
         log("copy probe: 1 GiB read + 1 GiB written")
         del a, b
 
-    def step():
-        return G.query_batch(src, wl.eps, k=wl.k, exclude_self=True, scores=True, stats=False)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    G.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-        log(f"step {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = G.profile_read()
-    G.profile(False)
-    qps = wl.n_sources * args.steps / dt
-
-    stats = G.query_batch(src, wl.eps, k=0, scores=False, stats=True)["stats"]
-    sweeps = float(np.mean([s["steps"] for s in stats]))
-
-    # plain single-source path on the same graph
-    single_qps = None
-    if args.single > 0:
-        G.query(int(src[0]), wl.eps)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for u in src[:args.single]:
-            G.query(int(u), wl.eps, with_stats=False)
-        torch.cuda.synchronize()
-        single_qps = args.single / (time.perf_counter() - t1)
-        log(f"single-source: {single_qps:.2f} q/s")
-
-    # roofline of the dominant kernel. A launch's algorithmic bytes follow the
-    # columns that run in it: the adjacency (index, weight and, for gather A,
-    # 1/ws of the neighbour) and the row offsets once per launch in which a
-    # source still runs, and one 4-byte value per entry and per output row for
-    # each running column. Over the timed steps that is
-    #     fixed x (launches with a running source) + per_column x (column sweeps),
-    # the column sweeps being the sum of the sources' sweeps and the launches
-    # with a running source the slowest source's sweeps, per step (the last
-    # chunk of a step can hold launches that find no running column and return
-    # at once). The select pass does no work in the timed sweeps but the first
-    # of each query (gather A applies the push rule), so it is counted as 0.
-    names = ["V-side gather with the push rule (k_gather64, SIDE_A)", "U-side gather (k_gather64)",
-             "U-side update (k_update)", "push selection (k_select)"]
-    kids = ["gather_a", "gather_b", "update", "select"]
-    steps_q = np.array([s["steps"] for s in stats], dtype=np.float64)
-    live_launches = args.steps * steps_q.max()
-    col_sweeps = args.steps * steps_q.sum()
-    nu1, nv1, E = el.n_u - info["isolated_u"], el.n_v - info["isolated_v"], el.n_e
-    fixed = [12 * E + 8 * nv1, 8 * E + 8 * nu1, 8 * nu1, 0]
-    per_col = [4 * E + 4 * nv1, 4 * E + 4 * nu1, 20 * nu1, 0]
-    # lower bound for comparison: the adjacency read once, each dense row read
-    # or written once per running column
-    comp_fixed = [12 * E + 8 * nv1, 8 * E + 8 * nu1, 8 * nu1, 0]
-    comp_per_col = [4 * (nu1 + nv1), 4 * (nu1 + nv1), 20 * nu1, 0]
-    alg = [fixed[i] * live_launches + per_col[i] * col_sweeps for i in range(4)]
-    comp = [comp_fixed[i] * live_launches + comp_per_col[i] * col_sweeps for i in range(4)]
-    dom = int(np.argmax(prof["ms"]))
-    sec = prof["ms"][dom] * 1e-3
-    launches = max(1, prof["launches"][dom])
-    avg_ms = prof["ms"][dom] / launches
-    achieved = alg[dom] / sec / 1e9
-    roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=stored_traffic(kids[dom]),
-                    avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom],
-                    algorithmic_bytes_per_launch=int(alg[dom] / launches),
-                    launches_with_running_sources=int(live_launches), column_sweeps=int(col_sweeps),
-                    compulsory=dict(bytes_per_launch=int(comp[dom] / launches),
-                                    achieved=round(comp[dom] / sec / 1e9, 1),
-                                    frac=round(comp[dom] / sec / 1e9 / HBM_PEAK_GBS, 4)),
-                    share_of_step=round(sum(prof["ms"]) / (dt * 1e3), 3),
-                    kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
-                                     gbs=round(alg[i] / max(1e-12, prof["ms"][i] * 1e-3) / 1e9, 1))
-                             for i, k in enumerate(kids)})
-
-    copy_gbs = copy_ceiling(torch)
-    roofline["copy_gbs"] = round(copy_gbs, 1)
-    if roofline["traffic"]:
-        tgbs = roofline["traffic"] / (avg_ms * 1e-3) / 1e9
-        roofline["traffic_gbs"] = round(tgbs, 1)
-        roofline["traffic_frac_of_copy"] = round(tgbs / copy_gbs, 4)
-    log(f"device copy: {copy_gbs:.0f} GB/s read+write")
-
-    # the eps split (Theorem 3 holds for any eps_b): tuned on 64 other sources,
-    # then the benchmark's sources timed with it; the headline keeps Eq. (epsilon-b)
-    tuned = None
-    if not args.no_tune_eps_b:
-        paper = info["eps_b_ratio"]
-        sample = np.setdiff1d(synth.sample_sources(el, 128, "uniform", 9090), src)[:64]
-        ratios = [0.01, 0.03, 0.1, 0.2, paper]
-        best, ms, gm, swc = G.tune_eps_b(sample, wl.eps, ratios, curve=True)
-        step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        tq = wl.n_sources * args.steps / (time.perf_counter() - t1)
-        sw = float(np.mean([x["steps"] for x in G.query_batch(src, wl.eps, k=0, scores=False)["stats"]]))
-        G.set_eps_b_ratio(0.0)
-        tuned = dict(candidates=[round(r, 4) for r in ratios], sample_ms=[round(m, 1) for m in ms],
-                     gamma_curve=[round(float(x), 5) for x in gm], sample_sweeps=[round(float(x), 1) for x in swc],
-                     best_ratio=round(best, 4), paper_ratio=round(paper, 4), queries_per_s=round(tq, 3),
-                     mean_sweeps_per_query=sw)
-        log(f"tuned eps_b ratio {best:.3f}: {tq:.1f} q/s, {sw:.1f} sweeps per query")
-
-    model, learned = None, None
-    if not args.no_learned:
-        model, learned = run_learned(bh, torch, np, G, el, wl, src, args.train_sources, args.train_steps, 2)
-
-    rates = [float(x) for x in args.serve.split(",") if x.strip()]
-    serving = run_serving(bh, G, el, wl, rates, args.serve_seconds, np, model) if rates else None
-    if model is not None:
-        model.close()
-
-    large = run_large(bh, torch, np) if args.large else None
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        n = args.cpu_threads or min(16, os.cpu_count() or 1)
-        log(f"CPU oracle baseline on {n} threads ...")
-        cpu = cpu_baseline(el, src, wl, n)
-
+    head = run_headline(bh, torch, np, args, hinfo)
+    medium = None if args.no_medium else run_medium(bh, torch, np, args)
+    wl, info = head["wl"], head["info"]
     out = {
         "metric": "BHPP queries/s at eps=1e-6 (plain vs batched+learned); HBM GB/s; p99 ms",
-        "value": round(qps, 3),
+        "value": round(head["value"], 3),
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "ms_per_step": round(head["dt"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "n_u": el.n_u, "n_v": el.n_v, "n_edges": el.n_e,
-                   "sources_per_step": wl.n_sources, "source_sampling": "uniform non-isolated",
-                   "alpha": wl.alpha, "eps": wl.eps, "k": wl.k, "lambda": round(info["lambda"], 3)},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "single_source_qps": round(single_qps, 3) if single_qps else None,
-        "tuned_eps_b": tuned,
-        "learned": learned,
-        "serving": serving,
-        "large": large,
-        "mean_sweeps_per_query": sweeps,
-        "sweeps_per_step": prof["launches"][0] / args.steps,
+        "config": {"workload": wl.name, "n_u": info["n_u"], "n_v": info["n_v"], "n_edges": info["n_edges"],
+                   "sources_per_step": args.sources_per_step, "source_set": int(wl.n_sources),
+                   "source_sampling": "degree-proportional", "alpha": wl.alpha, "eps": wl.eps, "k": wl.k,
+                   "lambda": round(info["lambda"], 3), "launch_config": head["cfg"]},
+        "roofline": head["roof"],
+        "cpu_baseline": head["cpu"],
+        "single_source_qps": round(head["single"], 3) if head["single"] else None,
+        "sweeps_per_query": dict(min=int(head["steps_q"].min()), mean=float(head["steps_q"].mean()),
+                                 max=int(head["steps_q"].max())),
+        "host": hinfo,
+        "medium": medium,
     }
     print(json.dumps(out), flush=True)
 

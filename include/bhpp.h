@@ -102,6 +102,13 @@ typedef struct {
     double gamma;           /* Eq. (gamma) */
     double sum_r_ss;        /* sum of the residue r when SS-Push returned */
     double sum_rf;          /* sum of the forward residue entering PowerIteration */
+    /* Edge visits of every sweep of the query (all phases), split by side:
+       visits_u sums d(x) over the U nodes pushed (the entries the V-side half
+       reads with a non-zero value), visits_v sums d(v) over the V nodes with a
+       non-zero residue. Their sum over the phases is the work measure n_p of
+       Algorithms 3-4 extended to the sequential and PowerIteration sweeps. */
+    double visits_u;
+    double visits_v;
 } bhpp_query_stats;
 
 /* Graph summary and preprocessing results (Lemma 4, Eq. (epsilon-b)). */
@@ -236,6 +243,13 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
  */
 bhpp_status bhpp_profile_enable(bhpp_graph* g, int32_t enable);
 bhpp_status bhpp_profile_read(bhpp_graph* g, double ms[4], int64_t launches[4], double bytes[4]);
+/* Number of sweeps run by query batches while profiling was on in which at
+   least one query of the block was still running (host, *live_out). A batch
+   runs its sweeps in chunks, so its last chunk can hold sweeps whose kernels
+   find nothing to do and return at once; those are not counted. The
+   launches of each kernel kind that did work equal this count. Errors:
+   INVALID_ARG. */
+bhpp_status bhpp_profile_sweeps(bhpp_graph* g, int64_t* live_out);
 
 /*
  * Launch settings of the sweep kernels: config[0] entries per work tile (rows
@@ -349,6 +363,24 @@ bhpp_status bhpp_query_batch_warm(bhpp_graph* g, bhpp_model* m, int32_t n_src, c
 bhpp_status bhpp_query_hpp(bhpp_graph* g, int32_t n_src, const int32_t* sources, const double* eps, double alpha,
                            double eps_all, int32_t direction, void* scores_out, bhpp_query_stats* stats,
                            void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * PISP, the baseline the paper compares Approx-BHPP with (Sec. 3.3,
+ * Baselines and Challenges; Sec. 5.4, Fig. 3): for each source u, the
+ * forward part pi(u, .) by PowerIteration (Algorithm 1) from e_u with t rounds,
+ * t = log_{1/(1-alpha)}(2/eps) - 1 rounded up (the smallest t with
+ * (1-alpha)^(t+1) <= eps/2), plus the backward part pi(., u) by SelectivePush
+ * (Algorithm 2) with eps_b = eps/2 run until no U residue exceeds eps_b;
+ * beta' = pi_f + pi_b, within [beta - eps, beta]. Arguments, outputs, batching
+ * and errors as bhpp_query_batch. In the statistics ss_sel_iters counts the
+ * SelectivePush iterations, np_ss their push cost and t the PowerIteration
+ * rounds; the other phase counters stay 0.
+ * ---------------------------------------------------------------------- */
+bhpp_status bhpp_query_batch_pisp(bhpp_graph* g, int32_t n_src, const int32_t* sources,
+                                  const double* eps, double alpha, double eps_all,
+                                  void* scores_out, int32_t k, int32_t exclude_self,
+                                  int32_t* topk_ids, void* topk_vals,
+                                  bhpp_query_stats* stats, void* hip_stream);
 
 /* Warm start from caller-given starts instead of a model: starts is device
    [n_src][n_u] of the graph dtype, row i = estimates of pi(sources[i], x) for

@@ -65,6 +65,13 @@ class WarmInfo(ctypes.Structure):
         return dict(res_l1=self.res_l1, res_max=self.res_max, fell_back=self.fell_back)
 
 
+class PispStats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_int32), ("sp_iters", ctypes.c_int32), ("np", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 TRACE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                             ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double))
 
@@ -95,6 +102,7 @@ def _load():
         L.orc_hpp_forward.argtypes = [P, I32, D, D, P, P]
         L.orc_hpp_backward.argtypes = [P, I32, D, D, P, P]
         L.orc_hpp_forward_many.argtypes = [P, I32, P, D, D, P, I32]
+        L.orc_hpp_forward_block.argtypes = [P, I32, P, D, D, P, I32, I32]
         L.orc_eps_b.restype = D
         L.orc_eps_b.argtypes = [I32, I32, I64, D]
         L.orc_default_tau.restype = I32
@@ -106,6 +114,8 @@ def _load():
         L.orc_approx_bhpp_warm.argtypes = [P, I32, D, D, D, D, P, P, ctypes.POINTER(Stats),
                                            ctypes.POINTER(WarmInfo)]
         L.orc_approx_bhpp_warm_many.argtypes = [P, I32, P, D, D, D, D, P, P, P, P, I32]
+        L.orc_pisp.argtypes = [P, I32, D, D, P, P, P, P]
+        L.orc_pisp_many.argtypes = [P, I32, P, D, D, P, P, I32]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_t.restype = I32
         L.orc_t.argtypes = [D, D, D]
@@ -194,13 +204,31 @@ class Graph:
                                             int(nthreads)))
         return out
 
-    def exact_beta_many(self, sources, alpha, tail=1e-10, nthreads=0):
+    def hpp_forward_block(self, sources, alpha, tail=1e-10, nthreads=0, progress=0):
+        """The series of ``hpp_forward`` for several sources in one pass over
+        the adjacency per term (rows split over threads); every row equals
+        ``hpp_forward`` of its source bit for bit. ``progress`` > 0 prints a
+        line to stderr every that many terms."""
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        out = np.empty((src.size, self.n_u))
+        _check(_load().orc_hpp_forward_block(self._h, src.size, _ptr(src), alpha, tail, _ptr(out),
+                                             int(nthreads), int(progress)))
+        return out
+
+    def exact_beta_many(self, sources, alpha, tail=1e-10, nthreads=0, block=64, progress=0):
         """beta(u, x) = pi(u, x) + pi(x, u), the second term from Lemma 3:
         pi(x, u) = pi(u, x) ws(u) / ws(x). Each entry is short of the exact
         value by at most 2 * tail: the dropped terms of pi(u, x) are at most
         tail * max_l P^l(u, x) and P^l(u, x) <= min(1, ws(x)/ws(u)) by the same
-        reversibility. Isolated x score 0 (x != u)."""
-        pf = self.hpp_forward_many(sources, alpha, tail, nthreads)
+        reversibility. Isolated x score 0 (x != u). ``block`` > 0 runs the
+        series for up to that many sources per adjacency pass
+        (``hpp_forward_block``, the same bits); 0 runs one source per thread."""
+        src = np.asarray(sources)
+        if block > 0:
+            pf = np.concatenate([self.hpp_forward_block(src[i:i + block], alpha, tail, nthreads, progress)
+                                 for i in range(0, src.size, block)]) if src.size else np.empty((0, self.n_u))
+        else:
+            pf = self.hpp_forward_many(sources, alpha, tail, nthreads)
         ws = self.ws_u
         out = np.empty_like(pf)
         for i, u in enumerate(np.asarray(sources)):
@@ -250,6 +278,24 @@ class Graph:
         _check(_load().orc_approx_bhpp_many(self._h, src.size, _ptr(src), alpha, eps, eps_b, lam,
                                             _ptr(beta), ctypes.cast(st, ctypes.c_void_p),
                                             int(nthreads)))
+        return beta, [st[i].as_dict() for i in range(src.size)]
+
+    # ---- PISP (Sec. 3.3, Baselines and Challenges) ----
+    def pisp(self, u, alpha, eps):
+        """The PISP baseline: PowerIteration for pi(u, .) with t rounds
+        ((1-alpha)^(t+1) <= eps/2) plus SelectivePush for pi(., u) with
+        eps_b = eps/2. Returns (beta', pi_f, pi_b, stats dict)."""
+        beta, pif, pib = np.empty(self.n_u), np.empty(self.n_u), np.empty(self.n_u)
+        st = PispStats()
+        _check(_load().orc_pisp(self._h, int(u), alpha, eps, _ptr(beta), _ptr(pif), _ptr(pib), ctypes.byref(st)))
+        return beta, pif, pib, st.as_dict()
+
+    def pisp_many(self, sources, alpha, eps, nthreads=0, keep=True):
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        beta = np.empty((src.size, self.n_u)) if keep else None
+        st = (PispStats * max(1, src.size))()
+        _check(_load().orc_pisp_many(self._h, src.size, _ptr(src), alpha, eps, _ptr(beta),
+                                     ctypes.cast(st, ctypes.c_void_p), int(nthreads)))
         return beta, [st[i].as_dict() for i in range(src.size)]
 
     def warm_residue(self, u, alpha, y):

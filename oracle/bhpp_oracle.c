@@ -20,10 +20,14 @@
  *   lambda                                                            Lemma 4, Eq. (lambda)
  *   eps_b                                                             Eq. (epsilon-b) (Sec. 4.3)
  * Everything is FP64 and single-threaded per query; loops run over node ids in
- * increasing order. The only parallelism is across independent queries.
+ * increasing order. The only parallelism is across independent queries, and
+ * in the block form of the exact series (orc_hpp_forward_block), whose output
+ * rows are split over threads while each value keeps the single-source order
+ * of operations.
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -292,6 +296,85 @@ int orc_hpp_forward_many(const orc_graph* g, int32_t n, const int32_t* src, doub
     }
     (void)nthreads;
     return rc;
+}
+
+int orc_max_threads(void);
+
+/*
+ * Eq. (hpp), forward direction, for n sources at once: out[i][x] = pi(src[i], x),
+ * the same truncated series as orc_hpp_forward. The n row vectors are kept
+ * node-major (p[x][i]) so one pass over the adjacency serves all of them; for
+ * every source the products and sums are the ones orc_hpp_forward makes, in
+ * the same order, so each row of out equals its single-source value bit for
+ * bit. Rows of the two products are split over threads (each output row is
+ * written by one thread; nothing is shared). Isolated sources give e_u alpha.
+ */
+int orc_hpp_forward_block(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double tail,
+                          double* out, int32_t nthreads, int32_t progress) {
+    if (n <= 0) return ORC_OK;
+    for (int32_t i = 0; i < n; ++i)
+        if (src[i] < 0 || src[i] >= g->nu) return ORC_ERANGE;
+    const int32_t L = series_terms(alpha, tail);
+    const size_t nu = (size_t)g->nu, nv = (size_t)g->nv, m = (size_t)n;
+    double* p = (double*)calloc(nu * m, sizeof(double));
+    double* nx = (double*)malloc(sizeof(double) * nu * m);
+    double* tv = (double*)malloc(sizeof(double) * nv * m);
+    double* acc = (double*)malloc(sizeof(double) * nu * m);
+    if (!p || !nx || !tv || !acc) {
+        free(p); free(nx); free(tv); free(acc);
+        return ORC_ENOMEM;
+    }
+    for (int32_t i = 0; i < n; ++i) p[(size_t)src[i] * m + i] = 1.0;
+    double c = alpha;
+    for (size_t j = 0; j < nu * m; ++j) acc[j] = c * p[j];
+    const int nt = nthreads > 0 ? nthreads : orc_max_threads();
+    for (int32_t l = 1; l <= L; ++l) {
+        /* (p U)(v) = sum_x p(x) w(x,v)/ws(x), per source, as row_times_P */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4096) num_threads(nt)
+#endif
+        for (int32_t y = 0; y < g->nv; ++y) {
+            double* s = tv + (size_t)y * m;
+            for (size_t i = 0; i < m; ++i) s[i] = 0.0;
+            for (int64_t q = g->rp_v[y]; q < g->rp_v[y + 1]; ++q) {
+                const int32_t x = g->ci_v[q];
+                const double* px = p + (size_t)x * m;
+                for (size_t i = 0; i < m; ++i) s[i] += px[i] * g->w_v[q] / g->ws_u[x];
+            }
+        }
+        /* ((pU) V)(x) = sum_v (pU)(v) w(v,x)/ws(v) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4096) num_threads(nt)
+#endif
+        for (int32_t x = 0; x < g->nu; ++x) {
+            double* s = nx + (size_t)x * m;
+            for (size_t i = 0; i < m; ++i) s[i] = 0.0;
+            for (int64_t q = g->rp_u[x]; q < g->rp_u[x + 1]; ++q) {
+                const int32_t y = g->ci_u[q];
+                const double* ty = tv + (size_t)y * m;
+                for (size_t i = 0; i < m; ++i) s[i] += ty[i] * g->w_u[q] / g->ws_v[y];
+            }
+        }
+        /* a source without edges keeps p = e_u and stops adding (orc_hpp_forward breaks) */
+        for (int32_t i = 0; i < n; ++i)
+            if (g->ws_u[src[i]] == 0.0)
+                for (size_t x = 0; x < nu; ++x) nx[x * m + i] = 0.0;
+        double* t = p; p = nx; nx = t;
+        c *= (1.0 - alpha);
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nt)
+#endif
+        for (int64_t x = 0; x < (int64_t)nu; ++x)
+            for (size_t i = 0; i < m; ++i) acc[(size_t)x * m + i] += c * p[(size_t)x * m + i];
+        if (progress > 0 && (l % progress == 0 || l == L)) {
+            fprintf(stderr, "[oracle] exact series of %d sources: term %d of %d\n", (int)n, (int)l, (int)L);
+            fflush(stderr);
+        }
+    }
+    for (size_t i = 0; i < m; ++i)
+        for (size_t x = 0; x < nu; ++x) out[i * nu + x] = acc[x * m + i];
+    free(p); free(nx); free(tv); free(acc);
+    return ORC_OK;
 }
 
 /* ---------------------------------------------------------------------------
@@ -758,6 +841,81 @@ int orc_approx_bhpp_many(const orc_graph* g, int32_t n, const int32_t* src, doub
         int r = orc_approx_bhpp(g, src[i], alpha, eps, eps_b, lambda,
                                 beta ? beta + (size_t)i * (size_t)g->nu : NULL, NULL, NULL,
                                 st ? st + i : NULL, NULL, NULL);
+        if (r != ORC_OK) rc = r;
+    }
+    (void)nthreads;
+    return rc;
+}
+
+/*
+ * PISP, the baseline of Sec. 3.3 (Baselines and Challenges) against which the
+ * paper measures Approx-BHPP (Sec. 5.4, Fig. 3). Two independent parts:
+ *   forward:  pi_f = PowerIteration(e_u, t) (Algorithm 1), t the paper's
+ *             log_{1/(1-alpha)}(2/eps) - 1 rounded up (as Eq. (t) with a
+ *             unit residue and eps_f = eps/2), so that the dropped mass
+ *             (1-alpha)^(t+1) is at most eps/2;
+ *   backward: pi_b = SelectivePush (Algorithm 2) from r = e_u with
+ *             eps_b = eps/2: push iterations with threshold eps_b until no U
+ *             residue exceeds eps_b (its loop's only exit), so that
+ *             0 <= pi(x, u) - pi_b(x) <= eps/2;
+ * beta' = pi_f + pi_b. Outputs as orc_approx_bhpp (NULL to skip).
+ */
+typedef struct {
+    int32_t t;          /* PowerIteration rounds */
+    int32_t sp_iters;   /* SelectivePush iterations */
+    double np;          /* edges touched by SelectivePush */
+} orc_pisp_stats;
+
+int orc_pisp(const orc_graph* g, int32_t u, double alpha, double eps, double* beta, double* pi_f_out,
+             double* pi_b_out, orc_pisp_stats* st) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    if (!(alpha > 0.0 && alpha < 1.0) || !(eps > 0.0)) return ORC_EINVAL;
+    if (g->ws_u[u] == 0.0) return ORC_EISOLATED;
+    orc_pisp_stats s;
+    memset(&s, 0, sizeof(s));
+    /* forward part */
+    s.t = orc_t(1.0, 0.5 * eps, alpha);
+    double* e = (double*)calloc((size_t)g->nu, sizeof(double));
+    double* pif = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    if (!e || !pif) { free(e); free(pif); return ORC_ENOMEM; }
+    e[u] = 1.0;
+    int rc = orc_power_iteration(g, e, alpha, s.t, pif);
+    free(e);
+    if (rc) { free(pif); return rc; }
+    /* backward part */
+    orc_work w;
+    if (work_alloc(&w, g)) { free(pif); return ORC_ENOMEM; }
+    const double eps_b = 0.5 * eps;
+    for (int32_t x = 0; x < g->nu; ++x) w.thr[x] = eps_b;
+    w.r[u] = 1.0;
+    for (;;) {
+        if (s.sp_iters >= ORC_MAX_ITERS) { work_free(&w); free(pif); return ORC_ENOCONV; }
+        s.np += push_iteration(g, &w, alpha);
+        s.sp_iters += 1;
+        double rmax = 0.0;
+        for (int32_t x = 0; x < g->nu; ++x) rmax = w.r[x] > rmax ? w.r[x] : rmax;
+        if (!(rmax > eps_b)) break;
+    }
+    for (int32_t x = 0; x < g->nu; ++x) {
+        if (beta) beta[x] = pif[x] + w.pib[x];
+        if (pi_f_out) pi_f_out[x] = pif[x];
+        if (pi_b_out) pi_b_out[x] = w.pib[x];
+    }
+    if (st) *st = s;
+    work_free(&w);
+    free(pif);
+    return ORC_OK;
+}
+
+int orc_pisp_many(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double eps, double* beta,
+                  orc_pisp_stats* st, int32_t nthreads) {
+    int rc = ORC_OK;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
+    for (int32_t i = 0; i < n; ++i) {
+        int r = orc_pisp(g, src[i], alpha, eps, beta ? beta + (size_t)i * (size_t)g->nu : NULL, NULL, NULL,
+                         st ? st + i : NULL);
         if (r != ORC_OK) rc = r;
     }
     (void)nthreads;

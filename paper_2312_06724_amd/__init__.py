@@ -29,12 +29,12 @@ BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER, BUILD_DENSE_ONLY, BUILD_FIXED_WIDTH = 1, 
 
 # names exported by include/bhpp.h
 EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
-            "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_autotune",
+            "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_profile_sweeps", "bhpp_autotune",
             "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_server_create", "bhpp_server_submit",
             "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_model_create", "bhpp_model_params",
             "bhpp_model_features", "bhpp_model_loss_grad", "bhpp_model_train", "bhpp_model_embed", "bhpp_model_free",
             "bhpp_query_batch_warm", "bhpp_query_batch_start", "bhpp_gemm_bf16", "bhpp_set_eps_b_ratio",
-            "bhpp_tune_eps_b", "bhpp_query_hpp", "bhpp_free_graph", "bhpp_status_string"]
+            "bhpp_tune_eps_b", "bhpp_query_hpp", "bhpp_query_batch_pisp", "bhpp_free_graph", "bhpp_status_string"]
 MODEL_PARAMS = 230656
 MODEL_FEATURES = 64
 
@@ -56,7 +56,8 @@ class QueryStats(ctypes.Structure):
                 ("ss_switched", ctypes.c_int32), ("pi_returned", ctypes.c_int32),
                 ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("np_ss", ctypes.c_double), ("np_pi", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("sum_r_ss", ctypes.c_double), ("sum_rf", ctypes.c_double)]
+                ("sum_r_ss", ctypes.c_double), ("sum_rf", ctypes.c_double),
+                ("visits_u", ctypes.c_double), ("visits_v", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -115,6 +116,8 @@ def load_library():
     L.bhpp_query.argtypes = [P, I32, D, D, P, ctypes.POINTER(QueryStats), P]
     L.bhpp_query_batch.restype = I32
     L.bhpp_query_batch.argtypes = [P, I32, P, P, D, D, P, I32, I32, P, P, P, P]
+    L.bhpp_query_batch_pisp.restype = I32
+    L.bhpp_query_batch_pisp.argtypes = [P, I32, P, P, D, D, P, I32, I32, P, P, P, P]
     L.bhpp_topk.restype = I32
     L.bhpp_topk.argtypes = [P, I32, I32, I32, P, I32, P, P, P]
     L.bhpp_graph_info.restype = I32
@@ -125,6 +128,8 @@ def load_library():
     L.bhpp_profile_enable.argtypes = [P, I32]
     L.bhpp_profile_read.restype = I32
     L.bhpp_profile_read.argtypes = [P, P, P, P]
+    L.bhpp_profile_sweeps.restype = I32
+    L.bhpp_profile_sweeps.argtypes = [P, P]
     L.bhpp_autotune.restype = I32
     L.bhpp_autotune.argtypes = [P, P, P]
     L.bhpp_set_launch_config.restype = I32
@@ -274,9 +279,10 @@ class Graph:
         return (out, st.as_dict()) if with_stats else out
 
     def query_batch(self, sources, eps, alpha=None, k=0, exclude_self=True, scores=True, stats=True, model=None,
-                    starts=None):
+                    starts=None, method="approx"):
         """Many queries (bhpp_query_batch; bhpp_query_batch_warm with a Model;
-        bhpp_query_batch_start with starts = [n, n_u] estimates of pi(u, x)).
+        bhpp_query_batch_start with starts = [n, n_u] estimates of pi(u, x);
+        bhpp_query_batch_pisp with method="pisp", the paper's PISP baseline).
         ``eps`` is a float or one per source. Returns dict(scores=[n, n_u]
         tensor or None, ids, vals, stats, warm)."""
         torch = _torch()
@@ -300,6 +306,9 @@ class Graph:
                                                        ctypes.cast(ws, ctypes.c_void_p), _stream())
             _check(rc, "bhpp_query_batch_start")
             warm = [ws[i].as_dict() for i in range(n)]
+        elif method == "pisp":
+            rc = load_library().bhpp_query_batch_pisp(self._h, *common, _stream())
+            _check(rc, "bhpp_query_batch_pisp")
         elif model is None:
             rc = load_library().bhpp_query_batch(self._h, *common, _stream())
             _check(rc, "bhpp_query_batch")
@@ -391,7 +400,9 @@ class Graph:
         n = (ctypes.c_int64 * 4)()
         b = (ctypes.c_double * 4)()
         _check(load_library().bhpp_profile_read(self._h, ms, n, b), "bhpp_profile_read")
-        return dict(ms=list(ms), launches=list(n), bytes=list(b))
+        live = ctypes.c_int64()
+        _check(load_library().bhpp_profile_sweeps(self._h, ctypes.byref(live)), "bhpp_profile_sweeps")
+        return dict(ms=list(ms), launches=list(n), bytes=list(b), live_sweeps=int(live.value))
 
 
 class Server:

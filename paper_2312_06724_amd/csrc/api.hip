@@ -161,6 +161,13 @@ bhpp_status bhpp_query_batch_start(bhpp_graph* h, const void* starts, int32_t n_
                             topk_ids, topk_vals, stats, warm_out, hip_stream);
 }
 
+bhpp_status bhpp_query_batch_pisp(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps,
+                                  double alpha, double eps_all, void* scores_out, int32_t k, int32_t exclude_self,
+                                  int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, void* hip_stream) {
+    return query_batch_impl(h, nullptr, nullptr, 3, n_src, sources, eps, alpha, eps_all, scores_out, k, exclude_self,
+                            topk_ids, topk_vals, stats, nullptr, hip_stream);
+}
+
 bhpp_status bhpp_query_hpp(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps, double alpha,
                            double eps_all, int32_t direction, void* scores_out, bhpp_query_stats* stats,
                            void* hip_stream) {
@@ -232,8 +239,17 @@ bhpp_status bhpp_profile_enable(bhpp_graph* h, int32_t enable) {
             g->prof_n[k] = 0;
             g->prof_bytes[k] = 0.0;
         }
+        g->prof_live = 0;
     }
     g->prof_on = enable != 0;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_profile_sweeps(bhpp_graph* h, int64_t* live_out) {
+    if (!h || !h->g || !live_out) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    std::lock_guard<std::mutex> lock(g->mu);
+    *live_out = g->prof_live;
     return BHPP_OK;
 }
 

@@ -60,7 +60,8 @@ enum Mode : int32_t {
 
 // Reductions taken over U after every sweep, per source.
 enum Red : int32_t {
-    RED_NP = 0,      // push cost n_p of the sweep (edges of pushed U and active V nodes)
+    RED_NP = 0,      // push cost n_p of the sweep (edges of pushed U and active V nodes): the V-side
+                     // part in the gather slots [0, off_u), the U-side part in the update slots
     RED_CNT_SS = 1,  // #{x : r(x) > eps_b}
     RED_SUM_R = 2,   // sum_x y(x)/ws(x)   (times ws(u) = sum of r)
     RED_CNT_PI = 3,  // #{x : y(x) > eps_f/lambda}
@@ -86,6 +87,7 @@ struct ColState {
     // statistics
     int32_t ss_sel_iters, ss_seq_iters, pi_sel_iters, t, ss_switched, pi_returned;
     double np_ss, np_pi, sum_r_ss, sum_rf;
+    double visits_u, visits_v;   // edge visits of all sweeps: pushed U nodes' edges, active V nodes' edges
     // scheduling: a column reused for a new query keeps the old query's Y and
     // ACC until its first sweep, which reads them as y = e_src and ACC = 0
     int32_t fresh;
@@ -96,7 +98,9 @@ struct ColState {
     int32_t warm;
     int32_t snap;
     int32_t fell_back;   // a warm start was no better than the cold start: ran cold
-    int32_t target;      // 0: beta (Algorithm 5); 1: pi(u, .) (PI-Push alone); 2: pi(., u) (SS-Push alone)
+    int32_t target;      // 0: beta (Algorithm 5); 1: pi(u, .) (PI-Push alone); 2: pi(., u) (SS-Push alone);
+                         // 3: beta by PISP (SelectivePush, then PowerIteration from e_u)
+    int32_t reset_y;     // the next sweep reads y = e_src (PISP's forward part) but keeps ACC
     double res_l1;       // sum_x |r_f(x)| of the warm start
     double res_max;      // max_x |r(x)|
 };
@@ -196,6 +200,7 @@ struct Graph {
     double prof_ms[4] = {0, 0, 0, 0};
     int64_t prof_n[4] = {0, 0, 0, 0};
     double prof_bytes[4] = {0, 0, 0, 0};
+    int64_t prof_live = 0;                // sweeps in which some query still ran
     std::vector<hipEvent_t> prof_ev;      // pairs, recorded on the query stream
     std::vector<int32_t> prof_kind;
     std::vector<double> prof_b;

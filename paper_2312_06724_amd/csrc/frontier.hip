@@ -108,9 +108,10 @@ __global__ void k_clear_v(const int32_t* TV, const unsigned long long* cnt, VT* 
 }
 
 // y += (1-alpha) G over all of U, then the reductions k_update makes after a
-// dense sweep, into the update slots [off_u, off_u + gridDim.x); n_p (edges of
-// F plus edges of the touched V nodes, from the counters) goes to slot off_u,
-// the other n_p slots (those of the gathers in a dense sweep) are zeroed.
+// dense sweep, into the update slots [off_u, off_u + gridDim.x); n_p goes
+// where a dense sweep puts it: the edges of F (U side) to slot off_u, the
+// edges of the touched V nodes (V side) to slot 0 of the gather slots
+// [0, off_u), whose other slots are zeroed.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_sparse_finish(VT* Y, const VT* G, const VT* inv_ws, const int32_t* deg,
                                                        int32_t nu, const ColState* st, double* red, int n_part,
@@ -138,14 +139,14 @@ __global__ __launch_bounds__(256) void k_sparse_finish(VT* Y, const VT* G, const
     }
     if (threadIdx.x == 0) {
         const int slot = off_u + blockIdx.x;
-        red[(size_t)RED_NP * n_part + slot] = blockIdx.x == 0 ? (double)(cnt[2] + cnt[3]) : 0.0;
+        red[(size_t)RED_NP * n_part + slot] = blockIdx.x == 0 ? (double)cnt[2] : 0.0;
         red[(size_t)RED_CNT_SS * n_part + slot] = sh[0][0];
         red[(size_t)RED_SUM_R * n_part + slot] = sh[1][0];
         red[(size_t)RED_CNT_PI * n_part + slot] = sh[2][0];
         red[(size_t)RED_SUM_Y * n_part + slot] = sh[3][0];
     }
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < off_u; i += gridDim.x * blockDim.x)
-        red[(size_t)RED_NP * n_part + i] = 0.0;
+        red[(size_t)RED_NP * n_part + i] = i == 0 ? (double)cnt[3] : 0.0;
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 4096); }

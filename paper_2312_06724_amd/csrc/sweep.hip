@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     PushTest<VT> test(RULE_NONE, VT(0), VT(0));
     if (SIDE_A && p.Yf != nullptr) {
         const ColState& cs = p.stf[col];
-        fused = __ballot(on && cs.fresh != 0) == 0ull;
+        fused = __ballot(on && (cs.fresh != 0 || cs.reset_y != 0)) == 0ull;
         test = PushTest<VT>(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
     }
     const VT* X = fused ? p.Yf : p.X;
@@ -575,13 +575,13 @@ __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ 
     if (only_fresh) {
         // gather A applies the rule itself unless a live column starts a query
         // (each wavefront covers all COLS == 64 columns, so this is uniform)
-        const bool fr = col < live_cols(n_active, COLS) && st[col].fresh != 0;
+        const bool fr = col < live_cols(n_active, COLS) && (st[col].fresh != 0 || st[col].reset_y != 0);
         if (__ballot(fr) == 0ull) return;
     }
     if (col >= live_cols(n_active, COLS)) return;   // no barrier below
     const ColState& cs = st[col];
     const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
-    const bool fresh = cs.fresh != 0;
+    const bool fresh = cs.fresh != 0 || cs.reset_y != 0;   // y = e_src this sweep
     const int32_t src_row = cs.src_row;
     const size_t n = (size_t)n_rows * COLS;
     const size_t stride = (size_t)gridDim.x * kPassThreads;
@@ -626,6 +626,7 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
     const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
     const VT one_minus_alpha = VT(1) - alpha;
     const bool fresh = cs.fresh != 0;
+    const bool y_src = fresh || cs.reset_y != 0;   // y = e_src this sweep (ACC kept unless fresh)
     const int32_t src_row = cs.src_row;
     double r[kNumRed] = {0, 0, 0, 0, 0};
     const size_t n = col < live_cols(n_active, COLS) ? (size_t)n_rows * COLS : 0;   // unused columns: no work
@@ -641,7 +642,7 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
             const int32_t x = in ? (int32_t)(i / COLS) : 0;
             d[k] = in ? deg[x] : 0;
             iw[k] = in ? inv_ws[x] : VT(0);
-            y[k] = in ? (fresh ? (x == src_row ? VT(1) : VT(0)) : Y[i]) : VT(0);   // new query: y = e_src
+            y[k] = in ? (y_src ? (x == src_row ? VT(1) : VT(0)) : Y[i]) : VT(0);   // new query: y = e_src
             a[k] = (in && !fresh) ? ACC[i] : VT(0);                                  // and ACC = 0
             g[k] = in ? G[i] : VT(0);
         }
@@ -710,12 +711,34 @@ __device__ void enter_pi(ColState& s, const double* R, double sum_r) {
     }
 }
 
-__device__ void control_update(ColState& s, const double* R, int32_t* n_active) {
+// R[RED_NP] is the sweep's whole push cost, np_v its V-side part.
+// PISP: SelectivePush has ended; the next sweep converts ACC to pi_b (the
+// backward part, convert 3), restarts the residue from y = e_u and begins the
+// t rounds of PowerIteration (Algorithm 1) that add pi_f into ACC.
+__device__ void enter_pisp_power(ColState& s, double sum_r) {
+    s.np_ss = s.np;
+    s.sum_r_ss = sum_r;
+    s.reset_y = 1;
+    if (s.t == 0) {
+        set_rules(s, MODE_FINAL, RULE_NONE, RULE_ALL, 3);
+    } else {
+        s.t_rem = s.t;
+        set_rules(s, MODE_POWER, RULE_ALL, RULE_ALL, 3);
+    }
+}
+
+__device__ void control_update(ColState& s, const double* R, double np_v, int32_t* n_active) {
     s.fresh = 0;   // after its first sweep a column holds its own query's Y and ACC
     s.snap = 0;    // the snapshot (if any) was taken by the sweep that just ran
+    s.reset_y = 0; // likewise the residue restart of PISP
     const int m = s.mode;
     if (m == MODE_DONE) return;
     s.steps += 1;
+    // edge visits of this sweep; the U-side count is the update's push set,
+    // which the V-side half read unless its rule was NONE (the last sweep of
+    // PowerIteration only adds alpha y)
+    if (s.ruleA != RULE_NONE) s.visits_u += R[RED_NP] - np_v;
+    s.visits_v += np_v;
     const double sum_r = R[RED_SUM_R] * s.ws_src;     // sum_x |r(x)|
     const double sum_y = R[RED_SUM_Y];                // sum_x |r_f(x)|
     const bool ss_stop = (R[RED_CNT_SS] == 0.0) || (sum_r <= s.eps_b);
@@ -723,7 +746,11 @@ __device__ void control_update(ColState& s, const double* R, int32_t* n_active) 
         case MODE_SS_SEL:
             s.np += R[RED_NP];
             s.ss_sel_iters += 1;
-            if (ss_stop) {
+            if (s.target == 3) {
+                // SelectivePush (Algorithm 2): its loop ends when no U residue
+                // exceeds eps_b; there is no budget test
+                if (R[RED_CNT_SS] == 0.0) enter_pisp_power(s, sum_r);
+            } else if (ss_stop) {
                 enter_pi(s, R, sum_r);
             } else if (s.np >= s.two_e * (log(1.0 / sum_r) / s.ln_inv)) {      // Eq. (bwd-np)
                 s.ss_switched = 1;
@@ -780,16 +807,24 @@ template <int COLS>
 __global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const double* red, int n_part, int n_used,
                                                              int off_u, int32_t* n_active) {
     __shared__ double P[kNumRed][kControlWaves];
+    __shared__ double PV[kControlWaves];
     __shared__ double R[kNumRed];
     if (*n_active == 0) return;
     const int col = blockIdx.x;
     if (col >= live_cols(n_active, COLS)) return;   // whole block
+    // n_active[4] counts the sweeps in which some query of the block ran
+    if (col == 0 && threadIdx.x == 0) n_active[4] += 1;
     const int wv = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
     const int k = wv / kControlWaves, sub = wv % kControlWaves;
     const double* src = red + ((size_t)k * COLS + col) * n_part;
     constexpr int stride = kControlWaves * kWave;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     int i = (k == RED_NP ? 0 : off_u) + sub * kWave + lane;
+    // n_p: the gather slots [0, off_u) (V side) first, kept apart
+    double av = 0.0;
+    if (k == RED_NP) {
+        for (; i < off_u; i += stride) av += src[i];
+    }
     for (; i + 3 * stride < n_used; i += 4 * stride) {
         a0 += src[i];
         a1 += src[i + stride];
@@ -799,16 +834,28 @@ __global__ __launch_bounds__(kControlThreads) void k_control(ColState* st, const
     for (; i < n_used; i += stride) a0 += src[i];
     double v = (a0 + a1) + (a2 + a3);
 #pragma unroll
-    for (int m = kWave / 2; m > 0; m >>= 1) v += __shfl_xor(v, m);
-    if (lane == 0) P[k][sub] = v;
+    for (int m = kWave / 2; m > 0; m >>= 1) {
+        v += __shfl_xor(v, m);
+        av += __shfl_xor(av, m);
+    }
+    if (lane == 0) {
+        P[k][sub] = v;
+        if (k == RED_NP) PV[sub] = av;
+    }
     __syncthreads();
     if ((int)threadIdx.x < kNumRed) {
         double t = 0.0;
         for (int j = 0; j < kControlWaves; ++j) t += P[threadIdx.x][j];
+        if (threadIdx.x == RED_NP) {
+            double tv = 0.0;
+            for (int j = 0; j < kControlWaves; ++j) tv += PV[j];
+            PV[0] = tv;   // read below, after the barrier
+            t += tv;
+        }
         R[threadIdx.x] = t;
     }
     __syncthreads();
-    if (threadIdx.x == 0) control_update(st[col], R, n_active);
+    if (threadIdx.x == 0) control_update(st[col], R, PV[0], n_active);
 }
 
 // ---------------------------------------------------------------------------
@@ -1195,8 +1242,9 @@ static void init_state(ColState& c, double alpha, double ws_src, double eps, dou
     c.ws_src = ws_src;
     c.eps = eps;
     c.target = target;
-    // Algorithm 5's split of eps; one direction alone takes the whole eps
-    c.eps_b = target == 1 ? 0.0 : target == 2 ? eps : eps * eps_b_ratio;
+    // Algorithm 5's split of eps; one direction alone takes the whole eps;
+    // PISP halves it (Sec. 3.3)
+    c.eps_b = target == 1 ? 0.0 : target == 2 ? eps : target == 3 ? 0.5 * eps : eps * eps_b_ratio;
     c.eps_f = eps - c.eps_b;
     c.k_ss = ws_src > 0 ? c.eps_b / ws_src : 0.0;
     c.k_pi = c.eps_f / lambda;
@@ -1209,6 +1257,14 @@ static void init_state(ColState& c, double alpha, double ws_src, double eps, dou
         c.mode = MODE_PI_SEL;
         c.ruleA = c.ruleB = RULE_PI;
         c.gamma = 1.0;
+    } else if (target == 3) {
+        // PISP: SelectivePush first; PowerIteration's rounds t are the
+        // smallest with (1-alpha)^(t+1) <= eps/2, i.e. log_{1/(1-alpha)}(2/eps) - 1
+        // rounded up (Sec. 3.3)
+        c.mode = MODE_SS_SEL;
+        c.ruleA = c.ruleB = RULE_SS;
+        const double tr = ceil(log(1.0 / c.eps_f) / c.ln_inv - 1.0);
+        c.t = tr > 0.0 ? (int)tr : 0;
     } else {
         c.mode = MODE_SS_SEL;                // Algorithm 3 starts with selective pushes
         c.ruleA = c.ruleB = RULE_SS;
@@ -1237,6 +1293,8 @@ static void fill_stats(const ColState& cs, bhpp_query_stats& q) {
     q.gamma = cs.gamma;
     q.sum_r_ss = cs.sum_r_ss;
     q.sum_rf = cs.sum_rf;
+    q.visits_u = cs.visits_u;
+    q.visits_v = cs.visits_v;
 }
 
 static int log2i(int x) {
@@ -1462,6 +1520,7 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
     };
     bhpp_status rc = upload();
     if (rc) return rc;
+    if (g->prof_on) BHPP_HIP(hipMemsetAsync(w.n_active + 4, 0, sizeof(int32_t), s));   // live sweeps
     if (COLS == 1 && n == 1 && target != 1 && !warm.any() && g->sparse_steps && !g->prof_on) {
         rc = sparse_phase<VT, WT>(g, w, hs, s);
         if (rc) return rc;
@@ -1590,6 +1649,12 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
         }
     }
     if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    if (rc == BHPP_OK && g->prof_on) {
+        int32_t live_sweeps = 0;
+        if (hipMemcpy(&live_sweeps, w.n_active + 4, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = BHPP_DEVICE_ERROR;
+        g->prof_live += live_sweeps;
+    }
     hipEventDestroy(evs[0]);
     hipEventDestroy(evs[1]);
     return rc;

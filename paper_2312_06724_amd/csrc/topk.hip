@@ -216,6 +216,26 @@ __global__ __launch_bounds__(1024) void k_topk_sort(const VT* scores, int32_t n,
     }
 }
 
+// The passes over n_rows rows with the scratch st[n_rows], hist[n_rows][256]
+// and cand[n_rows][k] given by the caller; k_topk_init clears what must
+// start at zero (no memset, so the passes can be captured in a graph).
+template <typename VT>
+static void topk_passes(const VT* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
+                        int32_t* ids_out, VT* vals_out, TopkRow* st, uint32_t* hist, Cand* cand, hipStream_t s) {
+    const int digits = KeyOf<VT>::kDigits;
+    const dim3 grid((n + kTopkChunk - 1) / kTopkChunk, n_rows);
+    hipLaunchKernelGGL(k_topk_init, dim3(n_rows), dim3(256), 0, s, st, n_rows, k, hist);
+    for (int d = 0; d < digits; ++d) {
+        hipLaunchKernelGGL(k_topk_hist<VT>, grid, dim3(kTopkThreads), 0, s, scores, n, exclude, st, d, hist);
+        hipLaunchKernelGGL(k_topk_select, dim3(n_rows), dim3(256), 0, s, st, d, hist, digits - 1);
+    }
+    hipLaunchKernelGGL(k_topk_collect<VT>, grid, dim3(kTopkThreads), 0, s, scores, n, exclude, st, k, cand);
+    const int kp2 = next_pow2(k);
+    const int threads = kp2 < 1024 ? (kp2 < 64 ? 64 : kp2) : 1024;
+    hipLaunchKernelGGL(k_topk_sort<VT>, dim3(n_rows), dim3(threads), sizeof(Cand) * kp2, s, scores, n, cand, st, k,
+                       kp2, ids_out, vals_out);
+}
+
 template <typename VT>
 static bhpp_status topk_impl(const VT* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
                              int32_t* ids_out, VT* vals_out, hipStream_t s) {
@@ -230,18 +250,7 @@ static bhpp_status topk_impl(const VT* scores, int32_t n_rows, int32_t n, int32_
         (void)hipGetLastError();
         return BHPP_OUT_OF_MEMORY;
     }
-    const int digits = KeyOf<VT>::kDigits;
-    const dim3 grid((n + kTopkChunk - 1) / kTopkChunk, n_rows);
-    hipLaunchKernelGGL(k_topk_init, dim3(n_rows), dim3(256), 0, s, st, n_rows, k, hist);
-    for (int d = 0; d < digits; ++d) {
-        hipLaunchKernelGGL(k_topk_hist<VT>, grid, dim3(kTopkThreads), 0, s, scores, n, exclude, st, d, hist);
-        hipLaunchKernelGGL(k_topk_select, dim3(n_rows), dim3(256), 0, s, st, d, hist, digits - 1);
-    }
-    hipLaunchKernelGGL(k_topk_collect<VT>, grid, dim3(kTopkThreads), 0, s, scores, n, exclude, st, k, cand);
-    const int kp2 = next_pow2(k);
-    const int threads = kp2 < 1024 ? (kp2 < 64 ? 64 : kp2) : 1024;
-    hipLaunchKernelGGL(k_topk_sort<VT>, dim3(n_rows), dim3(threads), sizeof(Cand) * kp2, s, scores, n, cand, st, k,
-                       kp2, ids_out, vals_out);
+    topk_passes<VT>(scores, n_rows, n, k, exclude, ids_out, vals_out, st, hist, cand, s);
     hipError_t e = hipGetLastError();
     hipFreeAsync(st, s);
     hipFreeAsync(hist, s);

@@ -29,3 +29,20 @@ def small_graph():
 def tiny_random(n_u, n_v, n_e, seed, gamma=2.3, weights="lognormal"):
     import synth
     return synth.chung_lu(n_u, n_v, n_e, gamma, weights, seed)
+
+
+@pytest.fixture(scope="session")
+def uncaptured(request):
+    """Context manager that lets output through pytest's capture, so long
+    oracle computations inside a test show their own progress lines."""
+    import contextlib
+    capman = request.config.pluginmanager.getplugin("capturemanager")
+
+    @contextlib.contextmanager
+    def cm():
+        if capman is None:
+            yield
+        else:
+            with capman.global_and_fixture_disabled():
+                yield
+    return cm

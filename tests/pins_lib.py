@@ -342,6 +342,46 @@ def pin_warm_start(g, Pi, sources, alpha, eps=1e-6):
     return out
 
 
+def pisp_rounds(alpha, eps):
+    """The PowerIteration rounds of PISP by their definition: the smallest
+    t >= 0 whose dropped mass (1-alpha)^(t+1) is at most eps/2 (a loop, not
+    the log formula)."""
+    t, m = 0, 1.0 - alpha
+    while m > eps / 2:
+        m *= 1.0 - alpha
+        t += 1
+    return t
+
+
+def pin_pisp(g, Pi, sources, alpha, eps_list=(1e-2, 1e-4, 1e-7)):
+    """PISP (Sec. 3.3): the forward part is short of pi(u, .) by exactly
+    the dropped mass (1-alpha)^(t+1) in total and by at most eps/2 per entry,
+    the backward part is within [pi(., u) - eps/2, pi(., u)] (SelectivePush's
+    guarantee), so 0 <= beta - beta' <= eps. The rounds at alpha = 0.15,
+    worked by hand: (1-a)^(t+1) <= eps/2 gives t = 32, 89, 103 at eps = 1e-2,
+    1e-6, 1e-7 (0.85^33 = 0.00469 <= 0.005 < 0.85^32 = 0.00551)."""
+    out = []
+    hand = {1e-2: 32, 1e-6: 89, 1e-7: 103}
+    for e, t in hand.items():
+        _fail(pisp_rounds(0.15, e) == t, f"PISP rounds by hand eps={e}", out)
+    for eps in eps_list:
+        for u in sources:
+            u = int(u)
+            b, pf, pb, st = g.pisp(u, alpha, eps)
+            t = pisp_rounds(alpha, eps)
+            _fail(st["t"] == t, f"PISP t u={u} eps={eps}: {st['t']} != {t}", out)
+            _fail(abs(pf.sum() - (1 - (1 - alpha) ** (t + 1))) <= 1e-12, f"PISP forward mass u={u} eps={eps}", out)
+            d_f = Pi[u, :] - pf
+            d_b = Pi[:, u] - pb
+            d = (Pi[u, :] + Pi[:, u]) - b
+            tol = 1e-12
+            _fail(d_f.min() >= -tol and d_f.max() <= eps / 2 + tol, f"PISP forward band u={u} eps={eps}", out)
+            _fail(d_b.min() >= -tol and d_b.max() <= eps / 2 + tol, f"PISP backward band u={u} eps={eps}", out)
+            _fail(d.min() >= -tol and d.max() <= eps + tol, f"PISP band u={u} eps={eps}", out)
+            _fail(st["sp_iters"] >= 1, f"PISP no SelectivePush iteration u={u}", out)
+    return out
+
+
 def run_core_pins(small, stop_early=False):
     """The pins the mutation tests rely on; fast enough to run per mutant.
     ``small`` holds the edge list and the dense Pi (computed with numpy, not
@@ -356,7 +396,8 @@ def run_core_pins(small, stop_early=False):
               lambda: pin_theorems(g, Pi, src[:4], a, [1e-3, 1e-6])[0],
               lambda: pin_lemma1_and_mass(g, Pi, int(src[0]), a, 1e-5),
               lambda: pin_lambda(g, Pi, a),
-              lambda: pin_warm_start(g, Pi, src, a)]
+              lambda: pin_warm_start(g, Pi, src, a),
+              lambda: pin_pisp(g, Pi, src[:4], a)]
     out = []
     for c in checks:
         try:

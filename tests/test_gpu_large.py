@@ -1,6 +1,14 @@
 """The 100M-edge workload: 5M x 10M nodes, 1024 degree-proportional sources
-run through the queue-fed 64-column block (FP32), top-100 each. Parity on
-sampled sources the oracle computes one by one; properties on all."""
+run through the queue-fed 64-column block (FP32, autotuned launch setting as
+the benchmark runs it), top-100 each. The scores of 32 sampled sources of
+that very batch (the highest- and lowest-degree sources among them) are
+compared with the exact series; every result is checked for properties that
+hold at any size.
+
+Tolerance: -1e-6 <= beta - beta' <= eps + 1e-6 (Definition 1, Theorem 3 plus
+FP32 rounding). The exact rows are the forward series of Eq. (hpp) summed to
+a tail of 1e-8: short of beta by at most 2e-8, which the upper test adds
+back."""
 import numpy as np
 import pytest
 
@@ -9,8 +17,13 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+TAIL = 1e-8
+N_SAMPLE = 32
 
-def test_large_uneven_batch():
+
+@pytest.mark.timeout(1200)
+def test_large_uneven_batch(uncaptured):
+    import torch
     import paper_2312_06724_amd as bh
     wl = synth.LARGE
     print(f"[gpu] generating {wl.name}", flush=True)
@@ -18,8 +31,9 @@ def test_large_uneven_batch():
     src = wl.sources(el)
     print("[gpu] building on the GPU", flush=True)
     G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
+    print(f"[gpu] autotuned {G.autotune()}", flush=True)
     print("[gpu] 1024-source batch", flush=True)
-    out = G.query_batch(src, wl.eps, k=wl.k, exclude_self=True, scores=False)
+    out = G.query_batch(src, wl.eps, k=wl.k, exclude_self=True, scores=True)
     ids = out["ids"].cpu().numpy()
     vals = out["vals"].cpu().numpy()
     st = out["stats"]
@@ -31,21 +45,32 @@ def test_large_uneven_batch():
         assert st[i]["steps"] > 0
     steps = np.array([x["steps"] for x in st])
     print(f"[gpu] sweeps per query: min {steps.min()} median {np.median(steps)} max {steps.max()}", flush=True)
-    # exact parity on a hub source, a tail source, a median-degree source and one more
+    # 32 sources spread over the degree order, the extremes included
     deg = el.degrees_u()
     order = np.argsort(deg[src], kind="stable")
-    pick = [int(order[-1]), int(order[0]), int(order[order.size // 2]), 517]
-    sub = G.query_batch(src[pick], wl.eps, k=wl.k, exclude_self=True, scores=True)
-    S = sub["scores"].double().cpu().numpy()
-    print(f"[gpu] oracle exact rows for {len(pick)} sources", flush=True)
-    g = oracle.Graph.from_edges(el)
-    ex = g.exact_beta_many(src[pick], wl.alpha, tail=1e-9, nthreads=len(pick))
+    pick = np.unique(order[np.linspace(0, src.size - 1, N_SAMPLE).round().astype(int)])
+    assert pick.size == N_SAMPLE
+    S = out["scores"][torch.as_tensor(pick, device="cuda")].cpu().numpy()
+    del out
+    G.close()
+    with uncaptured():
+        print(f"[gpu] oracle: exact rows of {pick.size} sources (series to {TAIL})", flush=True)
+        g = oracle.Graph.from_edges(el)
+        ex = g.exact_beta_many(src[pick], wl.alpha, tail=TAIL, block=N_SAMPLE, progress=8)
+    strict = 0
     for j, i in enumerate(pick):
-        d = ex[j] - S[j]
-        assert d.min() >= -1e-6 and d.max() <= wl.eps + 2e-6, (i, d.min(), d.max())
-        eid, ev = oracle.topk_bruteforce(ex[j], wl.k + 1, exclude=int(src[i]))
-        if ev[wl.k - 1] - ev[wl.k] > wl.eps + 3e-6:
-            assert set(ids[i].tolist()) == set(eid[:wl.k].tolist())
-        # the big batch and the run of the sampled sources agree on the top-k set
-        assert set(ids[i].tolist()) == set(sub["ids"][j].cpu().numpy().tolist()) or \
-            ev[wl.k - 1] - ev[wl.k] <= wl.eps + 3e-6
+        u = int(src[i])
+        d = ex[j] - S[j].astype(np.float64)
+        lo, hi = float(d.min()), float((d + 2 * TAIL).max())
+        print(f"[gpu] source {u} (degree {deg[u]}, {steps[i]} sweeps): min(beta - beta') = {lo:.3e}, "
+              f"max(beta - beta') - eps = {hi - wl.eps:.3e}", flush=True)
+        assert lo >= -1e-6 and hi <= wl.eps + 1e-6, (u, lo, hi - wl.eps)
+        # the batch's top-k is the sort of its own row, and the exact top-k
+        # wherever the k-th gap exceeds the tolerance
+        rid, _ = oracle.topk_bruteforce(S[j], wl.k, exclude=u)
+        assert np.array_equal(ids[i], rid), u
+        eid, ev = oracle.topk_bruteforce(ex[j], wl.k + 1, exclude=u)
+        if ev[wl.k - 1] - ev[wl.k] > wl.eps + 2e-6:
+            assert set(ids[i].tolist()) == set(eid[:wl.k].tolist()), u
+            strict += 1
+    print(f"[gpu] top-k sets compared strictly for {strict} of {pick.size} sources", flush=True)

@@ -36,6 +36,9 @@ MUTANTS = {
     "warm_combine_start": ("beta[x] = pif[x] + pib_ss[x]", "beta[x] = pif[x] + y0[x]"),
     "warm_fallback_never": ("if (!(info.res_l1 < 1.0 && info.res_max < 1.0)) {", "if (0) {"),
     "no_sequential_pushes": ("if (!(rmax > eps_b && rsum > eps_b)) break;", "break;"),
+    "pisp_t_full_eps": ("s.t = orc_t(1.0, 0.5 * eps, alpha);", "s.t = orc_t(1.0, eps, alpha);"),
+    "pisp_eps_b_full_eps": ("const double eps_b = 0.5 * eps;", "const double eps_b = eps;"),
+    "pisp_one_push_only": ("        if (!(rmax > eps_b)) break;\n", "        break;\n"),
 }
 
 

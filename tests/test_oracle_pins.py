@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from pins_lib import (pin_closed_forms, pin_dense_invariants, pin_eps_b, pin_golden_gamma,
-                      pin_golden_rounds, pin_lambda, pin_lemma1_and_mass, pin_power_mass,
+                      pin_golden_rounds, pin_lambda, pin_lemma1_and_mass, pin_pisp, pin_power_mass,
                       pin_random_walk, pin_series_agree, pin_theorems)
 
 
@@ -125,3 +125,43 @@ def test_topk_bruteforce_hand_example():
     assert ids.tolist() == [2, 0, 5, 3]
     ids, _ = oracle.topk_bruteforce(s, 6, exclude=-1)
     assert ids.tolist() == [1, 2, 0, 5, 3, 4]
+
+
+def test_block_series_matches_single_and_dense(small_graph):
+    """The block form of the exact series gives each source's single-source
+    series bit for bit (the same products in the same order), and so matches
+    the dense solve; an isolated source keeps alpha e_u, as the single form."""
+    import synth
+    s = small_graph
+    src = np.asarray(s["sources"][:7])
+    blk = s["g"].hpp_forward_block(src, 0.15, 1e-12, nthreads=3)
+    for i, u in enumerate(src):
+        one = s["g"].hpp_forward(int(u), 0.15, 1e-12)
+        assert np.array_equal(blk[i], one), int(u)
+        assert np.allclose(blk[i], s["Pi"][int(u), :], atol=1e-11)
+    el = synth.chung_lu(40, 60, 50, 2.1, "int10", 4)
+    g = oracle.Graph.from_edges(el)
+    iso = np.nonzero(g.ws_u == 0)[0][:1]
+    live = np.nonzero(g.ws_u > 0)[0][:3]
+    both = np.concatenate([live, iso, live[:1]])
+    blk = g.hpp_forward_block(both, 0.15, 1e-10)
+    for i, u in enumerate(both):
+        assert np.array_equal(blk[i], g.hpp_forward(int(u), 0.15, 1e-10)), int(u)
+    ex = g.exact_beta_many(live, 0.15, tail=1e-10)
+    ex0 = g.exact_beta_many(live, 0.15, tail=1e-10, block=0)
+    assert np.array_equal(ex, ex0)
+
+
+def test_pisp_bands_every_source(small_graph):
+    """PISP (Sec. 3.3) on every source of the 2k x 3k graph at three eps."""
+    s = small_graph
+    assert pin_pisp(s["g"], s["Pi"], s["sources"], s["wl"].alpha) == []
+
+
+def test_pisp_closed_forms():
+    """PISP on the hand-built graphs: the bands against the closed forms."""
+    from pins_lib import CLOSED_FORMS
+    for mk in CLOSED_FORMS.values():
+        (nu, nv, eu, ev, w), Pi = mk()
+        g = oracle.Graph(nu, nv, eu, ev, w)
+        assert pin_pisp(g, Pi, range(nu), 0.15, (1e-2, 1e-5)) == []
