@@ -210,6 +210,29 @@ bhpp_status bhpp_topk(const void* scores, int32_t n_rows, int32_t n, int32_t k,
                       const int32_t* exclude_ids, int32_t dtype,
                       int32_t* ids_out, void* vals_out, void* hip_stream);
 
+/*
+ * bhpp_topk without any allocation, for callers that cannot allocate device
+ * memory: code recorded into a HIP graph by stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same arguments, order and results
+ * as bhpp_topk; the caller still provides scores and outputs. The working
+ * memory of the selection (per row: a state record, a 256-bin histogram and
+ * k candidates) comes from one static device array of about 4.3 MB that the
+ * library holds on each device it runs on until the process ends; its device
+ * address is looked up on the first call on a device. Limits: n_rows <=
+ * BHPP_TOPK_NOALLOC_MAX_ROWS and k <= BHPP_TOPK_NOALLOC_MAX_K, else
+ * NOT_SUPPORTED before any work is enqueued. Every call on a device uses the
+ * same array: calls that overlap on one device (different streams, or
+ * threads enqueueing concurrently) race and must be serialised by the
+ * caller; consecutive calls on one stream are safe (each clears what it uses
+ * with a kernel, not a memset). Does not synchronise.
+ * Errors: INVALID_ARG, NOT_SUPPORTED, DEVICE_ERROR.
+ */
+#define BHPP_TOPK_NOALLOC_MAX_ROWS 64
+#define BHPP_TOPK_NOALLOC_MAX_K 4096
+bhpp_status bhpp_topk_noalloc(const void* scores, int32_t n_rows, int32_t n, int32_t k,
+                              const int32_t* exclude_ids, int32_t dtype,
+                              int32_t* ids_out, void* vals_out, void* hip_stream);
+
 /* Fill *out (host) with the graph summary. Errors: INVALID_ARG. */
 bhpp_status bhpp_graph_info(const bhpp_graph* g, bhpp_graph_summary* out);
 

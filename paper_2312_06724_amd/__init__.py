@@ -28,7 +28,7 @@ DTYPE_F32, DTYPE_F64 = 0, 1
 BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER, BUILD_DENSE_ONLY, BUILD_FIXED_WIDTH = 1, 2, 4, 8
 
 # names exported by include/bhpp.h
-EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_graph_info",
+EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_topk_noalloc", "bhpp_graph_info",
             "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_profile_sweeps", "bhpp_autotune",
             "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_server_create", "bhpp_server_submit",
             "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_model_create", "bhpp_model_params",
@@ -120,6 +120,8 @@ def load_library():
     L.bhpp_query_batch_pisp.argtypes = [P, I32, P, P, D, D, P, I32, I32, P, P, P, P]
     L.bhpp_topk.restype = I32
     L.bhpp_topk.argtypes = [P, I32, I32, I32, P, I32, P, P, P]
+    L.bhpp_topk_noalloc.restype = I32
+    L.bhpp_topk_noalloc.argtypes = [P, I32, I32, I32, P, I32, P, P, P]
     L.bhpp_graph_info.restype = I32
     L.bhpp_graph_info.argtypes = [P, ctypes.POINTER(GraphSummary)]
     L.bhpp_graph_export.restype = I32

@@ -197,6 +197,16 @@ bhpp_status bhpp_topk(const void* scores, int32_t n_rows, int32_t n, int32_t k, 
     }
 }
 
+bhpp_status bhpp_topk_noalloc(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude_ids,
+                              int32_t dtype, int32_t* ids_out, void* vals_out, void* hip_stream) {
+    if (n_rows < 0 || n <= 0 || k < 1 || k > n) return BHPP_INVALID_ARG;
+    if (n_rows > 0 && (!scores || !ids_out || !vals_out)) return BHPP_INVALID_ARG;
+    if (dtype != BHPP_DTYPE_F32 && dtype != BHPP_DTYPE_F64) return BHPP_NOT_SUPPORTED;
+    if (exclude_ids && k > n - 1) return BHPP_INVALID_ARG;
+    if (n_rows > BHPP_TOPK_NOALLOC_MAX_ROWS || k > BHPP_TOPK_NOALLOC_MAX_K) return BHPP_NOT_SUPPORTED;
+    return bhpp::topk_rows_static(scores, n_rows, n, k, exclude_ids, dtype, ids_out, vals_out, stream_of(hip_stream));
+}
+
 bhpp_status bhpp_graph_info(const bhpp_graph* h, bhpp_graph_summary* out) {
     if (!h || !h->g || !out) return BHPP_INVALID_ARG;
     *out = h->g->info;

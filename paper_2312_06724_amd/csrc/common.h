@@ -254,6 +254,9 @@ bhpp_status run_queries(Graph* g, Model* model, const void* starts, bhpp_warm_st
                         int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, hipStream_t s);
 bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
                       int32_t dtype, int32_t* ids_out, void* vals_out, hipStream_t s);
+bhpp_status topk_rows_static(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
+                             int32_t dtype, int32_t* ids_out, void* vals_out, hipStream_t s);
+size_t topk_static_scratch_bytes();
 bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s);
 bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s);
 size_t workspace_bytes(const Graph* g, int cols);

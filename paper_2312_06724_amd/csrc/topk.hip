@@ -9,6 +9,7 @@
 // gathers exactly the k keys at or above it, and a bitonic sort in LDS orders
 // them. All passes read rows with coalesced loads; many blocks share a row.
 #include <cstring>
+#include <mutex>
 
 #include "common.h"
 
@@ -18,6 +19,7 @@ constexpr int kTopkThreads = 256;
 constexpr int kTopkPerThread = 16;
 constexpr int kTopkChunk = kTopkThreads * kTopkPerThread;
 constexpr int kTopkMaxK = 4096;
+constexpr int kTopkStaticRows = 64;   // rows per call of the allocation-free top-k
 
 struct TopkRow {
     uint64_t pre_hi;   // chosen digits so far (left-aligned in a 96-bit key)
@@ -276,6 +278,64 @@ bhpp_status topk_rows(const void* scores, int32_t n_rows, int32_t n, int32_t k, 
         if (rc) return rc;
     }
     return BHPP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Top-k without allocation: the scratch of up to kTopkStaticRows rows at the
+// largest k lives in one file-scope device array, `scratch`, that every call
+// on a device shares (each device holds its own copy until the process ends).
+// Host code never passes the array's name to a kernel: its device address is
+// looked up once per device with hipGetSymbolAddress and kept in
+// g_scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchSt = 256 * ((sizeof(TopkRow) * kTopkStaticRows + 255) / 256);
+constexpr size_t kScratchHist = sizeof(uint32_t) * 256 * kTopkStaticRows;
+constexpr size_t kScratchCand = sizeof(Cand) * (size_t)kTopkMaxK * kTopkStaticRows;
+constexpr size_t kScratchBytes = kScratchSt + kScratchHist + kScratchCand;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with it current).
+static bhpp_status scratch_of_current_device(unsigned char** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BHPP_DEVICE_ERROR;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return BHPP_DEVICE_ERROR;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+    return BHPP_OK;
+}
+
+size_t topk_static_scratch_bytes() { return kScratchBytes; }
+
+bhpp_status topk_rows_static(const void* scores, int32_t n_rows, int32_t n, int32_t k, const int32_t* exclude,
+                             int32_t dtype, int32_t* ids_out, void* vals_out, hipStream_t s) {
+    if (k > kTopkMaxK || n_rows > kTopkStaticRows) return BHPP_NOT_SUPPORTED;
+    if (dtype != BHPP_DTYPE_F64 && dtype != BHPP_DTYPE_F32) return BHPP_NOT_SUPPORTED;
+    if (n_rows == 0) return BHPP_OK;
+    unsigned char* base = nullptr;
+    bhpp_status rc = scratch_of_current_device(&base);
+    if (rc) return rc;
+    TopkRow* st = reinterpret_cast<TopkRow*>(base);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(base + kScratchSt);
+    Cand* cand = reinterpret_cast<Cand*>(base + kScratchSt + kScratchHist);
+    if (dtype == BHPP_DTYPE_F64)
+        topk_passes<double>((const double*)scores, n_rows, n, k, exclude, ids_out, (double*)vals_out, st, hist, cand,
+                            s);
+    else
+        topk_passes<float>((const float*)scores, n_rows, n, k, exclude, ids_out, (float*)vals_out, st, hist, cand, s);
+    return hipGetLastError() == hipSuccess ? BHPP_OK : BHPP_DEVICE_ERROR;
 }
 
 }  // namespace bhpp
