@@ -141,7 +141,9 @@ def roofline(prof, stats, info, workload):
                avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom], live_sweeps=int(L),
                algorithmic_bytes_per_launch=int(alg[dom] / launches),
                counts=dict(column_sweeps=int(CS), visits_u=VU, visits_v=VV, edge_visits=VU + VV,
-                           paper_work_units=paper_units),
+                           paper_work_units=paper_units,
+                           sparse_column_sweeps=int(sum(s["sparse_sweeps"] for s in stats)),
+                           column_use=round(CS / max(1.0, 64.0 * L), 4)),
                compulsory=dict(bytes_per_launch=int(comp[dom] / launches), achieved=round(comp[dom] / sec / 1e9, 1),
                                frac=round(comp[dom] / sec / 1e9 / HBM_PEAK_GBS, 4)),
                kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
@@ -153,24 +155,37 @@ def roofline(prof, stats, info, workload):
     return out
 
 
-def cpu_baseline(el, sources, wl, threads):
-    """The FP64 oracle (Algorithms 1-5, one query per thread) on the first
-    `threads` sources of the set."""
+def cpu_baseline(el, sources, wl, threads, work_per_query, iters):
+    """The FP64 oracle (Algorithm 5 as it stands, one query per thread) on a
+    bounded sample: the first `threads` sources of the set, each stopped after
+    `iters` push iterations (a whole query takes minutes on this graph). The
+    sample's rate of edge visits (the paper's work unit n_p, 2|E| per
+    PowerIteration round) over all threads, divided by the mean work of a
+    whole query of the same sources (from their GPU statistics: n_p of both
+    sub-algorithms plus 2|E| t, the same iteration sequence), gives queries/s."""
     import oracle
     t0 = time.perf_counter()
     g = oracle.Graph.from_edges(el)
-    lam = g.lambda_(wl.alpha)
+    # lambda only sets PI-Push's thresholds, which the sampled iterations
+    # (SS-Push's first pushes) never reach: the ws-ratio branch of Eq. (lambda),
+    # a valid bound by Lemma 4, spares the oracle's long power iteration
+    ws = g.ws_u
+    lam = float(ws.max() / ws[ws > 0].min())
     eps_b = g.eps_b(wl.eps)
     t_pre = time.perf_counter() - t0
     sample = sources[:threads]
     t0 = time.perf_counter()
-    _, st = g.approx_bhpp_many(sample, wl.alpha, wl.eps, eps_b, lam, nthreads=threads, keep=False)
+    work = g.approx_bhpp_sample(sample, wl.alpha, wl.eps, iters, eps_b, lam, nthreads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=len(sample) / dt, unit="queries/s", cores=threads, kind="oracle",
-                ms_per_query_per_thread=round(dt * 1e3, 1),
+    rate = float(work.sum()) / dt
+    return dict(value=rate / work_per_query, unit="queries/s", cores=threads, kind="oracle",
+                edge_visits_per_s=round(rate, 1), work_per_query=work_per_query,
+                s_per_query_per_thread=round(work_per_query / (rate / threads), 1),
                 sample=f"{len(sample)} of the {len(sources)} sources of {wl.name}, one query per thread, FP64 "
-                       f"Approx-BHPP (Algorithms 1-5); graph build, lambda and eps_b ({t_pre:.1f} s) not timed; "
-                       f"{dt:.1f} s wall")
+                       f"Approx-BHPP (Algorithms 1-5) stopped after {iters} push iterations: "
+                       f"{work.sum():.4g} edge visits in {dt:.1f} s wall; a whole query of these sources does "
+                       f"{work_per_query:.4g} (mean, from their GPU statistics); graph build, lambda and eps_b "
+                       f"({t_pre:.1f} s) not timed")
 
 
 def run_headline(bh, torch, np, args, hinfo):
@@ -182,7 +197,14 @@ def run_headline(bh, torch, np, args, hinfo):
     log(f"graph {wl.name}: {el.n_e} edges generated in {time.perf_counter() - t0:.1f}s")
     G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
     info = G.info()
-    cfg = G.autotune()
+    if args.launch:
+        t, i, n, c = (int(x) for x in args.launch.split(","))
+        cfg = dict(tile_edges=t, inflight=i, nt_stream=n, graphs=1)
+        G.set_launch_config(cfg)
+        G.set_schedule(c)
+    else:
+        cfg = G.autotune()
+    cfg.update(G.schedule())
     log(f"built on GPU in {info['build_ms']:.0f} ms; lambda={info['lambda']:.1f} "
         f"eps_b/eps={info['eps_b_ratio']:.4f}; autotuned {cfg}")
     per = args.sources_per_step
@@ -231,8 +253,16 @@ def run_headline(bh, torch, np, args, hinfo):
     cpu = None
     if not args.no_cpu_baseline:
         n = args.cpu_threads or hinfo["threads"]
+        E = float(info["n_edges"])
+        # whole-query work of the sampled sources (the first n of the set), from the timed steps' statistics
+        first = {int(u): s for u, s in zip(np.concatenate([src[(i % parts) * per:(i % parts + 1) * per]
+                                                           for i in range(args.steps)]), stats)}
+        w = [first[int(u)]["np_ss"] + first[int(u)]["np_pi"] + 2 * E * first[int(u)]["t"]
+             for u in src[:n] if int(u) in first]
+        if not w:
+            w = [s["np_ss"] + s["np_pi"] + 2 * E * s["t"] for s in stats]
         log(f"CPU oracle baseline on {n} threads ...")
-        cpu = cpu_baseline(el, src, wl, n)
+        cpu = cpu_baseline(el, src, wl, n, float(np.mean(w)), args.cpu_iters)
         cpu.update(cpu_model=hinfo["cpu_model"], nproc=hinfo["nproc"], affinity=hinfo["affinity"])
         log(f"CPU oracle: {cpu['value']:.4f} q/s")
     head["cpu"] = cpu
@@ -304,6 +334,71 @@ def run_learned(bh, torch, np, G, el, wl, src, n_train, steps, reps):
                    data_s=round(t_data, 1), train_s=round(t_train, 1),
                    loss_first=float(losses[:50].mean()), loss_last=float(losses[-50:].mean()),
                    batched_learned=learned, ablation_self_term_only=ablation)
+
+
+def run_learned_curve(bh, torch, np, G, el, wl, src, sizes):
+    """The learned start against training-set size: training data (top-64 of
+    beta' plus 64 random entries) from the plain GPU path for max(sizes)
+    uniform sources disjoint from the evaluation sources; for each size a
+    fresh model is trained on the first `size` of them. On the evaluation
+    sources it reports the prediction error ||p_hat(u, .) - pi(u, .)||_1 (pi
+    from the plain path's beta' by Lemma 3: pi(u, x) = beta' ws(x)/(ws(u) +
+    ws(x))), the start's residual norm, the fallback rate and the sweeps,
+    beside the structural self term alone (size 0)."""
+    import synth
+    n_max = max(sizes)
+    live = np.nonzero(el.degrees_u() > 0)[0]
+    rng = np.random.default_rng(78)
+    cand = synth.sample_sources(el, n_max + src.size, "uniform", 4343)
+    train = np.setdiff1d(cand, src)[:n_max].astype(np.int32)
+    rng.shuffle(train)
+    ws = np.bincount(el.u, weights=el.w, minlength=el.n_u)
+    ws_t = torch.from_numpy(ws).to("cuda")
+    ref = G.query_batch(src, wl.eps, k=0, exclude_self=False, scores=True, stats=True)
+    pi = ref["scores"].double() * ws_t[None, :] / (ws_t[src.astype(np.int64)][:, None] + ws_t[None, :])
+    cold_sweeps = float(np.mean([x["steps"] for x in ref["stats"]]))
+    t0 = time.perf_counter()
+    ids = np.full((train.size, 128), -1, np.int32)
+    vals = np.zeros((train.size, 128), np.float32)
+    for i in range(0, train.size, 64):
+        chunk = train[i:i + 64]
+        out = G.query_batch(chunk, wl.eps, k=64, exclude_self=False, scores=True, stats=False)
+        r = torch.from_numpy(rng.choice(live, (chunk.size, 64))).to("cuda")
+        rv = torch.gather(out["scores"], 1, r.long())
+        ii = torch.cat([out["ids"], r.int()], 1).cpu().numpy()
+        vv = torch.cat([out["vals"], rv], 1).cpu().numpy()
+        for j, (a, b) in enumerate(zip(ii, vv)):
+            _, keep = np.unique(a, return_index=True)
+            ids[i + j, :keep.size], vals[i + j, :keep.size] = a[keep], b[keep]
+        del out
+        if (i // 64) % 200 == 0:
+            log(f"learned curve: training data {i + chunk.size}/{train.size}")
+    t_data = time.perf_counter() - t0
+    log(f"learned curve: training data from {train.size} plain queries in {t_data:.1f}s")
+    rows = []
+    for n in [0] + sorted(sizes):
+        M = bh.Model(G, seed=1)
+        steps = 0
+        if n == 0:
+            M.set_params(np.zeros(bh.MODEL_PARAMS, np.float32))
+            losses = np.zeros(1)
+        else:
+            steps = int(min(20000, max(2000, n // 10)))
+            losses = M.train(train[:n], ids[:n], vals[:n], steps=steps, batch_src=32, batch_cand=4096, lr=5e-4)
+        M.embed()
+        p_hat = M.predict(src).double()
+        dp = (p_hat - pi).abs().sum(1).cpu().numpy()
+        o = G.query_batch(src, wl.eps, k=0, scores=False, stats=True, model=M)
+        r = np.array([w["res_l1"] for w in o["warm"]])
+        fb = np.array([w["fell_back"] for w in o["warm"]])
+        rows.append(dict(train_sources=int(n), train_steps=steps, loss_last=float(np.mean(losses[-50:])),
+                         dp_l1_median=round(float(np.median(dp)), 4), dp_l1_max=round(float(dp.max()), 4),
+                         res_l1_median=round(float(np.median(r)), 4), fallback_rate=round(float(fb.mean()), 3),
+                         mean_sweeps_per_query=float(np.mean([x["steps"] for x in o["stats"]]))))
+        log(f"learned curve: {rows[-1]}")
+        M.close()
+        del p_hat
+    return dict(eval_sources=int(src.size), data_s=round(t_data, 1), cold_mean_sweeps=cold_sweeps, curve=rows)
 
 
 def run_serving(bh, G, el, wl, rates, duration, np, model=None):
@@ -385,6 +480,40 @@ def run_serving(bh, G, el, wl, rates, duration, np, model=None):
     return res
 
 
+def run_baselines(bh, torch, np, G, wl, src):
+    """The paper's comparison (Sec. 5.4, Fig. 3) on the GPU: Approx-BHPP
+    against PISP and MCSP (Sec. 3.3) on the same sources, batched, at several
+    eps. Time per batch, best of two runs after a warm-up; MCSP only where
+    its walk count stays small (the paper drops it at small eps too)."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(2):
+            t0 = time.perf_counter()
+            o = fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return o, best
+    rows = []
+    for eps in (1e-2, 1e-4, 1e-6, 1e-7):
+        a, ta = timed(lambda: G.query_batch(src, eps, k=wl.k, scores=False, stats=True))
+        p, tp = timed(lambda: G.query_batch(src, eps, k=wl.k, scores=False, stats=True, method="pisp"))
+        rec = dict(eps=eps, approx_qps=round(src.size / ta, 2), pisp_qps=round(src.size / tp, 2),
+                   approx_sweeps=float(np.mean([x["steps"] for x in a["stats"]])),
+                   pisp_sweeps=float(np.mean([x["steps"] for x in p["stats"]])),
+                   approx_edge_visits=float(np.mean([x["visits_u"] + x["visits_v"] for x in a["stats"]])),
+                   pisp_edge_visits=float(np.mean([x["visits_u"] + x["visits_v"] for x in p["stats"]])),
+                   speedup_over_pisp=round(tp / ta, 3))
+        if eps >= 1e-2:
+            m, tm = timed(lambda: G.query_mcsp(src, eps, p_f=1e-6, seed=1, k=wl.k, scores=False, stats=False))
+            rec.update(mcsp_qps=round(src.size / tm, 2), mcsp_walks_per_query=m["walks"],
+                       speedup_over_mcsp=round(tm / ta, 3))
+        rows.append(rec)
+        log(f"baselines eps={eps}: {rec}")
+    return rows
+
+
 def run_medium(bh, torch, np, args):
     """The 1M x 2M graph: plain batched (64 uniform sources per batch) and
     single-source queries, eps_b tuning, learned warm start, serving."""
@@ -394,7 +523,7 @@ def run_medium(bh, torch, np, args):
     el = wl.graph()
     src = wl.sources(el)
     log(f"graph {wl.name}: {el.n_e} edges generated in {time.perf_counter() - t0:.1f}s")
-    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32")
+    G = bh.Graph.from_edges(el, alpha=wl.alpha, dtype="f32", mcsp=not args.no_baselines)
     info = G.info()
     out = dict(workload=wl.name, sources=int(src.size), source_sampling="uniform non-isolated",
                lambda_=round(info["lambda"], 3))
@@ -421,6 +550,8 @@ def run_medium(bh, torch, np, args):
         torch.cuda.synchronize()
         out["single_source_qps"] = round(args.single / (time.perf_counter() - t1), 3)
         log(f"{wl.name}: single-source {out['single_source_qps']} q/s")
+    if not args.no_baselines:
+        out["baselines"] = run_baselines(bh, torch, np, G, wl, src)
     if not args.no_tune_eps_b:
         paper = info["eps_b_ratio"]
         sample = np.setdiff1d(synth.sample_sources(el, 128, "uniform", 9090), src)[:64]
@@ -446,6 +577,9 @@ def run_medium(bh, torch, np, args):
         if out.get("single_source_qps"):
             out["learned"]["gain_over_single_source"] = round(
                 out["learned"]["batched_learned"]["queries_per_s"] / out["single_source_qps"], 2)
+    if args.learned_curve:
+        sizes = [int(x) for x in args.learned_curve.split(",") if x.strip()]
+        out["learned_curve"] = run_learned_curve(bh, torch, np, G, el, wl, src, sizes)
     rates = [float(x) for x in args.serve.split(",") if x.strip()]
     if rates:
         out["serving"] = run_serving(bh, G, el, wl, rates, args.serve_seconds, np, model)
@@ -465,12 +599,20 @@ def main():
     ap.add_argument("--single", type=int, default=4, help="sources timed one at a time on each graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--cpu-iters", type=int, default=6, help="push iterations per query of the CPU sample")
     ap.add_argument("--no-medium", action="store_true", help="skip the 1M x 2M graph's measurements")
     ap.add_argument("--medium-reps", type=int, default=5)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm start")
+    ap.add_argument("--no-baselines", action="store_true", help="skip the PISP / MCSP comparison")
     ap.add_argument("--no-tune-eps-b", action="store_true", help="skip the eps_b split tuning")
     ap.add_argument("--train-sources", type=int, default=2048)
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--learned-curve", default="",
+                    help="training-set sizes for the learned-start curve on the 1M x 2M graph, e.g. 2048,20000,200000")
+    ap.add_argument("--no-headline", action="store_true", help="skip the 100M-edge headline (extras only)")
+    ap.add_argument("--launch", default="",
+                    help="tile,inflight,nt,chunk launch setting for the headline graph instead of autotuning "
+                         "(profiling runs)")
     ap.add_argument("--serve", default="150,300,2000,20000",
                     help="Poisson arrival rates (q/s) for the serving run; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=6.0)
@@ -497,6 +639,12 @@ def main():
         log("copy probe: 1 GiB read + 1 GiB written")
         del a, b
 
+    if args.no_headline:   # extras only (experiments); no headline value
+        medium = run_medium(bh, torch, np, args)
+        print(json.dumps({"metric": "BHPP queries/s at eps=1e-6 (plain vs batched+learned); HBM GB/s; p99 ms",
+                          "value": None, "unit": "queries/s", "n_gpus": 1, "host": hinfo, "medium": medium}),
+              flush=True)
+        return
     head = run_headline(bh, torch, np, args, hinfo)
     medium = None if args.no_medium else run_medium(bh, torch, np, args)
     wl, info = head["wl"], head["info"]

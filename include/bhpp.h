@@ -80,10 +80,15 @@ typedef struct {
    variable BHPP_TUNE, a comma-separated list of tile=<entries per work tile>,
    inflight=<4|8|16>, nt=<0|1> (non-temporal adjacency loads), graphs=<0|1>
    (replay sweeps as HIP graphs), sparse=<0|1> (as BHPP_BUILD_DENSE_ONLY),
-   narrow=<0|1> (as BHPP_BUILD_FIXED_WIDTH) and fuse=<0|1> (64-column blocks:
+   narrow=<0|1> (as BHPP_BUILD_FIXED_WIDTH), fuse=<0|1> (64-column blocks:
    the V-side gather applies the push rule itself instead of a separate
-   selection pass; same bits either way). */
+   selection pass; same bits either way) and hub=<0|1> (one-source gathers
+   read the values of the highest-degree nodes from a copy in LDS; same
+   bits either way). */
 #define BHPP_BUILD_FIXED_WIDTH   8u
+/* Build MCSP's Walker alias tables (bhpp_query_batch_mcsp): 16 bytes per
+   adjacency entry per side. */
+#define BHPP_BUILD_MCSP         16u
 
 typedef struct bhpp_graph bhpp_graph;  /* opaque; owns all of its device memory */
 
@@ -96,7 +101,8 @@ typedef struct {
     int32_t ss_switched;    /* 1 if Eq. (bwd-np) switched SS-Push to sequential pushes */
     int32_t pi_returned;    /* 1 if Eq. (fwd-eps) ended PI-Push without power iterations */
     int32_t steps;          /* two-hop sweeps executed for this source */
-    int32_t reserved;
+    int32_t sparse_sweeps;  /* of those, sweeps whose pushed U nodes have fewer than |E|/16 edges
+                               (a frontier small enough for edge-parallel push steps) */
     double np_ss;           /* push cost n_p recorded by SS-Push (edges touched) */
     double np_pi;           /* push cost n_p recorded by PI-Push */
     double gamma;           /* Eq. (gamma) */
@@ -292,6 +298,20 @@ bhpp_status bhpp_profile_sweeps(bhpp_graph* g, int64_t* live_out);
  * DEVICE_ERROR.
  */
 bhpp_status bhpp_autotune(bhpp_graph* g, void* hip_stream, int32_t config_out[4]);
+/*
+ * Scheduling of query batches: sched[0] sweeps per launched chunk (1..8;
+ * phase control runs on the device every sweep, the host looks at the block
+ * only between chunks), sched[1] 1 to let queue-fed batches of more than 64
+ * sources admit new queries without draining the stream (the host reads
+ * copies of the column states one chunk behind and queues the finished
+ * queries' extraction, top-k and the next admissions behind the running
+ * sweeps), 0 for draining export rounds. Results do not depend on them.
+ * bhpp_autotune also sets sched[0] from the sweep time it measured (chunks
+ * of about 2 ms). Errors: INVALID_ARG (also while a server of this graph
+ * exists).
+ */
+bhpp_status bhpp_set_schedule(bhpp_graph* g, const int32_t sched[2]);
+bhpp_status bhpp_get_schedule(const bhpp_graph* g, int32_t sched_out[2]);
 bhpp_status bhpp_set_launch_config(bhpp_graph* g, const int32_t config[4]);
 bhpp_status bhpp_get_launch_config(const bhpp_graph* g, int32_t config_out[4]);
 
@@ -362,6 +382,12 @@ bhpp_status bhpp_model_train(bhpp_model* m, int32_t n_src, const int32_t* src, i
                              const float* vals, int32_t steps, int32_t batch_src, int32_t batch_cand, double lr,
                              uint64_t seed, float* loss_out);
 bhpp_status bhpp_model_embed(bhpp_model* m);
+/* The start the model gives each source, as estimates of pi(u, x) (the warm
+   queries' p_hat, self term included, clamped at 0): out device FP32
+   [n_src][n_u], caller ids; sources host, caller ids. Needs embeddings.
+   Synchronises hip_stream. Errors: INVALID_ARG, OUT_OF_RANGE,
+   ISOLATED_SOURCE, OUT_OF_MEMORY, DEVICE_ERROR. */
+bhpp_status bhpp_model_predict(bhpp_model* m, int32_t n_src, const int32_t* sources, float* out, void* hip_stream);
 void bhpp_model_free(bhpp_model* m);
 bhpp_status bhpp_query_batch_warm(bhpp_graph* g, bhpp_model* m, int32_t n_src, const int32_t* sources,
                                   const double* eps, double alpha, double eps_all, void* scores_out, int32_t k,
@@ -404,6 +430,33 @@ bhpp_status bhpp_query_batch_pisp(bhpp_graph* g, int32_t n_src, const int32_t* s
                                   void* scores_out, int32_t k, int32_t exclude_self,
                                   int32_t* topk_ids, void* topk_vals,
                                   bhpp_query_stats* stats, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * MCSP, the paper's other baseline (Sec. 3.3, Baselines and Challenges;
+ * Sec. 5.4, Fig. 3), on a graph built with BHPP_BUILD_MCSP: for each source
+ * u, pi(u, .) estimated by MonteCarlo, n_r = 2 (1 + eps_f/3) ln(|U|/p_f) /
+ * eps_f^2 random walks with restart (eps_f = eps/2, rounded up; the paper's
+ * experiments use p_f = 1e-6), whose steps draw neighbours from Walker alias
+ * tables (weights w/ws of the row); plus pi(., u) by SelectivePush
+ * (Algorithm 2) with eps_b = eps/2; beta' = (walks ending at x)/n_r + pi_b(x),
+ * within eps of beta with probability at least 1 - p_f.
+ * The walks draw from Philox4x32-10 under the 64-bit seed: walk w of source u
+ * takes at step s the counters (w, u, 2s, 0x4D435350) and (w, u, 2s + 1,
+ * 0x4D435350) under the key (seed low 32 bits, seed high 32 bits); r0 of the
+ * first block stops the walk if r0 < alpha 2^32, else (r1, r2) pick the U->V
+ * step and (r3, first number of the second block) the V->U step: slot =
+ * (r d) >> 32 of a row of d entries, kept iff r' 2^-32 < prob(slot), else
+ * its alias. Outputs, top-k and statistics (of SelectivePush) as
+ * bhpp_query_batch; scores_out may be NULL (the rows are then held in a
+ * temporary buffer for the top-k); walks_out (host, nullable) receives n_r.
+ * Synchronises hip_stream.
+ * Errors: as bhpp_query_batch, NOT_SUPPORTED without the tables or when n_r
+ * exceeds 2^32 - 1 (eps too small).
+ * ---------------------------------------------------------------------- */
+bhpp_status bhpp_query_batch_mcsp(bhpp_graph* g, int32_t n_src, const int32_t* sources, double eps,
+                                  double alpha, double p_f, uint64_t seed, void* scores_out, int32_t k,
+                                  int32_t exclude_self, int32_t* topk_ids, void* topk_vals,
+                                  bhpp_query_stats* stats, int64_t* walks_out, void* hip_stream);
 
 /* Warm start from caller-given starts instead of a model: starts is device
    [n_src][n_u] of the graph dtype, row i = estimates of pi(sources[i], x) for

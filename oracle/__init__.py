@@ -115,6 +115,13 @@ def _load():
                                            ctypes.POINTER(WarmInfo)]
         L.orc_approx_bhpp_warm_many.argtypes = [P, I32, P, D, D, D, D, P, P, P, P, I32]
         L.orc_pisp.argtypes = [P, I32, D, D, P, P, P, P]
+        L.orc_approx_bhpp_sample.argtypes = [P, I32, P, D, D, D, D, I32, P, I32]
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_alias_tables.argtypes = [P, I32, P, P]
+        L.orc_mc_walks.restype = I64
+        L.orc_mc_walks.argtypes = [I32, D, D]
+        L.orc_mc_counts.argtypes = [P, I32, D, I64, ctypes.c_uint64, P, P]
+        L.orc_mcsp.argtypes = [P, I32, D, D, D, ctypes.c_uint64, P, P, P, P]
         L.orc_pisp_many.argtypes = [P, I32, P, D, D, P, P, I32]
         L.orc_max_threads.restype = ctypes.c_int
         L.orc_t.restype = I32
@@ -298,6 +305,45 @@ class Graph:
                                      ctypes.cast(st, ctypes.c_void_p), int(nthreads)))
         return beta, [st[i].as_dict() for i in range(src.size)]
 
+    def approx_bhpp_sample(self, sources, alpha, eps, max_iters, eps_b=None, lam=None, nthreads=0):
+        """Algorithm 5 for each source, stopped after max_iters push
+        iterations (a bounded sample for timing); returns the edges each
+        query touched."""
+        eps_b = self.eps_b(eps) if eps_b is None else eps_b
+        lam = self.lambda_(alpha) if lam is None else lam
+        src = np.ascontiguousarray(sources, dtype=np.int32)
+        work = np.zeros(src.size)
+        _check(_load().orc_approx_bhpp_sample(self._h, src.size, _ptr(src), alpha, eps, eps_b, lam, int(max_iters),
+                                              _ptr(work), int(nthreads)))
+        return work
+
+    # ---- MCSP (Sec. 3.3, Baselines and Challenges) ----
+    def alias_tables(self, side):
+        """Walker alias tables (Vose's construction) of the rows of U
+        (side 0, entries as in export()['ci_u']) or of V (side 1)."""
+        prob = np.empty(self.n_e)
+        alias = np.empty(self.n_e, np.int32)
+        _check(_load().orc_alias_tables(self._h, int(side), _ptr(prob), _ptr(alias)))
+        return prob, alias
+
+    def mc_counts(self, u, alpha, n_r, seed):
+        """End nodes of n_r random walks with restart from u (Philox draws)."""
+        counts = np.empty(self.n_u, np.int64)
+        steps = ctypes.c_double()
+        _check(_load().orc_mc_counts(self._h, int(u), alpha, int(n_r), ctypes.c_uint64(seed), _ptr(counts),
+                                     ctypes.byref(steps)))
+        return counts, steps.value
+
+    def mcsp(self, u, alpha, eps, p_f=1e-6, seed=0):
+        """The MCSP baseline: MonteCarlo with eps/2 plus SelectivePush with
+        eps/2. Returns (beta', counts, pi_b, n_r)."""
+        beta, pib = np.empty(self.n_u), np.empty(self.n_u)
+        counts = np.empty(self.n_u, np.int64)
+        n_r = ctypes.c_int64()
+        _check(_load().orc_mcsp(self._h, int(u), alpha, eps, p_f, ctypes.c_uint64(seed), _ptr(beta), _ptr(counts),
+                                _ptr(pib), ctypes.byref(n_r)))
+        return beta, counts, pib, int(n_r.value)
+
     def warm_residue(self, u, alpha, y):
         """Signed residue of a warm start y (estimates of pi(x, u)):
         r = e_u - (y - (1-alpha) P y) / alpha (Lemma 1 holds for it)."""
@@ -321,6 +367,21 @@ class Graph:
                                                  _ptr(beta), ctypes.cast(st, ctypes.c_void_p),
                                                  ctypes.cast(wi, ctypes.c_void_p), int(nthreads)))
         return beta, [st[i].as_dict() for i in range(src.size)], [wi[i].as_dict() for i in range(src.size)]
+
+
+def philox4x32_10(ctr, key):
+    """One block of Philox4x32-10: four 32-bit counters and two 32-bit key
+    words in, four 32-bit numbers out."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    _load().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def mc_walks(n_u, eps_f, p_f):
+    """MonteCarlo's walk count for an eps_f error with failure probability p_f."""
+    return int(_load().orc_mc_walks(int(n_u), eps_f, p_f))
 
 
 def max_threads() -> int:

@@ -509,9 +509,23 @@ int32_t orc_t(double sum_rf, double eps_f, double alpha);
  *   pi_f   = the forward estimate of pi(u, x)  (Algorithm 4's output)
  *   pi_b   = the backward estimate of pi(x, u) (after PI-Push's pushes)
  */
+/* Algorithm 5 with a cap on the push iterations (ORC_ENOCONV past it); work,
+ * if not NULL, receives the edges touched: the n_p of every push iteration
+ * and 2|E| per PowerIteration round. */
+static int approx_bhpp_core(const orc_graph* g, int32_t u, double alpha, double eps, double eps_b, double lambda,
+                            double* beta, double* pi_f_out, double* pi_b_out, orc_stats* st,
+                            orc_trace_fn trace, void* ctx, int32_t cap, double* work);
+
 int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, double eps_b, double lambda,
                     double* beta, double* pi_f_out, double* pi_b_out, orc_stats* st,
                     orc_trace_fn trace, void* ctx) {
+    return approx_bhpp_core(g, u, alpha, eps, eps_b, lambda, beta, pi_f_out, pi_b_out, st, trace, ctx,
+                            ORC_MAX_ITERS, NULL);
+}
+
+static int approx_bhpp_core(const orc_graph* g, int32_t u, double alpha, double eps, double eps_b, double lambda,
+                            double* beta, double* pi_f_out, double* pi_b_out, orc_stats* st,
+                            orc_trace_fn trace, void* ctx, int32_t cap, double* work) {
     if (u < 0 || u >= g->nu) return ORC_ERANGE;
     if (!(alpha > 0.0 && alpha < 1.0) || !(eps > 0.0) || !(eps_b > 0.0 && eps_b < eps) || !(lambda > 0.0))
         return ORC_EINVAL;
@@ -531,8 +545,8 @@ int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, dou
     int ss_done = 0;
     int32_t iters = 0;
     for (;;) {                                   /* selective pushes */
-        if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
-        np += push_iteration(g, &w, alpha);
+        if (++iters > cap) { work_free(&w); return ORC_ENOCONV; }
+        { const double d = push_iteration(g, &w, alpha); np += d; if (work) *work += d; }
         ++s.ss_sel_iters;
         if (trace) trace(ctx, PH_SS_SEL, s.ss_sel_iters, w.pib, w.r);
         double rmax = 0.0, rsum = 0.0;
@@ -548,8 +562,8 @@ int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, dou
             double rmax = 0.0, rsum = 0.0;
             for (int32_t x = 0; x < nu; ++x) { if (w.r[x] > rmax) rmax = w.r[x]; rsum += w.r[x]; }
             if (!(rmax > eps_b && rsum > eps_b)) break;
-            if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
-            s.np_ss += push_iteration(g, &w, alpha);
+            if (++iters > cap) { work_free(&w); return ORC_ENOCONV; }
+            { const double d = push_iteration(g, &w, alpha); s.np_ss += d; if (work) *work += d; }
             ++s.ss_seq_iters;
             if (trace) trace(ctx, PH_SS_SEQ, s.ss_seq_iters, w.pib, w.r);
         }
@@ -570,8 +584,8 @@ int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, dou
     np = 0.0;
     int pi_returned = 0;
     for (;;) {
-        if (++iters > ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
-        np += push_iteration(g, &w, alpha);
+        if (++iters > cap) { work_free(&w); return ORC_ENOCONV; }
+        { const double d = push_iteration(g, &w, alpha); np += d; if (work) *work += d; }
         ++s.pi_sel_iters;
         if (trace) trace(ctx, PH_PI_SEL, s.pi_sel_iters, w.pib, w.r);
         int all_below = 1;                       /* Eq. (fwd-eps) for every node */
@@ -596,6 +610,7 @@ int orc_approx_bhpp(const orc_graph* g, int32_t u, double alpha, double eps, dou
         s.sum_rf = fsum;
         int32_t t = orc_t(fsum, eps_f, alpha);                                              /* Eq. (t) */
         s.t = t;
+        if (work) *work += E2 * (double)t;
         int rc = orc_power_iteration(g, rf, alpha, t, pr);                                   /* Algorithm 1 */
         if (rc) { free(rf); free(pr); work_free(&w); return rc; }
         for (int32_t x = 0; x < nu; ++x) pif[x] += pr[x];
@@ -866,6 +881,30 @@ typedef struct {
     double np;          /* edges touched by SelectivePush */
 } orc_pisp_stats;
 
+/* SelectivePush (Algorithm 2) from r = e_u: push iterations with threshold
+ * thr_b (its eps_b) until no U residue exceeds it (the loop's only exit); pib
+ * receives pi_b(x, u), within [pi(x, u) - thr_b, pi(x, u)]. */
+static int selective_push(const orc_graph* g, int32_t u, double alpha, double thr_b, double* pib, int32_t* iters,
+                          double* np) {
+    orc_work w;
+    if (work_alloc(&w, g)) return ORC_ENOMEM;
+    for (int32_t x = 0; x < g->nu; ++x) w.thr[x] = thr_b;
+    w.r[u] = 1.0;
+    *iters = 0;
+    *np = 0.0;
+    for (;;) {
+        if (*iters >= ORC_MAX_ITERS) { work_free(&w); return ORC_ENOCONV; }
+        *np += push_iteration(g, &w, alpha);
+        *iters += 1;
+        double rmax = 0.0;
+        for (int32_t x = 0; x < g->nu; ++x) rmax = w.r[x] > rmax ? w.r[x] : rmax;
+        if (!(rmax > thr_b)) break;
+    }
+    memcpy(pib, w.pib, sizeof(double) * (size_t)g->nu);
+    work_free(&w);
+    return ORC_OK;
+}
+
 int orc_pisp(const orc_graph* g, int32_t u, double alpha, double eps, double* beta, double* pi_f_out,
              double* pi_b_out, orc_pisp_stats* st) {
     if (u < 0 || u >= g->nu) return ORC_ERANGE;
@@ -883,26 +922,17 @@ int orc_pisp(const orc_graph* g, int32_t u, double alpha, double eps, double* be
     free(e);
     if (rc) { free(pif); return rc; }
     /* backward part */
-    orc_work w;
-    if (work_alloc(&w, g)) { free(pif); return ORC_ENOMEM; }
-    const double eps_b = 0.5 * eps;
-    for (int32_t x = 0; x < g->nu; ++x) w.thr[x] = eps_b;
-    w.r[u] = 1.0;
-    for (;;) {
-        if (s.sp_iters >= ORC_MAX_ITERS) { work_free(&w); free(pif); return ORC_ENOCONV; }
-        s.np += push_iteration(g, &w, alpha);
-        s.sp_iters += 1;
-        double rmax = 0.0;
-        for (int32_t x = 0; x < g->nu; ++x) rmax = w.r[x] > rmax ? w.r[x] : rmax;
-        if (!(rmax > eps_b)) break;
-    }
+    double* pib = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    if (!pib) { free(pif); return ORC_ENOMEM; }
+    rc = selective_push(g, u, alpha, 0.5 * eps, pib, &s.sp_iters, &s.np);
+    if (rc) { free(pib); free(pif); return rc; }
     for (int32_t x = 0; x < g->nu; ++x) {
-        if (beta) beta[x] = pif[x] + w.pib[x];
+        if (beta) beta[x] = pif[x] + pib[x];
         if (pi_f_out) pi_f_out[x] = pif[x];
-        if (pi_b_out) pi_b_out[x] = w.pib[x];
+        if (pi_b_out) pi_b_out[x] = pib[x];
     }
     if (st) *st = s;
-    work_free(&w);
+    free(pib);
     free(pif);
     return ORC_OK;
 }
@@ -917,6 +947,175 @@ int orc_pisp_many(const orc_graph* g, int32_t n, const int32_t* src, double alph
         int r = orc_pisp(g, src[i], alpha, eps, beta ? beta + (size_t)i * (size_t)g->nu : NULL, NULL, NULL,
                          st ? st + i : NULL);
         if (r != ORC_OK) rc = r;
+    }
+    (void)nthreads;
+    return rc;
+}
+
+/* ---------------------------------------------------------------------------
+ * MCSP, the other baseline of Sec. 3.3 (Baselines and Challenges): pi(u, .)
+ * by MonteCarlo, random walks with restart whose steps draw neighbours from
+ * Walker alias tables (the structures Sec. 3.3 names), with eps_f = eps/2 and
+ * n_r = 2 (1 + eps_f/3) ln(|U|/p_f) / eps_f^2 walks (the count behind Eq. (mc),
+ * rounded up); plus pi(., u) by SelectivePush (Algorithm 2) with
+ * eps_b = eps/2; beta' = pi_f + pi_b.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011), a
+ * counter-based generator, so that any implementation of its definition draws
+ * the same walks. Walk w from source u takes, at step s, the eight 32-bit
+ * numbers of the counters (w, u, 2s, TAG) and (w, u, 2s + 1, TAG) under the
+ * key (seed low, seed high): r0 decides the stop (stop iff r0 < alpha 2^32),
+ * r1, r2 draw the U->V step and r3, r4 the V->U step (slot = (r d) >> 32 of a
+ * row with d entries; keep the slot iff r' 2^-32 < prob[slot], else take its
+ * alias).
+ * ------------------------------------------------------------------------- */
+#define ORC_MC_TAG 0x4D435350u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }     /* key schedule (Weyl sequence) */
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1, n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Vose's construction of Walker's alias table for each row of a CSR: row r
+ * with d entries of weights w and sum ws gets prob[e] and alias[e] (a slot of
+ * the same row) with, for every slot j,
+ *   (prob[j] + sum over slots i with alias[i] = j of (1 - prob[i])) / d = w_j / ws. */
+static int alias_rows(int32_t n, const int64_t* rp, const double* w, const double* ws, double* prob, int32_t* alias) {
+    int64_t maxd = 0;
+    for (int32_t r = 0; r < n; ++r) if (rp[r + 1] - rp[r] > maxd) maxd = rp[r + 1] - rp[r];
+    double* q = (double*)malloc(sizeof(double) * (size_t)(maxd > 0 ? maxd : 1));
+    int32_t* sm = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxd > 0 ? maxd : 1));
+    int32_t* lg = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxd > 0 ? maxd : 1));
+    if (!q || !sm || !lg) { free(q); free(sm); free(lg); return ORC_ENOMEM; }
+    for (int32_t r = 0; r < n; ++r) {
+        const int64_t b = rp[r];
+        const int32_t d = (int32_t)(rp[r + 1] - b);
+        if (d == 0) continue;
+        int32_t ns = 0, nl = 0;
+        for (int32_t j = 0; j < d; ++j) {
+            q[j] = w[b + j] * (double)d / ws[r];
+            if (q[j] < 1.0) sm[ns++] = j; else lg[nl++] = j;
+        }
+        while (ns > 0 && nl > 0) {
+            const int32_t a = sm[--ns], l = lg[--nl];
+            prob[b + a] = q[a];
+            alias[b + a] = l;
+            q[l] = (q[l] + q[a]) - 1.0;
+            if (q[l] < 1.0) sm[ns++] = l; else lg[nl++] = l;
+        }
+        while (nl > 0) { const int32_t l = lg[--nl]; prob[b + l] = 1.0; alias[b + l] = l; }
+        while (ns > 0) { const int32_t a = sm[--ns]; prob[b + a] = 1.0; alias[b + a] = a; }
+    }
+    free(q); free(sm); free(lg);
+    return ORC_OK;
+}
+
+/* side 0: rows of U (entries as in rp_u/ci_u), side 1: rows of V */
+int orc_alias_tables(const orc_graph* g, int32_t side, double* prob, int32_t* alias) {
+    return side == 0 ? alias_rows(g->nu, g->rp_u, g->w_u, g->ws_u, prob, alias)
+                     : alias_rows(g->nv, g->rp_v, g->w_v, g->ws_v, prob, alias);
+}
+
+/* Walks of MonteCarlo: n_r = 2 (1 + eps_f/3) ln(|U|/p_f) / eps_f^2, rounded up. */
+int64_t orc_mc_walks(int32_t nu, double eps_f, double p_f) {
+    return (int64_t)ceil(2.0 * (1.0 + eps_f / 3.0) * log((double)nu / p_f) / (eps_f * eps_f));
+}
+
+static int32_t alias_draw_row(const int64_t* rp, const int32_t* ci, const double* prob, const int32_t* alias,
+                              int32_t r, uint32_t rs, uint32_t rc) {
+    const int64_t b = rp[r];
+    const uint64_t d = (uint64_t)(rp[r + 1] - b);
+    const int64_t slot = (int64_t)(((uint64_t)rs * d) >> 32);
+    const int64_t pick = (double)rc * 0x1.0p-32 < prob[b + slot] ? slot : (int64_t)alias[b + slot];
+    return ci[b + pick];
+}
+
+/* counts[x] = number of the n_r walks from u that end at x (walks numbered 0..n_r-1) */
+int orc_mc_counts(const orc_graph* g, int32_t u, double alpha, int64_t n_r, uint64_t seed, int64_t* counts,
+                  double* steps_out) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    if (g->ws_u[u] == 0.0) return ORC_EISOLATED;
+    if (n_r > 0xFFFFFFFFll) return ORC_EINVAL;
+    double* pu = (double*)malloc(sizeof(double) * (size_t)(g->ne > 0 ? g->ne : 1));
+    double* pv = (double*)malloc(sizeof(double) * (size_t)(g->ne > 0 ? g->ne : 1));
+    int32_t* au = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g->ne > 0 ? g->ne : 1));
+    int32_t* av = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g->ne > 0 ? g->ne : 1));
+    if (!pu || !pv || !au || !av) { free(pu); free(pv); free(au); free(av); return ORC_ENOMEM; }
+    if (orc_alias_tables(g, 0, pu, au) || orc_alias_tables(g, 1, pv, av)) {
+        free(pu); free(pv); free(au); free(av); return ORC_ENOMEM;
+    }
+    for (int32_t x = 0; x < g->nu; ++x) counts[x] = 0;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const double stop_thr = alpha * 4294967296.0;
+    double steps = 0.0;
+    for (int64_t wk = 0; wk < n_r; ++wk) {
+        int32_t x = u;
+        for (uint32_t st = 0;; ++st) {
+            uint32_t c[4] = {(uint32_t)wk, (uint32_t)u, 2u * st, ORC_MC_TAG}, a[4], b[4];
+            orc_philox4x32_10(c, key, a);
+            c[2] = 2u * st + 1u;
+            orc_philox4x32_10(c, key, b);
+            if ((double)a[0] < stop_thr) break;                                  /* the walk stops at x */
+            const int32_t v = alias_draw_row(g->rp_u, g->ci_u, pu, au, x, a[1], a[2]);   /* U -> V */
+            x = alias_draw_row(g->rp_v, g->ci_v, pv, av, v, a[3], b[0]);                 /* V -> U */
+            steps += 1.0;
+        }
+        counts[x] += 1;
+    }
+    if (steps_out) *steps_out = steps;
+    free(pu); free(pv); free(au); free(av);
+    return ORC_OK;
+}
+
+/* MCSP: beta' = counts / n_r + pi_b (SelectivePush at eps/2); pi_b_out and
+ * counts_out are optional. */
+int orc_mcsp(const orc_graph* g, int32_t u, double alpha, double eps, double p_f, uint64_t seed, double* beta,
+             int64_t* counts_out, double* pi_b_out, int64_t* n_r_out) {
+    if (u < 0 || u >= g->nu) return ORC_ERANGE;
+    if (!(alpha > 0.0 && alpha < 1.0) || !(eps > 0.0) || !(p_f > 0.0 && p_f < 1.0)) return ORC_EINVAL;
+    if (g->ws_u[u] == 0.0) return ORC_EISOLATED;
+    const int64_t n_r = orc_mc_walks(g->nu, 0.5 * eps, p_f);
+    int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)g->nu);
+    double* pib = (double*)malloc(sizeof(double) * (size_t)g->nu);
+    if (!cnt || !pib) { free(cnt); free(pib); return ORC_ENOMEM; }
+    int rc = orc_mc_counts(g, u, alpha, n_r, seed, cnt, NULL);
+    int32_t it = 0;
+    double np = 0.0;
+    if (rc == ORC_OK) rc = selective_push(g, u, alpha, 0.5 * eps, pib, &it, &np);
+    if (rc == ORC_OK) {
+        for (int32_t x = 0; x < g->nu; ++x) {
+            if (beta) beta[x] = (double)cnt[x] / (double)n_r + pib[x];
+            if (counts_out) counts_out[x] = cnt[x];
+            if (pi_b_out) pi_b_out[x] = pib[x];
+        }
+        if (n_r_out) *n_r_out = n_r;
+    }
+    free(cnt); free(pib);
+    return rc;
+}
+
+/* A bounded sample of the CPU baseline: each source runs Algorithm 5 as
+ * orc_approx_bhpp does, stopped after max_iters push iterations; work[i]
+ * receives the edges its query touched. The rate of edge visits per second
+ * scales the oracle's speed to whole queries. */
+int orc_approx_bhpp_sample(const orc_graph* g, int32_t n, const int32_t* src, double alpha, double eps,
+                           double eps_b, double lambda, int32_t max_iters, double* work, int32_t nthreads) {
+    int rc = ORC_OK;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
+    for (int32_t i = 0; i < n; ++i) {
+        work[i] = 0.0;
+        int r = approx_bhpp_core(g, src[i], alpha, eps, eps_b, lambda, NULL, NULL, NULL, NULL, NULL, NULL,
+                                 max_iters, work + i);
+        if (r != ORC_OK && r != ORC_ENOCONV) rc = r;
     }
     (void)nthreads;
     return rc;

@@ -25,16 +25,18 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "node id out of range", -3: "sour
           -7: "not supported", -8: "step limit reached"}
 
 DTYPE_F32, DTYPE_F64 = 0, 1
-BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER, BUILD_DENSE_ONLY, BUILD_FIXED_WIDTH = 1, 2, 4, 8
+BUILD_KEEP_EXTERNAL, BUILD_NO_REORDER, BUILD_DENSE_ONLY, BUILD_FIXED_WIDTH, BUILD_MCSP = 1, 2, 4, 8, 16
 
 # names exported by include/bhpp.h
 EXPORTED = ["bhpp_build_graph", "bhpp_query", "bhpp_query_batch", "bhpp_topk", "bhpp_topk_noalloc", "bhpp_graph_info",
             "bhpp_graph_export", "bhpp_profile_enable", "bhpp_profile_read", "bhpp_profile_sweeps", "bhpp_autotune",
-            "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_server_create", "bhpp_server_submit",
+            "bhpp_set_launch_config", "bhpp_get_launch_config", "bhpp_set_schedule", "bhpp_get_schedule", "bhpp_server_create", "bhpp_server_submit",
             "bhpp_server_poll", "bhpp_server_info", "bhpp_server_destroy", "bhpp_model_create", "bhpp_model_params",
-            "bhpp_model_features", "bhpp_model_loss_grad", "bhpp_model_train", "bhpp_model_embed", "bhpp_model_free",
+            "bhpp_model_features", "bhpp_model_loss_grad", "bhpp_model_train", "bhpp_model_embed", "bhpp_model_predict",
+            "bhpp_model_free",
             "bhpp_query_batch_warm", "bhpp_query_batch_start", "bhpp_gemm_bf16", "bhpp_set_eps_b_ratio",
-            "bhpp_tune_eps_b", "bhpp_query_hpp", "bhpp_query_batch_pisp", "bhpp_free_graph", "bhpp_status_string"]
+            "bhpp_tune_eps_b", "bhpp_query_hpp", "bhpp_query_batch_pisp", "bhpp_query_batch_mcsp", "bhpp_free_graph",
+            "bhpp_status_string"]
 MODEL_PARAMS = 230656
 MODEL_FEATURES = 64
 
@@ -54,7 +56,7 @@ class QueryStats(ctypes.Structure):
     _fields_ = [("ss_sel_iters", ctypes.c_int32), ("ss_seq_iters", ctypes.c_int32),
                 ("pi_sel_iters", ctypes.c_int32), ("t", ctypes.c_int32),
                 ("ss_switched", ctypes.c_int32), ("pi_returned", ctypes.c_int32),
-                ("steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("steps", ctypes.c_int32), ("sparse_sweeps", ctypes.c_int32),
                 ("np_ss", ctypes.c_double), ("np_pi", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("sum_r_ss", ctypes.c_double), ("sum_rf", ctypes.c_double),
                 ("visits_u", ctypes.c_double), ("visits_v", ctypes.c_double)]
@@ -118,6 +120,8 @@ def load_library():
     L.bhpp_query_batch.argtypes = [P, I32, P, P, D, D, P, I32, I32, P, P, P, P]
     L.bhpp_query_batch_pisp.restype = I32
     L.bhpp_query_batch_pisp.argtypes = [P, I32, P, P, D, D, P, I32, I32, P, P, P, P]
+    L.bhpp_query_batch_mcsp.restype = I32
+    L.bhpp_query_batch_mcsp.argtypes = [P, I32, P, D, D, D, ctypes.c_uint64, P, I32, I32, P, P, P, P, P]
     L.bhpp_topk.restype = I32
     L.bhpp_topk.argtypes = [P, I32, I32, I32, P, I32, P, P, P]
     L.bhpp_topk_noalloc.restype = I32
@@ -138,6 +142,10 @@ def load_library():
     L.bhpp_set_launch_config.argtypes = [P, P]
     L.bhpp_get_launch_config.restype = I32
     L.bhpp_get_launch_config.argtypes = [P, P]
+    L.bhpp_set_schedule.restype = I32
+    L.bhpp_set_schedule.argtypes = [P, P]
+    L.bhpp_get_schedule.restype = I32
+    L.bhpp_get_schedule.argtypes = [P, P]
     L.bhpp_server_create.restype = I32
     L.bhpp_server_create.argtypes = [P, P, I32, D, D, I32, I32, ctypes.POINTER(P)]
     L.bhpp_server_submit.restype = I32
@@ -156,6 +164,8 @@ def load_library():
     L.bhpp_model_train.argtypes = [P, I32, P, I32, P, P, I32, I32, I32, D, ctypes.c_uint64, P]
     L.bhpp_model_embed.restype = I32
     L.bhpp_model_embed.argtypes = [P]
+    L.bhpp_model_predict.restype = I32
+    L.bhpp_model_predict.argtypes = [P, I32, P, P, P]
     L.bhpp_model_free.restype = None
     L.bhpp_model_free.argtypes = [P]
     L.bhpp_query_batch_warm.restype = I32
@@ -211,7 +221,7 @@ class Graph:
     """A built bipartite graph resident in HBM (bhpp_build_graph)."""
 
     def __init__(self, n_u, n_v, edge_u, edge_v, edge_w, alpha=0.15, dtype="f32", tau=-1,
-                 keep_external=False, reorder=True, sparse=True, fixed_width=False):
+                 keep_external=False, reorder=True, sparse=True, fixed_width=False, mcsp=False):
         torch = _torch()
         L = load_library()
         self.dtype = dtype
@@ -220,7 +230,8 @@ class Graph:
         ev = _dev(edge_v, torch.int32)
         ew = _dev(edge_w, self._tdtype)
         flags = ((BUILD_KEEP_EXTERNAL if keep_external else 0) | (0 if reorder else BUILD_NO_REORDER) |
-                 (0 if sparse else BUILD_DENSE_ONLY) | (BUILD_FIXED_WIDTH if fixed_width else 0))
+                 (0 if sparse else BUILD_DENSE_ONLY) | (BUILD_FIXED_WIDTH if fixed_width else 0) |
+                 (BUILD_MCSP if mcsp else 0))
         opts = GraphOpts(alpha, tau, DTYPE_F64 if dtype == "f64" else DTYPE_F32, flags)
         h = ctypes.c_void_p()
         rc = L.bhpp_build_graph(n_u, n_v, eu.numel(), eu.data_ptr(), ev.data_ptr(), ew.data_ptr(),
@@ -323,6 +334,27 @@ class Graph:
         return dict(scores=sc, ids=ids, vals=vals, stats=[st[i].as_dict() for i in range(n)] if stats else None,
                     warm=warm)
 
+    def query_mcsp(self, sources, eps, alpha=None, p_f=1e-6, seed=0, k=0, exclude_self=True, scores=True,
+                   stats=True):
+        """The MCSP baseline (bhpp_query_batch_mcsp; the graph needs mcsp=True).
+        Returns dict(scores, ids, vals, stats, walks)."""
+        torch = _torch()
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        n = src.size
+        sc = torch.empty((n, self.n_u), dtype=self._tdtype, device="cuda") if scores else None
+        ids = torch.empty((n, k), dtype=torch.int32, device="cuda") if k else None
+        vals = torch.empty((n, k), dtype=self._tdtype, device="cuda") if k else None
+        st = (QueryStats * max(1, n))()
+        walks = ctypes.c_int64()
+        rc = load_library().bhpp_query_batch_mcsp(
+            self._h, n, src.ctypes.data, float(eps), alpha or self.alpha, float(p_f), ctypes.c_uint64(seed),
+            sc.data_ptr() if sc is not None else None, int(k), 1 if exclude_self else 0,
+            ids.data_ptr() if ids is not None else None, vals.data_ptr() if vals is not None else None,
+            ctypes.cast(st, ctypes.c_void_p) if stats else None, ctypes.byref(walks), _stream())
+        _check(rc, "bhpp_query_batch_mcsp")
+        return dict(scores=sc, ids=ids, vals=vals, stats=[st[i].as_dict() for i in range(n)] if stats else None,
+                    walks=int(walks.value))
+
     def autotune(self, cache_path=None):
         """Pick the fastest launch setting for this graph (bhpp_autotune) and
         remember it in a JSON cache keyed by the graph's shape, so later builds
@@ -356,6 +388,16 @@ class Graph:
     def set_launch_config(self, cfg):
         arr = (ctypes.c_int32 * 4)(cfg["tile_edges"], cfg["inflight"], cfg["nt_stream"], cfg["graphs"])
         _check(load_library().bhpp_set_launch_config(self._h, arr), "bhpp_set_launch_config")
+
+    def schedule(self):
+        """(sweeps per chunk, asynchronous admission) of query batches."""
+        a = (ctypes.c_int32 * 2)()
+        _check(load_library().bhpp_get_schedule(self._h, a), "bhpp_get_schedule")
+        return dict(chunk_sweeps=a[0], async_admission=a[1])
+
+    def set_schedule(self, chunk_sweeps, async_admission=True):
+        a = (ctypes.c_int32 * 2)(int(chunk_sweeps), 1 if async_admission else 0)
+        _check(load_library().bhpp_set_schedule(self._h, a), "bhpp_set_schedule")
 
     def launch_config(self):
         cfg = (ctypes.c_int32 * 4)()
@@ -526,6 +568,16 @@ class Model:
                                                float(lr), ctypes.c_uint64(seed), losses.ctypes.data),
                "bhpp_model_train")
         return losses[:steps]
+
+    def predict(self, sources):
+        """The model's start for each source (bhpp_model_predict): [n, n_u]
+        device FP32 estimates of pi(u, x)."""
+        torch = _torch()
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32))
+        out = torch.empty((src.size, self.graph.n_u), dtype=torch.float32, device="cuda")
+        _check(load_library().bhpp_model_predict(self._h, src.size, src.ctypes.data, out.data_ptr(), _stream()),
+               "bhpp_model_predict")
+        return out
 
     def embed(self):
         _check(load_library().bhpp_model_embed(self._h), "bhpp_model_embed")

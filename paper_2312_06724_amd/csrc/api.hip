@@ -168,6 +168,77 @@ bhpp_status bhpp_query_batch_pisp(bhpp_graph* h, int32_t n_src, const int32_t* s
                             topk_ids, topk_vals, stats, nullptr, hip_stream);
 }
 
+bhpp_status bhpp_query_batch_mcsp(bhpp_graph* h, int32_t n_src, const int32_t* sources, double eps, double alpha,
+                                  double p_f, uint64_t seed, void* scores_out, int32_t k, int32_t exclude_self,
+                                  int32_t* topk_ids, void* topk_vals, bhpp_query_stats* stats, int64_t* walks_out,
+                                  void* hip_stream) {
+    if (!h || !h->g) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    if (!g->mc_prob_u) return BHPP_NOT_SUPPORTED;
+    if (!valid_eps(eps) || !(p_f > 0.0 && p_f < 1.0)) return BHPP_INVALID_ARG;
+    if (n_src < 0 || (n_src > 0 && !sources) || !valid_alpha(alpha)) return BHPP_INVALID_ARG;
+    if (n_src == 0) return BHPP_OK;
+    if (k < 0 || k > bhpp::kTopkTmpK || k > g->nu - (exclude_self ? 1 : 0)) return BHPP_INVALID_ARG;
+    if (k > 0 && (!topk_ids || !topk_vals)) return BHPP_INVALID_ARG;
+    for (int32_t i = 0; i < n_src; ++i) {
+        if (sources[i] < 0 || sources[i] >= g->nu) return BHPP_OUT_OF_RANGE;
+        if (!(g->h_ws_u[sources[i]] > 0.0)) return BHPP_ISOLATED_SOURCE;
+    }
+    const int64_t n_r = bhpp::mc_walk_count(g->nu, 0.5 * eps, p_f);
+    if (n_r > 0xFFFFFFFFll) return BHPP_NOT_SUPPORTED;   // walks are numbered with 32 bits
+    if (walks_out) *walks_out = n_r;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        hipStream_t s = stream_of(hip_stream);
+        double lam = 0.0;
+        bhpp_status rc = lambda_for(g, alpha, s, &lam);
+        if (rc) return sticky(g, rc);
+        const size_t rows_bytes = (size_t)n_src * g->nu * g->elem;
+        void* rows = scores_out;
+        uint32_t* counts = nullptr;
+        if (!rows && hipMalloc(&rows, rows_bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return BHPP_OUT_OF_MEMORY;
+        }
+        if (hipMalloc((void**)&counts, 4 * (size_t)n_src * g->nu) != hipSuccess) {
+            (void)hipGetLastError();
+            if (!scores_out) hipFree(rows);
+            return BHPP_OUT_OF_MEMORY;
+        }
+        std::vector<double> e((size_t)n_src, eps);
+        // backward part: SelectivePush with eps/2 (control mode 4) into the rows
+        rc = bhpp::run_queries(g, nullptr, nullptr, nullptr, 4, n_src, sources, e.data(), alpha, lam, rows, 0, 0,
+                               nullptr, nullptr, stats, s);
+        // forward part: the walks, then beta' = counts / n_r + pi_b
+        if (rc == BHPP_OK) rc = bhpp::mcsp_counts(g, n_src, sources, alpha, n_r, seed, counts, s);
+        if (rc == BHPP_OK) rc = bhpp::mcsp_combine(g, rows, counts, n_src, n_r, s);
+        if (rc == BHPP_OK && k > 0) {
+            std::vector<int32_t> ex((size_t)n_src, -1);
+            if (exclude_self)
+                for (int32_t i = 0; i < n_src; ++i) ex[i] = sources[i];
+            int32_t* d_ex = nullptr;
+            if (hipMalloc((void**)&d_ex, 4 * (size_t)n_src) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = BHPP_OUT_OF_MEMORY;
+            } else {
+                if (hipMemcpyAsync(d_ex, ex.data(), 4 * (size_t)n_src, hipMemcpyHostToDevice, s) != hipSuccess)
+                    rc = BHPP_DEVICE_ERROR;
+                if (rc == BHPP_OK)
+                    rc = bhpp::topk_rows(rows, n_src, g->nu, k, d_ex, g->dtype, topk_ids, topk_vals, s);
+                if (hipStreamSynchronize(s) != hipSuccess && rc == BHPP_OK) rc = BHPP_DEVICE_ERROR;
+                hipFree(d_ex);
+            }
+        }
+        if (rc == BHPP_OK && hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+        hipFree(counts);
+        if (!scores_out) hipFree(rows);
+        return sticky(g, rc);
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
 bhpp_status bhpp_query_hpp(bhpp_graph* h, int32_t n_src, const int32_t* sources, const double* eps, double alpha,
                            double eps_all, int32_t direction, void* scores_out, bhpp_query_stats* stats,
                            void* hip_stream) {
@@ -329,6 +400,24 @@ bhpp_status bhpp_get_launch_config(const bhpp_graph* h, int32_t config_out[4]) {
     config_out[1] = g->inflight;
     config_out[2] = g->nt_stream;
     config_out[3] = g->use_graphs;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_set_schedule(bhpp_graph* h, const int32_t sched[2]) {
+    if (!h || !h->g || !sched || sched[0] < 1 || sched[0] > 8) return BHPP_INVALID_ARG;
+    Graph* g = h->g;
+    std::lock_guard<std::mutex> lock(g->mu);
+    if (g->n_servers > 0) return BHPP_INVALID_ARG;
+    if (sched[0] != g->chunk_sweeps) bhpp::drop_chunk_graphs(g);
+    g->chunk_sweeps = sched[0];
+    g->async_sched = sched[1] ? 1 : 0;
+    return BHPP_OK;
+}
+
+bhpp_status bhpp_get_schedule(const bhpp_graph* h, int32_t sched_out[2]) {
+    if (!h || !h->g || !sched_out) return BHPP_INVALID_ARG;
+    sched_out[0] = h->g->chunk_sweeps;
+    sched_out[1] = h->g->async_sched;
     return BHPP_OK;
 }
 
@@ -499,6 +588,24 @@ bhpp_status bhpp_model_embed(bhpp_model* m) {
     try {
         std::lock_guard<std::mutex> lock(g->mu);
         return sticky(g, bhpp::model_embed(m->m));
+    } catch (...) {
+        return BHPP_OUT_OF_MEMORY;
+    }
+}
+
+bhpp_status bhpp_model_predict(bhpp_model* m, int32_t n_src, const int32_t* sources, float* out, void* hip_stream) {
+    if (!m || !m->m || n_src < 0 || (n_src > 0 && (!sources || !out))) return BHPP_INVALID_ARG;
+    Graph* g = m->h->g;
+    if (g->sticky_error) return BHPP_DEVICE_ERROR;
+    if (!bhpp::model_ready(m->m)) return BHPP_INVALID_ARG;
+    for (int32_t i = 0; i < n_src; ++i) {
+        if (sources[i] < 0 || sources[i] >= g->nu) return BHPP_OUT_OF_RANGE;
+        if (!(g->h_ws_u[sources[i]] > 0.0)) return BHPP_ISOLATED_SOURCE;
+    }
+    if (n_src == 0) return BHPP_OK;
+    try {
+        std::lock_guard<std::mutex> lock(g->mu);
+        return sticky(g, bhpp::model_predict_ext(m->m, n_src, sources, out, stream_of(hip_stream)));
     } catch (...) {
         return BHPP_OUT_OF_MEMORY;
     }

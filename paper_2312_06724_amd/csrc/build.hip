@@ -247,6 +247,8 @@ void free_tiles(TileSet* ts) {
 void free_graph(Graph* g) {
     if (!g) return;
     void* ptrs[] = {g->rp_u, g->ci_u, g->w_u, g->rp_v, g->ci_v, g->w_v, g->iw_v, g->inv_ws_u_f, g->inv_ws_v_f, g->deg_u, g->end_bits_u, g->end_bits_v,
+                    g->mc_rp_u, g->mc_rp_v, g->mc_prob_u, g->mc_prob_v, g->mc_keep_u, g->mc_keep_v, g->mc_alias_u,
+                    g->mc_alias_v,
                     g->inv_ws_u_d, g->inv_ws_v_d, g->perm_u, g->iperm_u, g->iperm_v, g->x_rp_u, g->x_ci_u, g->x_w_u,
                     g->x_rp_v, g->x_ci_v, g->x_w_v, g->x_ws_u, g->x_ws_v};
     for (void* p : ptrs) hipFree(p);
@@ -497,6 +499,11 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
         hipLaunchKernelGGL(k_cast<WT>, grid_for(nv), dim3(256), 0, s, (int64_t)nv, ws_v, (WT*)g->x_ws_v);
         BHPP_HIP(hipGetLastError());
     }
+    // 7. MCSP's alias tables from the merged FP64 weights in caller ids
+    if (opts.flags & BHPP_BUILD_MCSP) {
+        rc = mcsp_build_tables(g, xrp_u, xci_u, xw_u, ws_u, xrp_v, xci_v, xw_v, ws_v, s);
+        if (rc) return rc;
+    }
 
     // 7. host-side summaries and tiles
     g->h_ws_u.resize(nu);
@@ -575,7 +582,8 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
                         const void* ew, const bhpp_graph_opts& opts, hipStream_t s, Graph** out) {
     Graph* g = new (std::nothrow) Graph();
     if (!g) return BHPP_OUT_OF_MEMORY;
-    // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=)
+    // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=,
+    // hub=, chunk=, async=)
     if (const char* e = getenv("BHPP_TUNE")) {
         int v;
         const char* q;
@@ -587,6 +595,9 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "sparse=")) && sscanf(q, "sparse=%d", &v) == 1) g->sparse_steps = v ? 1 : 0;
         if ((q = strstr(e, "narrow=")) && sscanf(q, "narrow=%d", &v) == 1) g->narrow = v ? 1 : 0;
         if ((q = strstr(e, "fuse=")) && sscanf(q, "fuse=%d", &v) == 1) g->fuse_select = v ? 1 : 0;
+        if ((q = strstr(e, "hub=")) && sscanf(q, "hub=%d", &v) == 1) g->hub_lds = v ? 1 : 0;
+        if ((q = strstr(e, "chunk=")) && sscanf(q, "chunk=%d", &v) == 1 && v >= 1 && v <= 8) g->chunk_sweeps = v;
+        if ((q = strstr(e, "async=")) && sscanf(q, "async=%d", &v) == 1) g->async_sched = v ? 1 : 0;
     }
     if (opts.flags & BHPP_BUILD_DENSE_ONLY) g->sparse_steps = 0;
     if (opts.flags & BHPP_BUILD_FIXED_WIDTH) g->narrow = 0;

@@ -88,6 +88,7 @@ struct ColState {
     int32_t ss_sel_iters, ss_seq_iters, pi_sel_iters, t, ss_switched, pi_returned;
     double np_ss, np_pi, sum_r_ss, sum_rf;
     double visits_u, visits_v;   // edge visits of all sweeps: pushed U nodes' edges, active V nodes' edges
+    int32_t sparse_sweeps;       // sweeps whose pushed U nodes have fewer than |E|/16 edges
     // scheduling: a column reused for a new query keeps the old query's Y and
     // ACC until its first sweep, which reads them as y = e_src and ACC = 0
     int32_t fresh;
@@ -99,7 +100,8 @@ struct ColState {
     int32_t snap;
     int32_t fell_back;   // a warm start was no better than the cold start: ran cold
     int32_t target;      // 0: beta (Algorithm 5); 1: pi(u, .) (PI-Push alone); 2: pi(., u) (SS-Push alone);
-                         // 3: beta by PISP (SelectivePush, then PowerIteration from e_u)
+                         // 3: beta by PISP (SelectivePush, then PowerIteration from e_u);
+                         // 4: pi(., u) by SelectivePush alone (MCSP's backward part)
     int32_t reset_y;     // the next sweep reads y = e_src (PISP's forward part) but keeps ACC
     double res_l1;       // sum_x |r_f(x)| of the warm start
     double res_max;      // max_x |r(x)|
@@ -124,6 +126,7 @@ struct Workspace {
     int32_t* ids_tmp = nullptr;  // [cols][kTopkTmpK] top-k scratch
     void* vals_tmp = nullptr;
     int32_t* ex_tmp = nullptr;   // [3][64]: exported columns, their excluded ids, a narrowing map
+    ColState* adm = nullptr;     // [64] states of queries being admitted (asynchronous batches)
     size_t bytes = 0;
     // warm starts: an FP64 block that applies the two-hop operator to the
     // predictions of newly admitted queries (allocated on demand)
@@ -169,6 +172,10 @@ struct Graph {
     int32_t* iperm_u = nullptr;  // internal -> external
     int32_t* iperm_v = nullptr;  // internal V id -> external
     TileSet tiles_u, tiles_v;
+    // MCSP's alias tables (BHPP_BUILD_MCSP): rows of W and of W^T in caller ids
+    int64_t *mc_rp_u = nullptr, *mc_rp_v = nullptr;
+    double *mc_prob_u = nullptr, *mc_prob_v = nullptr;
+    int32_t *mc_keep_u = nullptr, *mc_keep_v = nullptr, *mc_alias_u = nullptr, *mc_alias_v = nullptr;
     // external-order copies (BHPP_BUILD_KEEP_EXTERNAL)
     int64_t* x_rp_u = nullptr; int32_t* x_ci_u = nullptr; void* x_w_u = nullptr;
     int64_t* x_rp_v = nullptr; int32_t* x_ci_v = nullptr; void* x_w_v = nullptr;
@@ -192,6 +199,9 @@ struct Graph {
     int fuse_select = 1;             // 64-column blocks: gather A applies the push rule (no select pass)
     int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
     int narrow = 1;                  // batches narrow their block as sources finish
+    int hub_lds = 1;                 // one-source gathers read the hub slice of their vector from LDS
+    int chunk_sweeps = 8;            // sweeps per launched chunk (captured graph), 1..8
+    int async_sched = 1;             // queue-fed 64-column batches admit without draining the stream
     double eps_b_paper = 0.5;        // eps_b / eps of Eq. (epsilon-b); info.eps_b_ratio is the one in use
     bool sticky_error = false;
     int n_servers = 0;               // live servers hold captured graphs of the tiles
@@ -233,6 +243,14 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
                         hipStream_t s, Graph** out);
 void free_graph(Graph* g);
 bhpp_status compute_lambda(Graph* g, double alpha, int32_t tau, hipStream_t s, double* lambda_out);
+// MCSP (mcsp.hip)
+int64_t mc_walk_count(int32_t nu, double eps_f, double p_f);
+bhpp_status mcsp_build_tables(Graph* g, const int64_t* xrp_u, const int32_t* xci_u, const double* xw_u,
+                              const double* ws_u, const int64_t* xrp_v, const int32_t* xci_v, const double* xw_v,
+                              const double* ws_v, hipStream_t s);
+bhpp_status mcsp_counts(Graph* g, int32_t n, const int32_t* src_ext, double alpha, int64_t n_r, uint64_t seed,
+                        uint32_t* counts, hipStream_t s);
+bhpp_status mcsp_combine(Graph* g, void* rows, const uint32_t* counts, int32_t n, int64_t n_r, hipStream_t s);
 // One sparse push step of a one-source block (frontier.hip): sparse_front
 // (frontier, take, U->V scatter into w.fQ), then the caller's dense U-side
 // gather of w.fQ into G, then sparse_finish (y += (1-alpha) G, reductions).
@@ -282,12 +300,14 @@ bhpp_status model_train(Model* m, int n_src, const int32_t* src, int M, const in
 bhpp_status model_embed(Model* m);
 bool model_ready(const Model* m);
 bhpp_status model_predict(Model* m, const int32_t* src_rows_host, int n, int cols, float* out, hipStream_t s);
+bhpp_status model_predict_ext(Model* m, int n, const int32_t* src_ext, float* out, hipStream_t s);
 bhpp_status gemm_test(int M, int N, int K, const uint16_t* A, int trans_a, const uint16_t* B, int trans_b, float* C,
                       hipStream_t s);
 bhpp_status set_launch_config(Graph* g, const int* cfg);
 bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts);
 void free_workspace(Workspace& w);
 bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg);
+void drop_chunk_graphs(Graph* g);
 void free_tiles(TileSet* ts);
 
 inline int next_pow2(int x) {

@@ -852,6 +852,41 @@ bhpp_status model_predict(Model* m, const int32_t* src_rows_host, int n, int col
     return BHPP_OK;
 }
 
+// Predictions in caller ids: out[j][x] = tmp[perm_u[x]][j] for j < m.
+__global__ void k_pred_rows(const float* tmp, int cols, int m, const int32_t* perm, int32_t nu, float* out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)m * nu) return;
+    const int j = (int)(i / nu);
+    const int32_t x = (int32_t)(i % nu);
+    out[i] = tmp[(size_t)perm[x] * cols + j];
+}
+
+// The start the model gives each source (caller ids): out[i][x] = p_hat(src_i, x).
+bhpp_status model_predict_ext(Model* m, int n, const int32_t* src_ext, float* out, hipStream_t s) {
+    if (!m->emb_valid) return BHPP_INVALID_ARG;
+    Graph* g = m->g;
+    float* tmp = nullptr;
+    if (hipMalloc((void**)&tmp, (size_t)g->nu * kMaxCols * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        return BHPP_OUT_OF_MEMORY;
+    }
+    bhpp_status rc = BHPP_OK;
+    for (int i0 = 0; i0 < n && rc == BHPP_OK; i0 += kMaxCols) {
+        const int c = n - i0 < kMaxCols ? n - i0 : kMaxCols;
+        std::vector<int32_t> rows(c);
+        for (int j = 0; j < c; ++j) rows[j] = g->h_perm_u[src_ext[i0 + j]];
+        rc = model_predict(m, rows.data(), c, kMaxCols, tmp, s);
+        if (rc) break;
+        const size_t tot = (size_t)c * g->nu;
+        hipLaunchKernelGGL(k_pred_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, tmp, kMaxCols, c,
+                           g->perm_u, g->nu, out + (size_t)i0 * g->nu);
+        if (hipGetLastError() != hipSuccess) rc = BHPP_DEVICE_ERROR;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == BHPP_OK) rc = BHPP_DEVICE_ERROR;
+    hipFree(tmp);
+    return rc;
+}
+
 // Raw GEMM for the layout test: C = A B with A [M][K], B [K][N] BF16 (device),
 // C FP32 [M][N]; trans_a / trans_b read A as [K][M] / B as [N][K].
 bhpp_status gemm_test(int M, int N, int K, const uint16_t* A, int trans_a, const uint16_t* B, int trans_b, float* C,

@@ -189,6 +189,11 @@ struct GatherArgs {
     const VT* Yf = nullptr;
     const VT* iwf = nullptr;     // per adjacency entry, beside ci and w
     const ColState* stf = nullptr;
+    // k_gather1: length of X and how many of its leading entries each block
+    // stages in LDS (nodes are numbered by decreasing degree, so the first
+    // entries are the hubs most adjacency entries point at); 0: none
+    int32_t n_x = 0;
+    int32_t hub = 0;
 };
 
 // Columns of a block in use: n_active[1] (0: all). A batch keeps its running
@@ -399,11 +404,20 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
 // lanes (fixed order) sums each row. The row still open at the end of a chunk
 // carries its partial sum into the next one. Tiles hold no empty rows.
 // ---------------------------------------------------------------------------
+constexpr int kHubLdsBytes = 32768;   // LDS per block for the hub slice of X (k_gather1)
+
 template <typename VT, typename WT, bool SIDE_A>
 __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) {
     constexpr int UNR = 4;
+    constexpr int HUB = kHubLdsBytes / (int)sizeof(VT);
     __shared__ double sh[kPassThreads];
+    __shared__ VT hub[HUB];
     if (*p.n_active == 0) return;
+    // the hub slice X[0, nh): one coalesced copy per block, then LDS reads
+    // instead of L2 requests for every entry that points at a hub
+    const int32_t nh = min(min(HUB, p.hub), p.n_x);
+    for (int32_t i = threadIdx.x; i < nh; i += kPassThreads) hub[i] = p.X[i];
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = wave_in_block();
     const uint64_t lt_mask = lane ? (~0ull >> (kWave - lane)) : 0ull;   // lanes below this one
@@ -440,7 +454,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather1(GatherArgs<VT, WT> p) 
                 }
             }
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) v[u] = lane < n[u] ? p.X[x[u]] : VT(0);
+            for (int u = 0; u < UNR; ++u) v[u] = lane < n[u] ? (x[u] < nh ? hub[x[u]] : p.X[x[u]]) : VT(0);
 #pragma unroll
             for (int u = 0; u < UNR; ++u) {
                 if (n[u] == 0) break;
@@ -737,7 +751,10 @@ __device__ void control_update(ColState& s, const double* R, double np_v, int32_
     // edge visits of this sweep; the U-side count is the update's push set,
     // which the V-side half read unless its rule was NONE (the last sweep of
     // PowerIteration only adds alpha y)
-    if (s.ruleA != RULE_NONE) s.visits_u += R[RED_NP] - np_v;
+    if (s.ruleA != RULE_NONE) {
+        s.visits_u += R[RED_NP] - np_v;
+        if (R[RED_NP] - np_v < s.two_e / 32.0) s.sparse_sweeps += 1;
+    }
     s.visits_v += np_v;
     const double sum_r = R[RED_SUM_R] * s.ws_src;     // sum_x |r(x)|
     const double sum_y = R[RED_SUM_Y];                // sum_x |r_f(x)|
@@ -746,10 +763,19 @@ __device__ void control_update(ColState& s, const double* R, double np_v, int32_
         case MODE_SS_SEL:
             s.np += R[RED_NP];
             s.ss_sel_iters += 1;
-            if (s.target == 3) {
+            if (s.target == 3 || s.target == 4) {
                 // SelectivePush (Algorithm 2): its loop ends when no U residue
-                // exceeds eps_b; there is no budget test
-                if (R[RED_CNT_SS] == 0.0) enter_pisp_power(s, sum_r);
+                // exceeds eps_b; there is no budget test. PISP goes on with
+                // PowerIteration; MCSP's backward part ends here (pi_b)
+                if (R[RED_CNT_SS] == 0.0) {
+                    if (s.target == 3) {
+                        enter_pisp_power(s, sum_r);
+                    } else {
+                        s.np_ss = s.np;
+                        s.sum_r_ss = sum_r;
+                        set_rules(s, MODE_FINAL, RULE_NONE, RULE_NONE, 3);
+                    }
+                }
             } else if (ss_stop) {
                 enter_pi(s, R, sum_r);
             } else if (s.np >= s.two_e * (log(1.0 / sum_r) / s.ln_inv)) {      // Eq. (bwd-np)
@@ -1105,6 +1131,8 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     A.red = b.red;
     A.n_part = G.n_part;
     A.nt_stream = g->nt_stream;
+    A.n_x = g->nu;
+    A.hub = g->hub_lds ? kHubLdsBytes / (int)sizeof(VT) : 0;
     GatherArgs<VT, WT> B = A;
     B.tiles = g->tiles_u.tiles;
     B.n_tiles = g->tiles_u.n_tiles;
@@ -1115,6 +1143,7 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     B.OUT = as<VT>(b.G);
     B.part = as<VT>(b.partB);
     B.end_bits = g->end_bits_u;
+    B.n_x = g->nv;
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto pb = [&](int kind) {
         if (prof) prof_begin(g, s, kind, launch_bytes<VT, WT>(g, COLS, kind), ev);
@@ -1182,10 +1211,9 @@ static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipS
     return BHPP_OK;
 }
 
-constexpr int kStepsPerChunk = 8;
 constexpr int kMaxSteps = 4000;   // sweeps without a finished query; a query needs O(log 1/eps)
 
-// One chunk of kStepsPerChunk sweeps. Unless the kernels are being profiled,
+// One chunk of g->chunk_sweeps sweeps. Unless the kernels are being profiled,
 // the chunk is captured once as a HIP graph (all state lives in device
 // memory, so every replay continues where the last one stopped) and replayed.
 template <int COLS, typename VT, typename WT>
@@ -1194,7 +1222,7 @@ static bhpp_status launch_chunk(Graph* g, const Block& b, const Geometry& G, hip
         if (*cache == nullptr) {
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return BHPP_DEVICE_ERROR;
             bhpp_status rc = BHPP_OK;
-            for (int i = 0; i < kStepsPerChunk && rc == BHPP_OK; ++i) rc = launch_step<COLS, VT, WT>(g, b, G, s);
+            for (int i = 0; i < g->chunk_sweeps && rc == BHPP_OK; ++i) rc = launch_step<COLS, VT, WT>(g, b, G, s);
             hipGraph_t graph = nullptr;
             const hipError_t e = hipStreamEndCapture(s, &graph);
             if (rc != BHPP_OK || e != hipSuccess || graph == nullptr) {
@@ -1212,7 +1240,7 @@ static bhpp_status launch_chunk(Graph* g, const Block& b, const Geometry& G, hip
         BHPP_HIP(hipGraphLaunch(*cache, s));
         return BHPP_OK;
     }
-    for (int i = 0; i < kStepsPerChunk; ++i) {
+    for (int i = 0; i < g->chunk_sweeps; ++i) {
         const bhpp_status rc = launch_step<COLS, VT, WT>(g, b, G, s);
         if (rc) return rc;
     }
@@ -1227,7 +1255,7 @@ static bhpp_status run_plain(Graph* g, const Block& b, hipStream_t s) {
     for (;;) {
         bhpp_status rc = launch_chunk<COLS, VT, WT>(g, b, G, s, nullptr);
         if (rc) return rc;
-        steps += kStepsPerChunk;
+        steps += g->chunk_sweeps;
         BHPP_HIP(hipMemcpyAsync(b.h_active, b.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BHPP_HIP(hipStreamSynchronize(s));
         if (b.h_active[0] == 0) return BHPP_OK;
@@ -1244,7 +1272,7 @@ static void init_state(ColState& c, double alpha, double ws_src, double eps, dou
     c.target = target;
     // Algorithm 5's split of eps; one direction alone takes the whole eps;
     // PISP halves it (Sec. 3.3)
-    c.eps_b = target == 1 ? 0.0 : target == 2 ? eps : target == 3 ? 0.5 * eps : eps * eps_b_ratio;
+    c.eps_b = target == 1 ? 0.0 : target == 2 ? eps : (target == 3 || target == 4) ? 0.5 * eps : eps * eps_b_ratio;
     c.eps_f = eps - c.eps_b;
     c.k_ss = ws_src > 0 ? c.eps_b / ws_src : 0.0;
     c.k_pi = c.eps_f / lambda;
@@ -1287,7 +1315,7 @@ static void fill_stats(const ColState& cs, bhpp_query_stats& q) {
     q.ss_switched = cs.ss_switched;
     q.pi_returned = cs.pi_returned;
     q.steps = cs.steps;
-    q.reserved = 0;
+    q.sparse_sweeps = cs.sparse_sweeps;
     q.np_ss = cs.np_ss;
     q.np_pi = cs.np_pi;
     q.gamma = cs.gamma;
@@ -1449,6 +1477,8 @@ static bhpp_status sparse_phase(Graph* g, Workspace& w, std::vector<ColState>& h
     B.n_part = G.n_part;
     B.nt_stream = g->nt_stream;
     B.red_slot = 0;
+    B.n_x = g->nv;
+    B.hub = g->hub_lds ? kHubLdsBytes / (int)sizeof(VT) : 0;
     for (int it = 0; it < kMaxSteps; ++it) {
         SparseStep io;
         io.max_work = g->ne / 16;
@@ -1538,7 +1568,7 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
     while (live > 0) {
         rc = launch_chunk<COLS, VT, WT>(g, b, G, s, cache);
         if (rc) break;
-        steps += kStepsPerChunk;
+        steps += g->chunk_sweeps;
         const int slot = chunk & 1;
         if (hipMemcpyAsync(&w.h_active[slot], w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipEventRecord(evs[slot], s) != hipSuccess) {
@@ -1660,6 +1690,250 @@ static bhpp_status run_sched(Graph* g, const WarmSource& warm, bhpp_warm_stats* 
     return rc;
 }
 
+// Admission of the next queries into freed columns: st[cols[j]] = adm[j];
+// the queries among them count as active.
+__global__ void k_admit(ColState* st, const ColState* adm, const int32_t* cols, int m, int32_t* n_active) {
+    const int j = threadIdx.x;
+    const bool act = j < m && adm[j].mode != MODE_DONE;
+    if (j < m) st[cols[j]] = adm[j];
+    const uint64_t b = __ballot(act);
+    if (j == 0 && b) atomicAdd(n_active, (int32_t)__popcll(b));
+}
+
+// A queue-fed 64-column batch that never drains the stream to admit queries.
+// After every chunk the column states are copied to a pinned host ring; the
+// host reads the copy of chunk i while chunk i+1 runs and, for the columns
+// whose query finished by chunk i, enqueues behind chunk i+1: the extraction
+// of their beta' rows, their top-k and output copies, then the admission of
+// the next queries into those columns (k_admit). A finished column is inert
+// (its rules are NONE: its ACC is rewritten with the same bits), so reading
+// it a chunk later gives the values it finished with. Packing the running
+// columns into the low half once the queue is empty drains the stream once.
+template <typename VT, typename WT>
+static bhpp_status run_sched_async(Graph* g, int target, int n, const int32_t* src_ext, const double* eps,
+                                   double alpha, double lambda, void* scores_out, int k, int exclude_self,
+                                   int32_t* ids_out, void* vals_out, bhpp_query_stats* stats, hipStream_t s) {
+    constexpr int COLS = 64;
+    constexpr int NS = 4;   // pinned slots: state copies and admission lists
+    Workspace& w = g->ws;
+    const Block b{w.Y, w.ACC, w.S, w.scores, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.h_active,
+                  w.SNAP};
+    const Geometry G = geometry(g);
+    const size_t nu = (size_t)g->nu, e = (size_t)g->elem;
+    ColState* h_snap = nullptr;   // [NS][COLS]
+    ColState* h_adm = nullptr;    // [NS][COLS]
+    int32_t* h_lists = nullptr;   // [NS][2][COLS]: columns, excluded ids
+    int32_t* h_cnt = nullptr;     // [NS] active counts
+    if (hipHostMalloc((void**)&h_snap, sizeof(ColState) * NS * COLS) != hipSuccess ||
+        hipHostMalloc((void**)&h_adm, sizeof(ColState) * NS * COLS) != hipSuccess ||
+        hipHostMalloc((void**)&h_lists, sizeof(int32_t) * NS * 2 * COLS) != hipSuccess ||
+        hipHostMalloc((void**)&h_cnt, sizeof(int32_t) * NS) != hipSuccess) {
+        if (h_snap) hipHostFree(h_snap);
+        if (h_adm) hipHostFree(h_adm);
+        if (h_lists) hipHostFree(h_lists);
+        (void)hipGetLastError();
+        return BHPP_OUT_OF_MEMORY;
+    }
+    hipEvent_t ev_snap[NS], ev_adm[NS];
+    bool adm_busy[NS] = {false, false, false, false};
+    for (int i = 0; i < NS; ++i) {
+        hipEventCreateWithFlags(&ev_snap[i], hipEventDisableTiming);
+        hipEventCreateWithFlags(&ev_adm[i], hipEventDisableTiming);
+    }
+    std::vector<ColState> hs(COLS);
+    std::vector<int32_t> qid(COLS, -1);   // the query each column holds (host view), -1 none
+    for (int c = 0; c < COLS; ++c) done_state(hs[c]);
+    int next = 0, ncols = COLS, exported = 0;
+    auto init_q = [&](ColState& c, int col) {
+        const int q = next++;
+        const int32_t u = src_ext[q];
+        init_state(c, alpha, g->h_ws_u[u], eps[q], g->info.eps_b_ratio, lambda, g->ne, target);
+        c.fresh = 1;
+        c.src_row = g->h_perm_u[u];
+        c.qid = q;
+        qid[col] = q;
+    };
+    for (int c = 0; c < COLS && next < n; ++c) init_q(hs[c], c);
+    bhpp_status rc = BHPP_OK;
+    {
+        int32_t act = 0;
+        for (int c = 0; c < COLS; ++c) act += hs[c].mode != MODE_DONE ? 1 : 0;
+        w.h_active[2] = act;
+        w.h_active[3] = 0;
+        if (hipMemcpyAsync(w.st, hs.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(w.n_active, &w.h_active[2], 2 * sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess)
+            rc = BHPP_DEVICE_ERROR;
+        if (g->prof_on && hipMemsetAsync(w.n_active + 4, 0, sizeof(int32_t), s) != hipSuccess) rc = BHPP_DEVICE_ERROR;
+        if (hipStreamSynchronize(s) != hipSuccess) rc = BHPP_DEVICE_ERROR;   // w.h_active is read by the copy
+    }
+    hipGraphExec_t* cache = &w.chunk_exec[log2i(COLS)];
+    int64_t chunk = 0, idle_sweeps = 0, rounds = 0;
+    // export the columns `cols` (finished as of the state copy `snap`) and
+    // admit the next queries into them, behind the work already queued
+    auto export_round = [&](const std::vector<int32_t>& cols, const ColState* snap) -> bhpp_status {
+        const int m = (int)cols.size();
+        // a pinned slot whose copies have run (rounds use the slots in turn)
+        const int slot = (int)(rounds % NS);
+        if (adm_busy[slot] && hipEventSynchronize(ev_adm[slot]) != hipSuccess) return BHPP_DEVICE_ERROR;
+        ++rounds;
+        int32_t* lc = h_lists + (size_t)slot * 2 * COLS;
+        int32_t* lx = lc + COLS;
+        ColState* ad = h_adm + (size_t)slot * COLS;
+        for (int j = 0; j < m; ++j) {
+            const int c = cols[j];
+            const int q = snap[c].qid;
+            lc[j] = c;
+            lx[j] = exclude_self ? src_ext[q] : -1;
+            if (stats) fill_stats(snap[c], stats[q]);
+        }
+        BHPP_HIP(hipMemcpyAsync(w.ex_tmp, lc, sizeof(int32_t) * 2 * COLS, hipMemcpyHostToDevice, s));
+        VT* rows = as<VT>(w.scores);   // [m][nu]; G is rewritten by the next sweep
+        if (scores_out || k > 0) {
+            hipLaunchKernelGGL((k_extract<COLS, VT>), dim3((g->nu + 63) / 64), dim3(256), 0, s, as<VT>(w.ACC),
+                               g->perm_u, g->deg_u, g->nu, w.ex_tmp, m, rows);
+            BHPP_HIP(hipGetLastError());
+        }
+        if (k > 0) {
+            const bhpp_status r = topk_rows(rows, m, g->nu, k, w.ex_tmp + COLS, g->dtype, w.ids_tmp, w.vals_tmp, s);
+            if (r) return r;
+        }
+        for (int j = 0; j < m; ++j) {
+            const int q = snap[cols[j]].qid;
+            if (scores_out)
+                BHPP_HIP(hipMemcpyAsync((char*)scores_out + (size_t)q * nu * e, (char*)rows + (size_t)j * nu * e,
+                                        nu * e, hipMemcpyDeviceToDevice, s));
+            if (k > 0) {
+                BHPP_HIP(hipMemcpyAsync(ids_out + (size_t)q * k, w.ids_tmp + (size_t)j * k, sizeof(int32_t) * k,
+                                        hipMemcpyDeviceToDevice, s));
+                BHPP_HIP(hipMemcpyAsync((char*)vals_out + (size_t)q * k * e, (char*)w.vals_tmp + (size_t)j * k * e,
+                                        e * k, hipMemcpyDeviceToDevice, s));
+            }
+        }
+        exported += m;
+        // admission: the next queries, or nothing, into the freed columns
+        for (int j = 0; j < m; ++j) {
+            const int c = cols[j];
+            if (next < n) {
+                init_q(ad[j], c);
+            } else {
+                done_state(ad[j]);
+                qid[c] = -1;
+            }
+        }
+        BHPP_HIP(hipMemcpyAsync(w.adm, ad, sizeof(ColState) * m, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_admit, dim3(1), dim3(COLS), 0, s, w.st, w.adm, w.ex_tmp, m, w.n_active);
+        BHPP_HIP(hipGetLastError());
+        BHPP_HIP(hipEventRecord(ev_adm[slot], s));
+        adm_busy[slot] = true;
+        return BHPP_OK;
+    };
+    std::vector<int32_t> fin;
+    while (rc == BHPP_OK && exported < n) {
+        rc = launch_chunk<COLS, VT, WT>(g, b, G, s, cache);
+        if (rc) break;
+        const int cs = (int)(chunk % NS);
+        if (hipMemcpyAsync(h_snap + (size_t)cs * COLS, w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(h_cnt + cs, w.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipEventRecord(ev_snap[cs], s) != hipSuccess) {
+            rc = BHPP_DEVICE_ERROR;
+            break;
+        }
+        ++chunk;
+        if (chunk < 2) continue;
+        // the state copy of the chunk before the one just launched
+        const int ps = (int)((chunk - 2) % NS);
+        if (hipEventSynchronize(ev_snap[ps]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
+        const ColState* snap = h_snap + (size_t)ps * COLS;
+        fin.clear();
+        for (int c = 0; c < ncols; ++c)
+            if (qid[c] >= 0 && snap[c].qid == qid[c] && snap[c].mode == MODE_DONE) fin.push_back(c);
+        if (!fin.empty()) {
+            rc = export_round(fin, snap);
+            idle_sweeps = 0;
+        } else {
+            idle_sweeps += g->chunk_sweeps;
+            if (idle_sweeps > kMaxSteps) rc = BHPP_NO_CONVERGENCE;
+        }
+        if (rc) break;
+        // once the queue is empty and at most 32 columns run, move them to the
+        // low columns (same bits: columns are independent of their position)
+        int live = 0;
+        for (int c = 0; c < ncols; ++c) live += qid[c] >= 0 ? 1 : 0;
+        if (g->narrow && next >= n && ncols > 32 && live > 0 && live <= 32) {
+            if (hipStreamSynchronize(s) != hipSuccess ||
+                hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost) != hipSuccess) {
+                rc = BHPP_DEVICE_ERROR;
+                break;
+            }
+            for (int i = 0; i < NS; ++i) adm_busy[i] = false;   // the stream has drained
+            // columns that finished since the last copy leave first
+            fin.clear();
+            for (int c = 0; c < ncols; ++c)
+                if (qid[c] >= 0 && hs[c].qid == qid[c] && hs[c].mode == MODE_DONE) fin.push_back(c);
+            if (!fin.empty()) {
+                rc = export_round(fin, hs.data());
+                if (rc) break;
+                if (hipStreamSynchronize(s) != hipSuccess ||
+                    hipMemcpy(hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost) != hipSuccess) {
+                    rc = BHPP_DEVICE_ERROR;
+                    break;
+                }
+                for (int i = 0; i < NS; ++i) adm_busy[i] = false;
+            }
+            std::vector<int32_t> map(kMaxCols, -1), nq(COLS, -1);
+            std::vector<ColState> nh(COLS);
+            for (auto& c : nh) done_state(c);
+            int j = 0;
+            for (int c = 0; c < COLS; ++c)
+                if (qid[c] >= 0) {
+                    map[j] = c;
+                    nh[j] = hs[c];
+                    nq[j] = qid[c];
+                    ++j;
+                }
+            if (j > 0) {
+                int32_t* d_map = w.ex_tmp + 2 * kMaxCols;
+                BHPP_HIP(hipMemcpyAsync(d_map, map.data(), sizeof(int32_t) * kMaxCols, hipMemcpyHostToDevice, s));
+                const size_t tot = nu * COLS;
+                void* arrays[2] = {w.Y, w.ACC};
+                for (void* a : arrays) {
+                    hipLaunchKernelGGL(k_compact<VT>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, as<VT>(a),
+                                       COLS, as<VT>(w.S), COLS, d_map, g->nu);
+                    BHPP_HIP(hipMemcpyAsync(a, w.S, tot * e, hipMemcpyDeviceToDevice, s));
+                }
+                BHPP_HIP(hipGetLastError());
+                ncols = j;
+                qid = nq;
+                int32_t act = 0;
+                for (int c = 0; c < COLS; ++c) act += nh[c].mode != MODE_DONE ? 1 : 0;
+                w.h_active[2] = act;
+                w.h_active[3] = ncols;
+                BHPP_HIP(hipMemcpyAsync(w.st, nh.data(), sizeof(ColState) * COLS, hipMemcpyHostToDevice, s));
+                BHPP_HIP(hipMemcpyAsync(w.n_active, &w.h_active[2], 2 * sizeof(int32_t), hipMemcpyHostToDevice, s));
+                BHPP_HIP(hipStreamSynchronize(s));   // map, nh and h_active are read by the copies
+            }
+            chunk = 0;   // the state copies in flight predate the packing
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == BHPP_OK) rc = BHPP_DEVICE_ERROR;
+    if (rc == BHPP_OK && g->prof_on) {
+        int32_t live_sweeps = 0;
+        if (hipMemcpy(&live_sweeps, w.n_active + 4, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = BHPP_DEVICE_ERROR;
+        g->prof_live += live_sweeps;
+    }
+    for (int i = 0; i < NS; ++i) {
+        hipEventDestroy(ev_snap[i]);
+        hipEventDestroy(ev_adm[i]);
+    }
+    hipHostFree(h_snap);
+    hipHostFree(h_adm);
+    hipHostFree(h_lists);
+    hipHostFree(h_cnt);
+    return rc;
+}
+
 template <typename VT, typename WT>
 static bhpp_status run_sched_dispatch(Graph* g, const WarmSource& model, bhpp_warm_stats* ws, int target, int cols,
                                       int n,
@@ -1668,6 +1942,8 @@ static bhpp_status run_sched_dispatch(Graph* g, const WarmSource& model, bhpp_wa
                                       hipStream_t s) {
 #define BHPP_RUN(C) \
     return run_sched<C, VT, WT>(g, model, ws, target, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s)
+    if (cols == 64 && n > 64 && !model.any() && g->async_sched)
+        return run_sched_async<VT, WT>(g, target, n, src, eps, alpha, lambda, scores, k, ex, ids, vals, st, s);
     switch (cols) {
         case 1: BHPP_RUN(1);
         case 2: BHPP_RUN(2);
@@ -1685,7 +1961,7 @@ void free_workspace(Workspace& w) {
             hipGraphExecDestroy(x);
             x = nullptr;
         }
-    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.scores,
+    void* ptrs[] = {w.Y, w.ACC, w.S, w.Q, w.partA, w.partB, w.red, w.st, w.n_active, w.scores, w.adm,
                     w.ids_tmp, w.vals_tmp, w.ex_tmp, w.SNAP, w.wY, w.wS, w.wG, w.wQ, w.wpartA, w.wpartB,
                     w.wred, w.wst, w.wn_active, w.wP, w.wres, w.wcol_ids, w.fF, w.fS, w.fDeg,
                     w.fOffs, w.fTV, w.fQ, w.fMark, w.fCnt, w.fScanTmp};
@@ -1704,7 +1980,7 @@ size_t workspace_bytes(const Graph* g, int cols) {
     const size_t e = (size_t)g->elem, c = (size_t)cols;
     return (size_t)g->nu * c * e * 4 + (size_t)g->nv * c * e + (size_t)g->tiles_v.n_slots * c * e +
            (size_t)g->tiles_u.n_slots * c * e + (size_t)kNumRed * c * G.n_part * 8 + sizeof(ColState) * c +
-           (size_t)kMaxCols * kTopkTmpK * (4 + e) + 4096;
+           (size_t)kMaxCols * kTopkTmpK * (4 + e) + sizeof(ColState) * kMaxCols + 4096;
 }
 
 bhpp_status ensure_workspace(Graph* g, int cols, hipStream_t s) { return ensure_workspace(g, g->ws, cols, s); }
@@ -1729,7 +2005,8 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
               alloc(&w.scores, (size_t)g->nu * c * e) &&
               alloc((void**)&w.ids_tmp, (size_t)kMaxCols * kTopkTmpK * 4) &&
               alloc(&w.vals_tmp, (size_t)kMaxCols * kTopkTmpK * e) &&
-              alloc((void**)&w.ex_tmp, (size_t)3 * kMaxCols * 4);
+              alloc((void**)&w.ex_tmp, (size_t)3 * kMaxCols * 4) &&
+              alloc((void**)&w.adm, sizeof(ColState) * kMaxCols);
     if (ok) ok = hipHostMalloc((void**)&w.h_active, 64) == hipSuccess;
     if (!ok) {
         free_workspace(w);
@@ -1889,7 +2166,7 @@ static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out
     hipEventElapsedTime(&ms, e0, e1);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    *ms_out = ms / (float)(reps * kStepsPerChunk);
+    *ms_out = ms / (float)(reps * g->chunk_sweeps);
     // leave the block inactive
     done_state(hs[0]);
     for (int c = 0; c < COLS_T; ++c) done_state(hs[c]);
@@ -1900,12 +2177,16 @@ static bhpp_status time_setting(Graph* g, hipStream_t s, int reps, float* ms_out
     return rc;
 }
 
-static bhpp_status apply_setting(Graph* g, int tile_edges, int inflight, int nt, int graphs) {
+void drop_chunk_graphs(Graph* g) {
     for (hipGraphExec_t& x : g->ws.chunk_exec)
         if (x) {
             hipGraphExecDestroy(x);
             x = nullptr;
         }
+}
+
+static bhpp_status apply_setting(Graph* g, int tile_edges, int inflight, int nt, int graphs) {
+    drop_chunk_graphs(g);
     if (tile_edges != g->tile_edges) {
         free_tiles(&g->tiles_u);
         free_tiles(&g->tiles_v);
@@ -1949,6 +2230,14 @@ bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg) {
             }
     bhpp_status rc = apply_setting(g, best[0], best[1], best[2], best[3]);
     for (int i = 0; i < 4; ++i) out_cfg[i] = best[i];
+    // sweeps per chunk: a query that finishes waits for the chunk boundary
+    // (and, in queue-fed batches, one more chunk) before its column is
+    // refilled, while each chunk costs the host a launch and a state copy;
+    // chunks of about 2 ms of sweeps keep the host far ahead of the device
+    int chunk = 8;
+    while (chunk > 1 && chunk * (double)best_ms > 2.0) chunk /= 2;
+    if (chunk != g->chunk_sweeps) drop_chunk_graphs(g);
+    g->chunk_sweeps = chunk;
     return rc;
 }
 
@@ -2054,8 +2343,8 @@ static bhpp_status server_poll_impl(Server* sv, int64_t* tags, int32_t* ids, voi
     if (live == 0) return BHPP_OK;
     bhpp_status rc = launch_chunk<COLS, VT, WT>(g, b, G, s, &w.chunk_exec[log2i(COLS)]);
     if (rc) return rc;
-    sv->sweeps += kStepsPerChunk;
-    sv->since_done += kStepsPerChunk;
+    sv->sweeps += g->chunk_sweeps;
+    sv->since_done += g->chunk_sweeps;
     BHPP_HIP(hipStreamSynchronize(s));
     BHPP_HIP(hipMemcpy(sv->hs.data(), w.st, sizeof(ColState) * COLS, hipMemcpyDeviceToHost));
     std::vector<int32_t> cols, ex;

@@ -382,6 +382,63 @@ def pin_pisp(g, Pi, sources, alpha, eps_list=(1e-2, 1e-4, 1e-7)):
     return out
 
 
+PHILOX_KAT = [  # Philox4x32-10 known-answer vectors of its authors (Random123): counter, key -> output
+    ((0x00000000, 0x00000000, 0x00000000, 0x00000000), (0x00000000, 0x00000000),
+     (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff, 0xffffffff, 0xffffffff, 0xffffffff), (0xffffffff, 0xffffffff),
+     (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+]
+
+
+def pin_mcsp(g, Pi, sources, alpha=0.15):
+    """MCSP (Sec. 3.3): the generator reproduces Philox4x32-10's published
+    known answers; every alias table encodes its row's distribution
+    w(x, .)/ws(x); the walk count for |U| = 2000, eps_f = 5e-3, p_f = 1e-6 is
+    2 (1 + 5e-3/3) ln(2e9) / 2.5e-5 = 1716168.56..., rounded up (worked by
+    hand); walk frequencies agree with the dense Pi within 5 standard errors;
+    and beta' is within eps of beta (both parts' errors are at most eps/2, the
+    MonteCarlo part with probability 1 - p_f)."""
+    out = []
+    for ctr, key, want in PHILOX_KAT:
+        got = oracle.philox4x32_10(ctr, key)
+        _fail([int(x) for x in got] == list(want), f"Philox known answer {ctr}", out)
+    _fail(oracle.mc_walks(2000, 5e-3, 1e-6) == 1716169, "MonteCarlo walk count", out)
+    exp = g.export()
+    for side, (rp, w, ws) in enumerate(((exp["rp_u"], exp["w_u"], exp["ws_u"]), (exp["rp_v"], exp["w_v"], exp["ws_v"]))):
+        prob, alias = g.alias_tables(side)
+        worst = 0.0
+        for r in range(rp.size - 1):
+            b, e = rp[r], rp[r + 1]
+            d = e - b
+            if d == 0:
+                continue
+            mass = prob[b:e].copy()
+            np.add.at(mass, alias[b:e], 1.0 - prob[b:e])
+            worst = max(worst, np.abs(mass / d - w[b:e] / ws[r]).max())
+        _fail(worst <= 1e-12, f"alias tables side {side}: {worst}", out)
+    n_r = 200000
+    for u in sources[:2]:
+        u = int(u)
+        cnt, steps = g.mc_counts(u, alpha, n_r, 12345)
+        est = cnt / n_r
+        sig = np.sqrt(np.maximum(Pi[u] * (1 - Pi[u]), 1e-7) / n_r)
+        _fail(np.all(np.abs(est - Pi[u]) <= 5 * sig + 1e-4), f"walk frequencies u={u}", out)
+        _fail(cnt.sum() == n_r, "every walk ends once", out)
+        _fail(abs(steps / n_r - (1 - alpha) / alpha) <= 0.05, f"mean walk length u={u}: {steps / n_r}", out)
+    for u in sources[:2]:
+        u = int(u)
+        eps = 2e-2
+        b, cnt, pib, nr = g.mcsp(u, alpha, eps, 1e-6, 7)
+        beta = Pi[u, :] + Pi[:, u]
+        _fail(np.abs(beta - b).max() <= eps, f"MCSP band u={u}: {np.abs(beta - b).max()}", out)
+        d_b = Pi[:, u] - pib
+        _fail(d_b.min() >= -1e-12 and d_b.max() <= eps / 2 + 1e-12, f"MCSP backward band u={u}", out)
+        _fail(nr == oracle.mc_walks(g.n_u, eps / 2, 1e-6) and cnt.sum() == nr, f"MCSP walks u={u}", out)
+    return out
+
+
 def run_core_pins(small, stop_early=False):
     """The pins the mutation tests rely on; fast enough to run per mutant.
     ``small`` holds the edge list and the dense Pi (computed with numpy, not
@@ -397,7 +454,8 @@ def run_core_pins(small, stop_early=False):
               lambda: pin_lemma1_and_mass(g, Pi, int(src[0]), a, 1e-5),
               lambda: pin_lambda(g, Pi, a),
               lambda: pin_warm_start(g, Pi, src, a),
-              lambda: pin_pisp(g, Pi, src[:4], a)]
+              lambda: pin_pisp(g, Pi, src[:4], a),
+              lambda: pin_mcsp(g, Pi, src, a)]
     out = []
     for c in checks:
         try:

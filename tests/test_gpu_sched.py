@@ -106,3 +106,32 @@ def test_fused_select_matches_select_pass(setup, monkeypatch):
     assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
     assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
     assert a["stats"] == b["stats"]
+
+
+def test_async_admission_matches_draining_rounds(setup, monkeypatch):
+    """Batches of more than 64 sources admit new queries without draining the
+    stream (the host reads copies of the column states a chunk behind and
+    queues extraction, top-k and admission behind the running sweeps). With
+    chunks of 1, 2 or 8 sweeps, packing on or off, every query gets the bits
+    and counters of the draining export rounds: a query's arithmetic does not
+    depend on when it is admitted or which column it takes."""
+    s = setup
+    src, eps = s["src"], s["eps"]
+    monkeypatch.setenv("BHPP_TUNE", "async=0")
+    Gh = s["bh"].Graph.from_edges(s["el"], dtype="f32", fixed_width=True)
+    Gh.set_launch_config(s["Gf"].launch_config())
+    base = Gh.query_batch(src, eps, k=10)
+    Gh.close()
+    for chunk, fixed in ((1, False), (2, True), (8, False)):
+        monkeypatch.setenv("BHPP_TUNE", f"async=1,chunk={chunk}")
+        Ga = s["bh"].Graph.from_edges(s["el"], dtype="f32", fixed_width=fixed)
+        Ga.set_launch_config(s["Gf"].launch_config())
+        out = Ga.query_batch(src, eps, k=10)
+        assert np.array_equal(out["scores"].cpu().numpy(), base["scores"].cpu().numpy()), chunk
+        assert np.array_equal(out["ids"].cpu().numpy(), base["ids"].cpu().numpy()), chunk
+        assert out["stats"] == base["stats"], chunk
+        # without scores or top-k outputs only the statistics come back
+        st = Ga.query_batch(src, eps, k=0, scores=False)["stats"]
+        assert st == base["stats"], chunk
+        Ga.close()
+    monkeypatch.delenv("BHPP_TUNE")

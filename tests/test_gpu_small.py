@@ -281,3 +281,22 @@ def test_single_direction_hpp(small, bh):
         assert np.abs(one.cpu().numpy()[0] - B[0]).max() <= 1e-12
     with pytest.raises(bh.BhppError):
         G.query_hpp(src, 1e-6, "forward", alpha=2.0)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hub_lds_is_bit_neutral(small, bh, dtype, monkeypatch):
+    """One-source gathers read the hub slice of their vector from an LDS copy;
+    the values are the same as the global ones, so dense one-source queries
+    give the same bits with the copy on or off."""
+    el = small["el"]
+    monkeypatch.setenv("BHPP_TUNE", "hub=0")
+    G0 = bh.Graph.from_edges(el, dtype=dtype, sparse=False)
+    monkeypatch.setenv("BHPP_TUNE", "hub=1")
+    G1 = bh.Graph.from_edges(el, dtype=dtype, sparse=False)
+    for u in small["sources"][:6]:
+        b0, s0 = G0.query(int(u), 1e-7)
+        b1, s1 = G1.query(int(u), 1e-7)
+        assert s0 == s1
+        assert np.array_equal(b0.cpu().numpy().view(np.uint8), b1.cpu().numpy().view(np.uint8)), int(u)
+    G0.close()
+    G1.close()

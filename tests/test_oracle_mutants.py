@@ -37,8 +37,14 @@ MUTANTS = {
     "warm_fallback_never": ("if (!(info.res_l1 < 1.0 && info.res_max < 1.0)) {", "if (0) {"),
     "no_sequential_pushes": ("if (!(rmax > eps_b && rsum > eps_b)) break;", "break;"),
     "pisp_t_full_eps": ("s.t = orc_t(1.0, 0.5 * eps, alpha);", "s.t = orc_t(1.0, eps, alpha);"),
-    "pisp_eps_b_full_eps": ("const double eps_b = 0.5 * eps;", "const double eps_b = eps;"),
-    "pisp_one_push_only": ("        if (!(rmax > eps_b)) break;\n", "        break;\n"),
+    "pisp_eps_b_full_eps": ("rc = selective_push(g, u, alpha, 0.5 * eps, pib, &s.sp_iters, &s.np);",
+                            "rc = selective_push(g, u, alpha, eps, pib, &s.sp_iters, &s.np);"),
+    "pisp_one_push_only": ("        if (!(rmax > thr_b)) break;\n", "        break;\n"),
+    "mc_stop_inverted": ("if ((double)a[0] < stop_thr) break;", "if ((double)a[0] >= stop_thr) break;"),
+    "mc_alias_coin_inverted": ("(double)rc * 0x1.0p-32 < prob[b + slot] ? slot", "(double)rc * 0x1.0p-32 >= prob[b + slot] ? slot"),
+    "mc_walks_half": ("return (int64_t)ceil(2.0 * (1.0 + eps_f / 3.0)", "return (int64_t)ceil(1.0 * (1.0 + eps_f / 3.0)"),
+    "alias_no_carry": ("q[l] = (q[l] + q[a]) - 1.0;", "q[l] = q[l] - 1.0;"),
+    "philox_no_key_bump": ("if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }", "if (r < 0) { k0 += 0x9E3779B9u; }"),
 }
 
 

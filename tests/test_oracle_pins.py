@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from pins_lib import (pin_closed_forms, pin_dense_invariants, pin_eps_b, pin_golden_gamma,
-                      pin_golden_rounds, pin_lambda, pin_lemma1_and_mass, pin_pisp, pin_power_mass,
+                      pin_golden_rounds, pin_lambda, pin_lemma1_and_mass, pin_mcsp, pin_pisp, pin_power_mass,
                       pin_random_walk, pin_series_agree, pin_theorems)
 
 
@@ -165,3 +165,40 @@ def test_pisp_closed_forms():
         (nu, nv, eu, ev, w), Pi = mk()
         g = oracle.Graph(nu, nv, eu, ev, w)
         assert pin_pisp(g, Pi, range(nu), 0.15, (1e-2, 1e-5)) == []
+
+
+def test_bounded_sample_counts_the_work(small_graph):
+    """The CPU baseline's bounded sample (Algorithm 5 stopped after a number
+    of push iterations) counts the edges touched: uncapped, that is the
+    statistics' n_p of both sub-algorithms plus 2|E| per PowerIteration round;
+    capped, a part of it."""
+    s = small_graph
+    g, src = s["g"], s["sources"][:4]
+    full = g.approx_bhpp_sample(src, 0.15, 1e-7, 100000)
+    _, st = g.approx_bhpp_many(src, 0.15, 1e-7)
+    for i in range(len(src)):
+        want = st[i]["np_ss"] + st[i]["np_pi"] + 2 * g.n_e * st[i]["t"]
+        assert abs(full[i] - want) <= 1e-9 * want
+    part = g.approx_bhpp_sample(src, 0.15, 1e-7, 3)
+    assert np.all(part > 0) and np.all(part < full)
+
+
+def test_mcsp_generator_alias_walks_and_band(small_graph):
+    """MCSP (Sec. 3.3): Philox known answers, alias tables, the walk count,
+    walk frequencies against the dense solve and the eps band."""
+    s = small_graph
+    assert pin_mcsp(s["g"], s["Pi"], s["sources"], s["wl"].alpha) == []
+
+
+def test_mc_walks_on_the_walk_graph():
+    """The walks against the random-walk definition on a small irregular graph
+    (asymmetric P): frequencies within 5 standard errors of the dense row."""
+    from pins_lib import walk_graph
+    nu, nv, eu, ev, w = walk_graph()
+    g = oracle.Graph(nu, nv, eu, ev, w)
+    Pi, _, _ = oracle.exact_dense(nu, nv, eu, ev, w, 0.15)
+    n_r = 400000
+    for u in range(nu):
+        cnt, _ = g.mc_counts(u, 0.15, n_r, 99 + u)
+        sig = np.sqrt(Pi[u] * (1 - Pi[u]) / n_r)
+        assert np.all(np.abs(cnt / n_r - Pi[u]) <= 5 * sig + 1e-9), u
