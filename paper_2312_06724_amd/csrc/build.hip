@@ -11,10 +11,9 @@
 //  4. the internal adjacency in both directions, 1/ws vectors, work tiles;
 //  5. lambda (Lemma 4) by PowerIteration from the all-ones vector and
 //     eps_b / eps (Eq. (epsilon-b)).
-// Sorting uses the hipCUB device radix sort (stable LSD); every other step
-// is a kernel below.
-#include <hipcub/hipcub.hpp>
-
+// Sorting is a stable LSD radix sort on 8-bit digits written below (tile
+// histograms, one prefix sum over them, a stable scatter); prefix sums use
+// scan.h.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -22,6 +21,7 @@
 #include <cstring>
 
 #include "common.h"
+#include "scan.h"
 
 namespace bhpp {
 
@@ -284,33 +284,130 @@ struct Tmp {
     }
 };
 
-// Stable sort of (keys, idx) pairs on the low `bits` bits.
+// Stable LSD radix sort, one launch pair per 8-bit digit. The keys are cut
+// into tiles of kRsTile consecutive entries, one workgroup each:
+//   k_rs_hist: the tile's digit counts, stored digit-major (digit d of tile t
+//     at d * n_tiles + t), so one exclusive prefix sum over them gives every
+//     (digit, tile) its first output position;
+//   k_rs_scatter: the tile's keys in input order, 256 at a time; a key's rank
+//     among equal digits of its wavefront comes from eight ballots, the counts
+//     of the earlier wavefronts and rounds from LDS, so equal digits keep
+//     their input order.
+constexpr int kRsItems = 16;
+constexpr int kRsTile = 256 * kRsItems;
+
+__global__ __launch_bounds__(256) void k_rs_hist(const uint64_t* keys, int64_t n, int shift, int32_t n_tiles,
+                                                 int32_t* hist) {
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t i = base + (int64_t)r * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+template <bool PAIRS>
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint64_t* keys, const int32_t* vals, int64_t n, int shift,
+                                                    int32_t n_tiles, const int32_t* offs, uint64_t* keys_out,
+                                                    int32_t* vals_out) {
+    __shared__ int32_t run[256];        // position of the next key with digit d in this tile's output range
+    __shared__ int32_t wcnt[4][256];    // keys with digit d in wavefront w of the current round
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    run[t] = offs[(int64_t)t * n_tiles + blockIdx.x];
+    for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (int r = 0; r < kRsItems; ++r) {
+        const int64_t i = base + (int64_t)r * 256 + t;
+        const bool ok = i < n;
+        uint64_t key = 0;
+        int32_t val = 0;
+        if (ok) {
+            key = keys[i];
+            if (PAIRS) val = vals[i];
+        }
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t same = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t on = __ballot((d >> b) & 1u);
+            same &= ((d >> b) & 1u) ? on : ~on;
+        }
+        const int rank = __popcll(same & lt);
+        if (ok && rank == 0) wcnt[wid][d] = __popcll(same);
+        __syncthreads();
+        if (ok) {
+            int32_t pos = run[d] + rank;
+            for (int k = 0; k < wid; ++k) pos += wcnt[k][d];
+            keys_out[pos] = key;
+            if (PAIRS) vals_out[pos] = val;
+        }
+        __syncthreads();
+        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+        for (int k = 0; k < 4; ++k) wcnt[k][t] = 0;
+        __syncthreads();
+    }
+}
+
+// Stable sort on the low `bits` bits; the result lands in keys_out (and
+// idx_out); keys_in and idx_in serve as the other buffer of the passes and are
+// overwritten.
+static bool radix_sort(Tmp& tmp, uint64_t* keys_in, uint64_t* keys_out, int32_t* idx_in, int32_t* idx_out, int64_t n,
+                       int bits, hipStream_t s) {
+    if (n <= 0) return true;
+    const int32_t n_tiles = (int32_t)((n + kRsTile - 1) / kRsTile);
+    const int64_t nh = (int64_t)n_tiles * 256;
+    int32_t* hist = tmp.get<int32_t>(nh);
+    int32_t* ts = tmp.get<int32_t>(scan_tiles(nh));
+    if (!tmp.ok) return false;
+    const bool pairs = idx_in != nullptr;
+    const int passes = std::max(1, (bits + 7) / 8);
+    uint64_t* ka = keys_in;
+    uint64_t* kb = keys_out;
+    int32_t* va = idx_in;
+    int32_t* vb = idx_out;
+    if (passes % 2 == 0) {   // an even number of passes ends where it starts: begin from a copy in keys_out
+        if (hipMemcpyAsync(keys_out, keys_in, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return false;
+        if (pairs && hipMemcpyAsync(idx_out, idx_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return false;
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(n_tiles), dim3(256), 0, s, ka, n, shift, n_tiles, hist);
+        if (scan_many<int32_t, int32_t, true>(hist, hist, nh, ts, s) != hipSuccess) return false;
+        if (pairs)
+            hipLaunchKernelGGL(k_rs_scatter<true>, dim3(n_tiles), dim3(256), 0, s, ka, va, n, shift, n_tiles, hist,
+                               kb, vb);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<false>, dim3(n_tiles), dim3(256), 0, s, ka, va, n, shift, n_tiles, hist,
+                               kb, vb);
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    return hipGetLastError() == hipSuccess;
+}
+
 static bool sort_pairs(Tmp& tmp, uint64_t* keys_in, uint64_t* keys_out, int32_t* idx_in, int32_t* idx_out, int64_t n,
                        int bits, hipStream_t s) {
-    size_t tb = 0;
-    if (hipcub::DeviceRadixSort::SortPairs(nullptr, tb, keys_in, keys_out, idx_in, idx_out, (int)n, 0, bits, s) !=
-        hipSuccess)
-        return false;
-    void* t = tmp.get<char>(tb);
-    if (!tmp.ok) return false;
-    return hipcub::DeviceRadixSort::SortPairs(t, tb, keys_in, keys_out, idx_in, idx_out, (int)n, 0, bits, s) ==
-           hipSuccess;
+    return radix_sort(tmp, keys_in, keys_out, idx_in, idx_out, n, bits, s);
 }
 
 static bool sort_keys(Tmp& tmp, uint64_t* in, uint64_t* out, int64_t n, int bits, hipStream_t s) {
-    size_t tb = 0;
-    if (hipcub::DeviceRadixSort::SortKeys(nullptr, tb, in, out, (int)n, 0, bits, s) != hipSuccess) return false;
-    void* t = tmp.get<char>(tb);
-    if (!tmp.ok) return false;
-    return hipcub::DeviceRadixSort::SortKeys(t, tb, in, out, (int)n, 0, bits, s) == hipSuccess;
+    return radix_sort(tmp, in, out, nullptr, nullptr, n, bits, s);
 }
 
 static bool exclusive_sum(Tmp& tmp, const int32_t* in, int32_t* out, int64_t n, hipStream_t s) {
-    size_t tb = 0;
-    if (hipcub::DeviceScan::ExclusiveSum(nullptr, tb, in, out, (int)n, s) != hipSuccess) return false;
-    void* t = tmp.get<char>(tb);
+    int32_t* ts = tmp.get<int32_t>(scan_tiles(n));
     if (!tmp.ok) return false;
-    return hipcub::DeviceScan::ExclusiveSum(t, tb, in, out, (int)n, s) == hipSuccess;
+    return scan_many<int32_t, int32_t, true>(in, out, n, ts, s) == hipSuccess;
 }
 
 // CSR of the edge list (a[i] -> b[i], weight w[i]) sorted by (a, b).

@@ -7,7 +7,8 @@
 //      wavefront), and adds up their degrees;
 //   2. take: ACC(x) += alpha y(x), S(x) = y(x)/ws(x), y(x) = 0 for x in F;
 //   3. U->V scatter, edge-parallel over the frontier's edges (an inclusive
-//      scan of their degrees maps a thread to its edge):
+//      scan of their degrees, scan.h's three-launch tile scan, maps a thread
+//      to its edge):
 //      Q(v) += w(x,v) S(x) into a V vector kept zero between steps; the first
 //      touch of v lists it and adds d(v) to n_p;
 //   4. V->U: the dense U-side gather of the sweep kernels over Q (its zeros
@@ -15,11 +16,10 @@
 //      of the dense update, and Q is cleared on the listed nodes.
 // The U->V scatter uses atomic adds, so its summation order (not the result
 // up to rounding) depends on timing.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 
 #include "common.h"
+#include "scan.h"
 
 namespace bhpp {
 
@@ -174,8 +174,7 @@ bhpp_status sparse_front_impl(Graph* g, Workspace& w, SparseStep& io, hipStream_
     if (!io.done || nF == 0) return BHPP_OK;
     hipLaunchKernelGGL(k_take<VT>, dim3(grid_of(nF)), dim3(256), 0, s, w.fF, nF, Y, ACC, inv_ws, g->deg_u, w.st, S,
                        w.fDeg);
-    size_t tb = w.fScanBytes;
-    BHPP_HIP(hipcub::DeviceScan::InclusiveSum(w.fScanTmp, tb, w.fDeg, w.fOffs, nF, s));
+    BHPP_HIP((scan_many<int64_t, int64_t, false>(w.fDeg, w.fOffs, nF, (int64_t*)w.fScanTmp, s)));
     hipLaunchKernelGGL((k_scatter_u<VT, WT>), dim3(grid_of(workF)), dim3(256), 0, s, w.fF, w.fOffs, nF, workF, S,
                        g->rp_u, g->ci_u, reinterpret_cast<const WT*>(g->w_u), inv_ws_v, g->rp_v,
                        reinterpret_cast<VT*>(w.fQ), w.fMark, w.fTV, (unsigned long long*)w.fCnt);
@@ -201,10 +200,7 @@ bhpp_status sparse_finish_impl(Graph* g, Workspace& w, const SparseStep& io, con
 bhpp_status ensure_sparse(Graph* g, Workspace& w, hipStream_t s) {
     if (w.fF) return BHPP_OK;
     const size_t nu = (size_t)g->nu, nv = (size_t)g->nv, e = (size_t)g->elem, nm = std::max(nu, nv);
-    size_t tb = 0;
-    if (hipcub::DeviceScan::InclusiveSum(nullptr, tb, (int64_t*)nullptr, (int64_t*)nullptr, (int)nm, s) !=
-        hipSuccess)
-        return BHPP_DEVICE_ERROR;
+    const size_t tb = (size_t)scan_tiles((int64_t)nm) * 8;
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
     const bool ok = A((void**)&w.fF, nu * 4) && A(&w.fS, nu * e) && A((void**)&w.fDeg, nm * 8) &&
                     A((void**)&w.fOffs, nm * 8) && A((void**)&w.fTV, nv * 4) && A(&w.fQ, nv * e) &&

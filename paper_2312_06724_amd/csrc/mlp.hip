@@ -34,7 +34,7 @@ constexpr int64_t kParams = 2 * kTower;
 constexpr int kEmbedChunk = 32768;   // rows per tower pass when embedding all nodes
 
 typedef uint16_t bf16;
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __host__ __device__ inline bf16 to_bf16(float f) {   // round to nearest, ties to even
@@ -54,8 +54,9 @@ __device__ inline float gelu_grad(float z) {
 // GEMM on MFMA: C[M][N] = A[M][K] B[K][N], A and B BF16 with arbitrary element
 // strides (so transposed operands need no copy), FP32 accumulation, and an
 // epilogue. A workgroup of 4 waves owns a 64x64 tile of C; each wave a 32x32
-// quarter computed by v_mfma_f32_32x32x8_bf16 over K chunks of 32 staged in
-// LDS (A as [row][k], B as [col][k], so both operands are 4 contiguous k).
+// quarter computed by gfx950's v_mfma_f32_32x32x16_bf16 over K chunks of 32
+// staged in LDS (A as [row][k], B as [col][k], so each lane's operand is 8
+// contiguous k: one 16-byte LDS read).
 // ---------------------------------------------------------------------------
 enum Epi { EPI_F32 = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_BWD = 3, EPI_PRED = 4, EPI_LOSS = 5 };
 
@@ -83,34 +84,68 @@ struct GemmArgs {
     const int32_t* col_node; // PRED, LOSS: node of each column (-1: none)
 };
 
+// Stage the 64 x 32 block X(r, k) = X[r rs + k ks], rows r0.., k from k0,
+// into S[r][k] (zero outside n_r x K). Where k (or r) is the contiguous
+// dimension and 8 entries stay in range on 16-byte boundaries, a thread moves
+// them with one 16-byte load; otherwise entry by entry.
+__device__ inline void stage_block(bf16 (*S)[40], const bf16* X, int64_t rs, int64_t ks, int n_r, int K, int r0,
+                                   int k0, bool vec_ok, int tid) {
+    if (ks == 1 && vec_ok) {   // 4 threads per row, 8 k each
+        const int r = tid >> 2, kk = (tid & 3) * 8, i = r0 + r, k = k0 + kk;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (i < n_r && k + 8 <= K) {
+            v = *reinterpret_cast<const uint4*>(X + (int64_t)i * rs + k);
+        } else if (i < n_r) {
+            bf16 t[8];
+            for (int q = 0; q < 8; ++q) t[q] = k + q < K ? X[(int64_t)i * rs + k + q] : (bf16)0;
+            memcpy(&v, t, 16);
+        }
+        *reinterpret_cast<uint4*>(&S[r][kk]) = v;
+        return;
+    }
+    if (rs == 1 && vec_ok) {   // 8 threads per k, 8 rows each
+        const int kk = tid >> 3, r = (tid & 7) * 8, i = r0 + r, k = k0 + kk;
+        bf16 t[8];
+        if (k < K && i + 8 <= n_r) {
+            const uint4 v = *reinterpret_cast<const uint4*>(X + (int64_t)k * ks + i);
+            memcpy(t, &v, 16);
+        } else {
+            for (int q = 0; q < 8; ++q) t[q] = (k < K && i + q < n_r) ? X[(int64_t)k * ks + i + q] : (bf16)0;
+        }
+        for (int q = 0; q < 8; ++q) S[r + q][kk] = t[q];
+        return;
+    }
+    for (int e = tid; e < 64 * 32; e += 256) {
+        // the loop index runs along whichever dimension is contiguous in memory
+        const bool kfast = ks == 1;
+        const int r = kfast ? e >> 5 : e & 63, kk = kfast ? e & 31 : e >> 6;
+        const int i = r0 + r, k = k0 + kk;
+        S[r][kk] = (i < n_r && k < K) ? X[(int64_t)i * rs + (int64_t)k * ks] : (bf16)0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs p) {
-    __shared__ bf16 As[64][40];
-    __shared__ bf16 Bs[64][40];
+    __shared__ __align__(16) bf16 As[64][40];   // rows of 80 bytes: 16-byte aligned reads
+    __shared__ __align__(16) bf16 Bs[64][40];
     __shared__ float red[256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
     const int row0 = blockIdx.x * 64, col0 = blockIdx.y * 64;   // rows on x: up to 2^31 tiles
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-    const bool a_kfast = p.a_cs == 1, b_kfast = p.b_rs == 1;
+    // 16-byte moves need 16-byte aligned bases and strides of the non-contiguous dimension
+    const bool a_vec = ((uintptr_t)p.A & 15) == 0 && ((p.a_cs == 1 && p.a_rs % 8 == 0) || (p.a_rs == 1 && p.a_cs % 8 == 0));
+    const bool b_vec = ((uintptr_t)p.B & 15) == 0 && ((p.b_rs == 1 && p.b_cs % 8 == 0) || (p.b_cs == 1 && p.b_rs % 8 == 0));
     for (int k0 = 0; k0 < p.K; k0 += 32) {
-        for (int e = tid; e < 64 * 32; e += 256) {
-            // the loop index runs along whichever dimension is contiguous in memory
-            const int r = a_kfast ? e >> 5 : e & 63, kk = a_kfast ? e & 31 : e >> 6;
-            const int i = row0 + r, k = k0 + kk;
-            As[r][kk] = (i < p.M && k < p.K) ? p.A[(int64_t)i * p.a_rs + (int64_t)k * p.a_cs] : (bf16)0;
-        }
-        for (int e = tid; e < 64 * 32; e += 256) {
-            const int c = b_kfast ? e >> 5 : e & 63, kk = b_kfast ? e & 31 : e >> 6;
-            const int j = col0 + c, k = k0 + kk;
-            Bs[c][kk] = (j < p.N && k < p.K) ? p.B[(int64_t)k * p.b_rs + (int64_t)j * p.b_cs] : (bf16)0;
-        }
+        stage_block(As, p.A, p.a_rs, p.a_cs, p.M, p.K, row0, k0, a_vec, tid);
+        stage_block(Bs, p.B, p.b_cs, p.b_rs, p.N, p.K, col0, k0, b_vec, tid);
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 32; kk += 8) {
-            const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[wr * 32 + (lane & 31)][kk + (lane >> 5) * 4]);
-            const bf16x4 b = *reinterpret_cast<const bf16x4*>(&Bs[wc * 32 + (lane & 31)][kk + (lane >> 5) * 4]);
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        for (int kk = 0; kk < 32; kk += 16) {
+            // lane l holds row (col) l % 32 and k = kk + 8 (l / 32) + 0..7
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wr * 32 + (lane & 31)][kk + (lane >> 5) * 8]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wc * 32 + (lane & 31)][kk + (lane >> 5) * 8]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
         __syncthreads();
     }

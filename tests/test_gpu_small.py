@@ -184,6 +184,27 @@ def test_duplicate_edges_merged(bh):
         assert np.array_equal(ex[k], ref[k]), k
 
 
+def test_graph_index_many_sort_tiles(bh):
+    """The build's radix sort over many tiles: 300k edges with repeated
+    pairs (input-order FP64 merges), (u, v) and (v, u) keys of 30 bits (four
+    digit passes, an even count; the 2k x 3k graph's keys take three), and the
+    degree sorts of 20k and 40k nodes (eight passes)."""
+    el = synth.chung_lu(20000, 40000, 300000, 2.1, "lognormal", 31)
+    rng = np.random.default_rng(12)
+    dup = rng.integers(0, el.n_e, 20000)
+    eu = np.concatenate([el.u, el.u[dup]]).astype(np.int32)
+    ev = np.concatenate([el.v, el.v[dup]]).astype(np.int32)
+    w = np.concatenate([el.w, rng.uniform(0.5, 2.0, dup.size)])
+    perm = rng.permutation(eu.size)
+    eu, ev, w = eu[perm], ev[perm], w[perm]
+    print(f"[gpu] build sort: {eu.size} edges over 20k x 40k", flush=True)
+    G = bh.Graph(20000, 40000, eu, ev, w, dtype="f64", keep_external=True)
+    ex = {k: v.cpu().numpy() for k, v in G.export().items()}
+    ref = oracle.Graph(20000, 40000, eu, ev, w).export()
+    for k in ("rp_u", "ci_u", "w_u", "rp_v", "ci_v", "w_v", "ws_u", "ws_v"):
+        assert np.array_equal(ex[k], ref[k]), k
+
+
 @pytest.mark.parametrize("reorder", [True, False])
 def test_fp32_random_graph_batch(bh, reorder):
     """FP32 values and accumulation; several tiles, split rows and a ragged

@@ -20,7 +20,9 @@ def bf16_tensor(torch, a):
 
 
 @pytest.mark.parametrize("M,N,K,ta,tb", [(64, 64, 32, 0, 0), (100, 70, 50, 0, 0), (37, 129, 200, 1, 0),
-                                         (130, 33, 64, 0, 1), (65, 65, 300, 1, 1)])
+                                         (130, 33, 64, 0, 1), (65, 65, 300, 1, 1),
+                                         # 16-byte staging: k contiguous with a ragged K, rows contiguous
+                                         (64, 48, 104, 0, 1), (72, 40, 100, 1, 0)])
 def test_gemm_lane_layout(M, N, K, ta, tb):
     import torch
     import paper_2312_06724_amd as bh
@@ -195,13 +197,12 @@ def test_model_warm_queries_within_bound(small):
     M.close()
 
 
-def test_trained_network_against_cold_start():
-    """What the trained network gains over the method without it, on a
-    20k x 40k graph (FP32): training data from the plain GPU path, then the
-    same evaluation queries cold, warm from the structural self term alone
+@pytest.fixture(scope="module")
+def trained():
+    """A 20k x 40k graph (FP32): training data from the plain GPU path, then
+    the same evaluation queries cold, warm from the structural self term alone
     (the network's output set to zero: the no-network ablation) and warm from
-    the trained network. All stay within eps of the exact scores; the report
-    prints residual norms, fallback rates and sweeps."""
+    the trained network."""
     import paper_2312_06724_amd as bh
     import torch
     el = synth.chung_lu(20000, 40000, 300000, 2.1, "lognormal", 51)
@@ -235,19 +236,60 @@ def test_trained_network_against_cold_start():
     losses = M.train(train, np.array(ids), np.array(vals), steps=1500, batch_src=32, batch_cand=4096, lr=5e-4)
     M.embed()
     warm = G.query_batch(evals, 1e-6, k=50, model=M)
-    ex = oracle.Graph.from_edges(el).exact_beta_many(evals[:6], 0.15, tail=1e-11, nthreads=16)
-    for name, o in (("cold", cold), ("prior only", prior_only), ("trained", warm)):
-        S = o["scores"][:6].double().cpu().numpy()
-        assert np.abs(ex - S).max() <= 1e-6 + 1e-6, name
     sw = lambda o: float(np.mean([x["steps"] for x in o["stats"]]))
     rep = {}
     for name, o in (("prior only", prior_only), ("trained", warm)):
         r = np.array([w["res_l1"] for w in o["warm"]])
         fb = np.array([w["fell_back"] for w in o["warm"]])
-        assert np.all((r >= 1) <= (fb == 1))
         rep[name] = dict(res_l1_median=round(float(np.median(r)), 3), fallback=float(fb.mean()), sweeps=sw(o))
     print(f"[gpu] loss {losses[:50].mean():.4g} -> {losses[-50:].mean():.4g}; sweeps cold {sw(cold):.1f}; "
           f"{rep}", flush=True)
-    assert rep["prior only"]["fallback"] == 0.0          # the self term alone always beats the cold start
+    yield dict(bh=bh, el=el, G=G, evals=evals, cold=cold, prior_only=prior_only, warm=warm, M=M, M0=M0, rep=rep,
+               sweeps=sw)
     M.close()
     M0.close()
+    G.close()
+
+
+def test_trained_network_against_cold_start(trained):
+    """Cold, self-term-only and trained starts all stay within eps of the
+    exact scores; a start is dropped exactly when its residual is no better
+    than the cold start's; the self term alone always beats the cold start."""
+    t = trained
+    ex = oracle.Graph.from_edges(t["el"]).exact_beta_many(t["evals"][:6], 0.15, tail=1e-11, nthreads=16)
+    for name in ("cold", "prior_only", "warm"):
+        S = t[name]["scores"][:6].double().cpu().numpy()
+        assert np.abs(ex - S).max() <= 1e-6 + 1e-6, name
+    for name in ("prior_only", "warm"):
+        r = np.array([w["res_l1"] for w in t[name]["warm"]])
+        fb = np.array([w["fell_back"] for w in t[name]["warm"]])
+        assert np.all((r >= 1) <= (fb == 1))
+    assert t["rep"]["prior only"]["fallback"] == 0.0
+
+
+@pytest.mark.xfail(strict=False, reason="negative result on random power-law graphs: the trained towers' starts "
+                                        "leave a larger signed residue than the structural self term alone (the "
+                                        "residue amplifies the prediction error by about 1/alpha); recorded in the "
+                                        "design notes with the curve against training-set size")
+def test_trained_network_beats_self_term(trained):
+    """What the trained network gains over the method without it: a smaller
+    median residual than the self-term-only start, starts that are kept, and
+    fewer sweeps than that ablation."""
+    rep = trained["rep"]
+    assert rep["trained"]["res_l1_median"] < rep["prior only"]["res_l1_median"]
+    assert rep["trained"]["fallback"] < 1.0
+    assert rep["trained"]["sweeps"] < rep["prior only"]["sweeps"]
+
+
+def test_model_predictions_are_the_warm_starts(trained):
+    """bhpp_model_predict exports the start each warm query uses: giving the
+    exported starts back through bhpp_query_batch_start reproduces the model's
+    warm queries bit for bit (residuals, fallbacks, scores)."""
+    t = trained
+    p = t["M0"].predict(t["evals"])
+    assert p.shape == (t["evals"].size, t["el"].n_u) and float(p.min()) >= 0.0
+    a = t["G"].query_batch(t["evals"], 1e-6, k=50, starts=p)
+    b = t["prior_only"]
+    assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
+    assert [w["fell_back"] for w in a["warm"]] == [w["fell_back"] for w in b["warm"]]
+    assert np.allclose([w["res_l1"] for w in a["warm"]], [w["res_l1"] for w in b["warm"]], rtol=0, atol=0)
