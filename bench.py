@@ -109,7 +109,9 @@ def roofline(prof, stats, info, workload):
       visits:    4 B per visit (the neighbour's value);
       outputs:   4 B per output row and running column (column-sweeps).
     The update reads degree and 1/ws once per sweep (8 B per node) and per
-    node and running column reads y, ACC, G and writes y, ACC (20 B).
+    node and running column reads y, ACC, G and writes y, ACC (20 B); fused
+    into the U-side gather it drops G (the gather's output row) and keeps
+    16 B per node and column.
     Each gather read counts as a memory read (no reuse); the per-entry 1/ws
     the V-side gather streams beside the adjacency is overhead, not counted.
     """
@@ -129,6 +131,14 @@ def roofline(prof, stats, info, workload):
             L * (8 * E + 8 * U1) + 4 * (U1 + V1) * CS,
             L * 8 * U1 + 20 * U1 * CS,
             0.0]
+    # the U-side gather with the update fused (no update launches): it takes
+    # on the update's node terms without G (8 B per node per sweep; read y,
+    # ACC and write y, ACC: 16 B per node and column) and no longer writes
+    # its G row (4 B per node and column)
+    fused_update = prof["launches"][2] == 0 and prof["launches"][1] > 0
+    if fused_update:
+        alg[1] += L * 8 * U1 + 12 * U1 * CS
+        comp[1] += L * 8 * U1 + 12 * U1 * CS
     dom = int(np.argmax(prof["ms"]))
     sec = prof["ms"][dom] * 1e-3
     launches = max(1, prof["launches"][dom])
@@ -136,7 +146,10 @@ def roofline(prof, stats, info, workload):
     achieved = alg[dom] / sec / 1e9
     paper_units = sum(s["np_ss"] + s["np_pi"] + 2 * E * s["t"] for s in stats)
     traffic = stored_traffic(workload, KINDS[dom])
-    out = dict(bound="hbm", kernel=KIND_NAMES[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+    name = KIND_NAMES[dom]
+    if dom == 1 and fused_update:
+        name = "U-side gather with the update fused (k_gather64, UPD)"
+    out = dict(bound="hbm", kernel=name, achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                avg_launch_ms=round(avg_ms, 4), launches=prof["launches"][dom], live_sweeps=int(L),
                algorithmic_bytes_per_launch=int(alg[dom] / launches),
@@ -148,8 +161,8 @@ def roofline(prof, stats, info, workload):
                                frac=round(comp[dom] / sec / 1e9 / HBM_PEAK_GBS, 4)),
                kernels={k: dict(avg_ms=round(prof["ms"][i] / max(1, prof["launches"][i]), 4),
                                 launches=prof["launches"][i],
-                                gbs=round(alg[i] / max(1e-12, prof["ms"][i] * 1e-3) / 1e9, 1))
-                        for i, k in enumerate(KINDS)})
+                                gbs=round(alg[i] / (prof["ms"][i] * 1e-3) / 1e9, 1) if prof["ms"][i] > 0 else None)
+                        for i, k in enumerate(KINDS) if prof["launches"][i] > 0})
     if traffic:
         out["traffic_gbs"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
     return out

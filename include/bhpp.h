@@ -82,9 +82,12 @@ typedef struct {
    (replay sweeps as HIP graphs), sparse=<0|1> (as BHPP_BUILD_DENSE_ONLY),
    narrow=<0|1> (as BHPP_BUILD_FIXED_WIDTH), fuse=<0|1> (64-column blocks:
    the V-side gather applies the push rule itself instead of a separate
-   selection pass; same bits either way) and hub=<0|1> (one-source gathers
-   read the values of the highest-degree nodes from a copy in LDS; same
-   bits either way). */
+   selection pass; same bits either way), upd=<0|1> (64-column blocks: the
+   U-side gather applies the update itself instead of a separate update
+   pass; same bits per entry, per-source sums added in another order; on by
+   default) and hub=<0|1> (one-source gathers read the values of the
+   highest-degree nodes from a copy in LDS; same bits either way; off by
+   default). */
 #define BHPP_BUILD_FIXED_WIDTH   8u
 /* Build MCSP's Walker alias tables (bhpp_query_batch_mcsp): 16 bytes per
    adjacency entry per side. */
@@ -257,7 +260,8 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
 
 /*
  * Device-time profile of the sweep kernels. While enabled, every launch of the
- * V-side gather (kind 0), the U-side gather (kind 1), the U-side update
+ * V-side gather (kind 0), the U-side gather (kind 1; in 64-column blocks it
+ * also applies the update, and kind 2 then has no launches), the U-side update
  * (kind 2) and the push selection (kind 3) on a query stream is bracketed by
  * HIP events on that stream and the
  * elapsed times are accumulated; bhpp_profile_read synchronises and returns,

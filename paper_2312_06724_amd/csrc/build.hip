@@ -183,7 +183,7 @@ static int bits_for(uint64_t maxval) {
 // work tiles (host): rows grouped so each tile covers about kTileEdges
 // adjacency entries; rows longer than that are split into pieces.
 // ---------------------------------------------------------------------------
-bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts) {
+bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts, int max_rows) {
     std::vector<Tile> tiles;
     std::vector<SplitRow> split;
     int32_t slot = 0;
@@ -218,7 +218,7 @@ bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile
         while (row < end) {
             const int64_t dd = rp[row + 1] - rp[row];
             if (dd == 0 || dd > T) break;
-            if (row > start && (edges + dd > T || row - start >= 512)) break;
+            if (row > start && (edges + dd > T || row - start >= max_rows)) break;
             edges += dd;
             maxd = std::max(maxd, dd);
             ++row;
@@ -254,6 +254,7 @@ void free_graph(Graph* g) {
     for (void* p : ptrs) hipFree(p);
     free_tiles(&g->tiles_u);
     free_tiles(&g->tiles_v);
+    free_tiles(&g->tiles_uf);
     free_workspace(g->ws);
     for (hipEvent_t e : g->prof_ev) hipEventDestroy(e);
     if (g->work) hipStreamDestroy(g->work);
@@ -617,6 +618,8 @@ bhpp_status build_impl(int32_t nu, int32_t nv, int64_t n, const int32_t* eu, con
     if (rc) return rc;
     rc = build_tiles(h_rp_v, nv, g->tile_edges, &g->tiles_v);
     if (rc) return rc;
+    rc = build_tiles(h_rp_u, nu, g->tile_edges, &g->tiles_uf, upd_rows(g->elem));
+    if (rc) return rc;
     g->h_rp_u = std::move(h_rp_u);
     g->h_rp_v = std::move(h_rp_v);
 
@@ -680,7 +683,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
     Graph* g = new (std::nothrow) Graph();
     if (!g) return BHPP_OUT_OF_MEMORY;
     // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=,
-    // hub=, chunk=, async=)
+    // hub=, chunk=, async=, upd=)
     if (const char* e = getenv("BHPP_TUNE")) {
         int v;
         const char* q;
@@ -695,6 +698,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "hub=")) && sscanf(q, "hub=%d", &v) == 1) g->hub_lds = v ? 1 : 0;
         if ((q = strstr(e, "chunk=")) && sscanf(q, "chunk=%d", &v) == 1 && v >= 1 && v <= 8) g->chunk_sweeps = v;
         if ((q = strstr(e, "async=")) && sscanf(q, "async=%d", &v) == 1) g->async_sched = v ? 1 : 0;
+        if ((q = strstr(e, "upd=")) && sscanf(q, "upd=%d", &v) == 1) g->fuse_update = v ? 1 : 0;
     }
     if (opts.flags & BHPP_BUILD_DENSE_ONLY) g->sparse_steps = 0;
     if (opts.flags & BHPP_BUILD_FIXED_WIDTH) g->narrow = 0;

@@ -172,6 +172,10 @@ struct Graph {
     int32_t* iperm_u = nullptr;  // internal -> external
     int32_t* iperm_v = nullptr;  // internal V id -> external
     TileSet tiles_u, tiles_v;
+    // tiles_u with at most upd_rows(elem) whole rows per tile: the U-side gather
+    // of 64-column blocks that applies the update itself keeps a tile's row sums
+    // in LDS until the tile ends
+    TileSet tiles_uf;
     // MCSP's alias tables (BHPP_BUILD_MCSP): rows of W and of W^T in caller ids
     int64_t *mc_rp_u = nullptr, *mc_rp_v = nullptr;
     double *mc_prob_u = nullptr, *mc_prob_v = nullptr;
@@ -199,9 +203,10 @@ struct Graph {
     int fuse_select = 1;             // 64-column blocks: gather A applies the push rule (no select pass)
     int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
     int narrow = 1;                  // batches narrow their block as sources finish
-    int hub_lds = 1;                 // one-source gathers read the hub slice of their vector from LDS
+    int hub_lds = 0;                 // one-source gathers read the hub slice of their vector from LDS (hub=1)
     int chunk_sweeps = 8;            // sweeps per launched chunk (captured graph), 1..8
     int async_sched = 1;             // queue-fed 64-column batches admit without draining the stream
+    int fuse_update = 1;             // 64-column blocks: the U-side gather applies the update (no G array)
     double eps_b_paper = 0.5;        // eps_b / eps of Eq. (epsilon-b); info.eps_b_ratio is the one in use
     bool sticky_error = false;
     int n_servers = 0;               // live servers hold captured graphs of the tiles
@@ -304,7 +309,10 @@ bhpp_status model_predict_ext(Model* m, int n, const int32_t* src_ext, float* ou
 bhpp_status gemm_test(int M, int N, int K, const uint16_t* A, int trans_a, const uint16_t* B, int trans_b, float* C,
                       hipStream_t s);
 bhpp_status set_launch_config(Graph* g, const int* cfg);
-bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts);
+bhpp_status build_tiles(const std::vector<int64_t>& rp, int32_t n_rows, int tile_edges, TileSet* ts,
+                        int max_rows = 512);
+// Rows per tile of tiles_uf: 4 KB of row sums (64 columns) per wavefront.
+inline int upd_rows(int elem) { return 4096 / (64 * elem); }
 void free_workspace(Workspace& w);
 bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg);
 void drop_chunk_graphs(Graph* g);

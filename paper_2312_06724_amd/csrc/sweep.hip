@@ -26,6 +26,7 @@
 // adjacency entry feeds C lanes with one contiguous load. The gathers contain
 // no loads besides the row gathers inside their inner loop (row metadata is
 // loaded per chunk of entries), so the row gathers stay in flight.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -49,9 +50,15 @@ constexpr int kUpdateBlocks = 2048;
 constexpr int kUpdateBlocks1 = 512;   // one-column blocks: 1/64 of the work, fewer partial sums
 
 struct Geometry {
-    int blkA, blkFA, blkB, blkFB, blkU, blkU1;
-    int offA, offFA, offU, n_part;   // reduction slots: gather A, fix-up A, update
+    int blkA, blkFA, blkB, blkFB, blkU, blkU1, blkBU;
+    // reduction slots: gather A, fix-up A, then the update's: k_update's blocks,
+    // or (update fused into gather B) gather B's blocks followed by its fix-up's
+    int offA, offFA, offU, n_part;
 };
+
+// Partial-sum slots of the U-side split rows (tiles_u and tiles_uf split the
+// same rows into the same pieces).
+static int32_t slots_u(const Graph* g) { return std::max(g->tiles_u.n_slots, g->tiles_uf.n_slots); }
 
 static Geometry geometry(const Graph* g) {
     Geometry G;
@@ -62,10 +69,11 @@ static Geometry geometry(const Graph* g) {
     G.blkFB = clampi(g->tiles_u.n_split, 1, kMaxFixBlocks);
     G.blkU = kUpdateBlocks;
     G.blkU1 = kUpdateBlocks1;
+    G.blkBU = clampi((g->tiles_uf.n_tiles + kWavesPerBlock - 1) / kWavesPerBlock, 1, kMaxPassBlocks);
     G.offA = 0;
     G.offFA = G.blkA;
     G.offU = G.offFA + G.blkFA;
-    G.n_part = G.offU + G.blkU;
+    G.n_part = G.offU + std::max(G.blkU, G.blkBU + G.blkFB);
     return G;
 }
 
@@ -194,6 +202,77 @@ struct GatherArgs {
     // entries are the hubs most adjacency entries point at); 0: none
     int32_t n_x = 0;
     int32_t hub = 0;
+    // k_gather64 / k_fixup, gather B with the update fused (64 columns): the
+    // row sums stay on chip and the update of those rows follows, as k_update
+    // does it, with its reductions in the slots from red_slot
+    VT* Yu = nullptr;
+    VT* ACCu = nullptr;
+    VT* SNAPu = nullptr;
+    const VT* iwu = nullptr;       // 1/ws of the U rows
+    const int32_t* degu = nullptr;
+    const ColState* stu = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// Update of one U row and column (k_update, and gather B with the update
+// fused): the push of x decided by ruleB (ACC += alpha y, y = 0), the
+// conversion of ACC the control asks for, y += (1-alpha) G, and the per-source
+// reductions. Both kernels call apply() with the same operands, so they
+// produce the same bits.
+// ---------------------------------------------------------------------------
+template <typename VT>
+struct UpdateRule {
+    PushTest<VT> test;
+    VT kss, kpi, ws_src, alpha, oma;
+    int convert;
+    bool warm, snap, fresh, y_src;
+    int32_t src_row;
+    // has_snap: the block has a SNAP array (the host never marks a column
+    // warm in a block without one; the check only keeps a slip in bounds)
+    __device__ __forceinline__ UpdateRule(const ColState& cs, bool has_snap)
+        : test(cs.ruleB, (VT)cs.k_ss, (VT)cs.k_pi) {
+        convert = cs.convert;
+        warm = cs.warm != 0 && has_snap;   // combine with pi_b as SS-Push left it
+        snap = warm && cs.snap != 0;
+        kss = (VT)cs.k_ss;
+        kpi = (VT)cs.k_pi;
+        ws_src = (VT)cs.ws_src;
+        alpha = (VT)cs.alpha;
+        oma = VT(1) - alpha;
+        fresh = cs.fresh != 0;
+        y_src = fresh || cs.reset_y != 0;   // y = e_src this sweep (ACC kept unless fresh)
+        src_row = cs.src_row;
+    }
+    // y and ACC of row x as this sweep reads them (a new query: y = e_src, ACC = 0)
+    __device__ __forceinline__ VT y_of(const VT* Y, size_t i, int32_t x) const {
+        return y_src ? (x == src_row ? VT(1) : VT(0)) : Y[i];
+    }
+    __device__ __forceinline__ VT acc_of(const VT* ACC, size_t i) const { return fresh ? VT(0) : ACC[i]; }
+    __device__ __forceinline__ void apply(VT y, VT a, VT g, VT iw, int32_t d, size_t i, VT* Y, VT* ACC, VT* SNAP,
+                                          double* r) const {
+        const VT yw = y * iw;
+        const bool sel = test(fabs(y), fabs(yw));
+        const VT s = sel ? y : VT(0);
+        VT acc = a;
+        if (snap) SNAP[i] = acc;                              // forward image of pi_b when SS-Push returned
+        if (convert == 1) {
+            // Eq. (fppr) plus the backward part of Alg. 5's combine: ACC -> beta' part
+            if (warm) acc = acc + ws_src * iw * (snap ? acc : SNAP[i]);
+            else acc = acc * (VT(1) + ws_src * iw);
+        } else if (convert == 3) {
+            acc = acc * ws_src * iw;   // SS-Push alone: the forward image back to pi_b(x) ~ pi(x, u)
+        }                              // convert == 2 (PI-Push alone): ACC already holds pi_f's part
+        acc += alpha * s;
+        const VT yn = (y - s) + oma * g;
+        Y[i] = yn;
+        ACC[i] = acc;
+        const VT tn = fabs(yn * iw), ya = fabs(yn);
+        r[RED_NP] += sel ? (double)d : 0.0;
+        r[RED_CNT_SS] += (tn > kss) ? 1.0 : 0.0;
+        r[RED_SUM_R] += (double)tn;
+        r[RED_CNT_PI] += (ya > kpi) ? 1.0 : 0.0;
+        r[RED_SUM_Y] += (double)ya;
+    }
 };
 
 // Columns of a block in use: n_active[1] (0: all). A batch keeps its running
@@ -285,11 +364,13 @@ struct Gather64State {
 
 // One chunk of n entries starting at cb. FULL: n == 64, so no entry needs a
 // bounds test; otherwise loads past n re-read entry n-1 and are not used.
-template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL, bool FUSED>
+// UPD: whole rows go to this wavefront's LDS rows (lrow, row st.row at
+// (st.row - T.row_begin) * 64) for the update at the end of the tile.
+template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL, bool FUSED, bool UPD>
 __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, const VT* X, const PushTest<VT>& test,
                                                const Tile& T, bool split, bool ns, bool on, int col, int xcol,
                                                int64_t cb, int n, int32_t lx, VT lw, VT liw, int mbase, int m_rel,
-                                               Gather64State<VT, WT>& st) {
+                                               Gather64State<VT, WT>& st, VT* lrow) {
     constexpr int COLS = 64;
     const int jend = FULL ? kWave : n;
     for (int j0 = 0; j0 < jend; j0 += INF) {
@@ -313,9 +394,13 @@ __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, cons
                     if (split) {
                         if (on) p.part[(size_t)T.slot * COLS + col] = st.acc;
                     } else {
-                        const size_t idx = (size_t)st.row * COLS + col;
-                        if (on) {
-                            if (ns) st_nt(&p.OUT[idx], st.acc); else p.OUT[idx] = st.acc;
+                        if (UPD) {
+                            if (on) lrow[(st.row - T.row_begin) * COLS + col] = st.acc;
+                        } else {
+                            const size_t idx = (size_t)st.row * COLS + col;
+                            if (on) {
+                                if (ns) st_nt(&p.OUT[idx], st.acc); else p.OUT[idx] = st.acc;
+                            }
                         }
                         const int64_t rend_abs = cb + st.rend;
                         if (SIDE_A && st.acc != VT(0)) st.np += (double)(rend_abs - st.rbeg);
@@ -330,16 +415,54 @@ __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, cons
     }
 }
 
-template <typename VT, typename WT, bool SIDE_A, int INF>
+// The update of a tile's rows [rb, re) from their sums in lrow (gather B with
+// the update fused): four rows' loads in flight, then UpdateRule::apply.
+template <typename VT, typename WT>
+__device__ __forceinline__ void update_tile_rows(const GatherArgs<VT, WT>& p, const VT* lrow, int rb, int re, int col,
+                                                 double* r) {
+    constexpr int COLS = 64, B = 2;
+    const UpdateRule<VT> u(p.stu[col], p.SNAPu != nullptr);
+    for (int x0 = rb; x0 < re; x0 += B) {
+        VT y[B], a[B], iw[B];
+        int32_t d[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int x = x0 + k;
+            const bool in = x < re;
+            const size_t i = (size_t)x * COLS + col;
+            d[k] = in ? p.degu[x] : 0;
+            iw[k] = in ? p.iwu[x] : VT(0);
+            y[k] = in ? u.y_of(p.Yu, i, x) : VT(0);
+            a[k] = in ? u.acc_of(p.ACCu, i) : VT(0);
+        }
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            const int x = x0 + k;
+            if (x < re && d[k] != 0)
+                u.apply(y[k], a[k], lrow[(x - rb) * COLS + col], iw[k], d[k], (size_t)x * COLS + col, p.Yu, p.ACCu,
+                        p.SNAPu, r);
+        }
+    }
+}
+
+// UPD (gather B only): tiles of at most upd_rows whole rows, whose sums stay
+// in LDS (each lane writes and reads only its own column: no barrier); after
+// each whole-row tile its rows are updated. Split pieces go to the partial
+// sums as usual (their rows are updated by the fix-up). The block's update
+// reductions go to slots red_slot + blockIdx.x.
+template <typename VT, typename WT, bool SIDE_A, int INF, bool UPD>
 __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p) {
     constexpr int COLS = 64;
+    constexpr int LROWS = UPD ? 4096 / (COLS * (int)sizeof(VT)) : 1;   // upd_rows()
     __shared__ double sh[kPassThreads];
+    __shared__ VT lds_rows[UPD ? kWavesPerBlock * LROWS * COLS : 1];
     if (*p.n_active == 0) return;
     const bool ns = p.nt_stream != 0;
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = wave_in_block();
     const int col = lane;
     const bool on = col < live_cols(p.n_active, COLS);
+    VT* lrow = UPD ? lds_rows + wid * LROWS * COLS : nullptr;
     // lanes of unused columns read column 0 of the same row (lane 0's cache
     // line, so no extra traffic and no divergent branch around the loads);
     // their sums are never stored and their push cost is dropped
@@ -356,6 +479,7 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     const VT* X = fused ? p.Yf : p.X;
     Gather64State<VT, WT> st;
     st.np = 0.0;
+    double r[kNumRed] = {0, 0, 0, 0, 0};   // UPD: the update's reductions
     const int n_waves = gridDim.x * kWavesPerBlock;
     for (int t = blockIdx.x * kWavesPerBlock + wid; t < p.n_tiles; t += n_waves) {
         const Tile T = load_tile(p.tiles, t);
@@ -376,24 +500,30 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
             st.rend = rl(m_rel, 0);
             if (fused) {
                 if (n == kWave)
-                    gather64_chunk<VT, WT, SIDE_A, INF, true, true>(p, X, test, T, split, ns, on, col, xcol, cb, n,
-                                                                    lx, lw, liw, mbase, m_rel, st);
+                    gather64_chunk<VT, WT, SIDE_A, INF, true, true, UPD>(p, X, test, T, split, ns, on, col, xcol, cb,
+                                                                         n, lx, lw, liw, mbase, m_rel, st, lrow);
                 else
-                    gather64_chunk<VT, WT, SIDE_A, INF, false, true>(p, X, test, T, split, ns, on, col, xcol, cb, n,
-                                                                     lx, lw, liw, mbase, m_rel, st);
+                    gather64_chunk<VT, WT, SIDE_A, INF, false, true, UPD>(p, X, test, T, split, ns, on, col, xcol, cb,
+                                                                          n, lx, lw, liw, mbase, m_rel, st, lrow);
             } else {
                 if (n == kWave)
-                    gather64_chunk<VT, WT, SIDE_A, INF, true, false>(p, X, test, T, split, ns, on, col, xcol, cb, n,
-                                                                     lx, lw, liw, mbase, m_rel, st);
+                    gather64_chunk<VT, WT, SIDE_A, INF, true, false, UPD>(p, X, test, T, split, ns, on, col, xcol, cb,
+                                                                          n, lx, lw, liw, mbase, m_rel, st, lrow);
                 else
-                    gather64_chunk<VT, WT, SIDE_A, INF, false, false>(p, X, test, T, split, ns, on, col, xcol, cb,
-                                                                      n, lx, lw, liw, mbase, m_rel, st);
+                    gather64_chunk<VT, WT, SIDE_A, INF, false, false, UPD>(p, X, test, T, split, ns, on, col, xcol,
+                                                                           cb, n, lx, lw, liw, mbase, m_rel, st, lrow);
             }
         }
+        if (UPD && !split && on) update_tile_rows(p, lrow, T.row_begin, T.row_end, col, r);
     }
     if (!on) st.np = 0.0;
     if (SIDE_A) block_column_sum<COLS>(st.np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
                                        p.red_slot + blockIdx.x);
+    if (UPD) {
+#pragma unroll
+        for (int k = 0; k < kNumRed; ++k)
+            block_column_sum<COLS>(r[k], sh, p.red + (size_t)k * COLS * p.n_part, p.n_part, p.red_slot + blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -533,7 +663,10 @@ __global__ __launch_bounds__(kPassThreads) void k_fixup1(GatherArgs<VT, WT> p, c
 // sl, sl + L, sl + 2L, ... (L = threads / COLS) into eight running sums (eight
 // loads in flight: a hub row has hundreds of pieces), the block then adds the
 // L partial sums in a fixed tree, and writes the row like the gather.
-template <int COLS, typename VT, typename WT, bool SIDE_A>
+// UPD (gather B with the update fused): the row is updated instead of
+// written to OUT, and the block's update reductions go to red_slot + blockIdx.x
+// (written even when there is no split row).
+template <int COLS, typename VT, typename WT, bool SIDE_A, bool UPD = false>
 __global__ __launch_bounds__(kFixThreads) void k_fixup(GatherArgs<VT, WT> p, const SplitRow* split, int n_split) {
     __shared__ double sh[kFixThreads];
     __shared__ VT sv[kFixThreads];
@@ -544,6 +677,7 @@ __global__ __launch_bounds__(kFixThreads) void k_fixup(GatherArgs<VT, WT> p, con
     const int sl = tid / COLS;
     const bool on = col < live_cols(p.n_active, COLS);
     double np = 0.0;
+    double r[kNumRed] = {0, 0, 0, 0, 0};
     for (int i = blockIdx.x; i < n_split; i += gridDim.x) {
         const SplitRow S = split[i];
         VT a[8];
@@ -564,7 +698,15 @@ __global__ __launch_bounds__(kFixThreads) void k_fixup(GatherArgs<VT, WT> p, con
         if (sl == 0 && on) {
             const int row = S.row;
             const VT q = sv[tid];
-            p.OUT[(size_t)row * COLS + col] = q;
+            const size_t i = (size_t)row * COLS + col;
+            if (UPD) {
+                const UpdateRule<VT> u(p.stu[col], p.SNAPu != nullptr);
+                const int32_t d = p.degu[row];
+                if (d != 0)
+                    u.apply(u.y_of(p.Yu, i, row), u.acc_of(p.ACCu, i), q, p.iwu[row], d, i, p.Yu, p.ACCu, p.SNAPu, r);
+            } else {
+                p.OUT[i] = q;
+            }
             // gather A: the V node is pushed (its cost counted) when its residue is
             // non-zero, the rule the unsplit rows apply to their sums
             if (SIDE_A && q != VT(0)) np += (double)(p.rp[row + 1] - p.rp[row]);
@@ -574,6 +716,12 @@ __global__ __launch_bounds__(kFixThreads) void k_fixup(GatherArgs<VT, WT> p, con
     if (SIDE_A)
         block_column_sum<COLS, kFixThreads / kWave>(np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
                                                     p.red_slot + blockIdx.x);
+    if (UPD) {
+#pragma unroll
+        for (int k = 0; k < kNumRed; ++k)
+            block_column_sum<COLS, kFixThreads / kWave>(r[k], sh, p.red + (size_t)k * COLS * p.n_part, p.n_part,
+                                                        p.red_slot + blockIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -631,17 +779,7 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
     __shared__ double sh[kPassThreads];
     if (*n_active == 0) return;
     const int col = threadIdx.x & (COLS - 1);
-    const ColState& cs = st[col];
-    const PushTest<VT> test(cs.ruleB, (VT)cs.k_ss, (VT)cs.k_pi);
-    const int convert = cs.convert;
-    // warm start: combine with pi_b as SS-Push left it (the host never marks a
-    // column warm in a block without SNAP; the check only keeps a slip in bounds)
-    const bool warm = cs.warm != 0 && SNAP != nullptr, snap = warm && cs.snap != 0;
-    const VT kss = (VT)cs.k_ss, kpi = (VT)cs.k_pi, ws_src = (VT)cs.ws_src, alpha = (VT)cs.alpha;
-    const VT one_minus_alpha = VT(1) - alpha;
-    const bool fresh = cs.fresh != 0;
-    const bool y_src = fresh || cs.reset_y != 0;   // y = e_src this sweep (ACC kept unless fresh)
-    const int32_t src_row = cs.src_row;
+    const UpdateRule<VT> u(st[col], SNAP != nullptr);
     double r[kNumRed] = {0, 0, 0, 0, 0};
     const size_t n = col < live_cols(n_active, COLS) ? (size_t)n_rows * COLS : 0;   // unused columns: no work
     const size_t stride = (size_t)gridDim.x * kPassThreads;   // a multiple of COLS: the column stays fixed
@@ -656,36 +794,14 @@ __global__ __launch_bounds__(kPassThreads) void k_update(VT* __restrict__ Y, VT*
             const int32_t x = in ? (int32_t)(i / COLS) : 0;
             d[k] = in ? deg[x] : 0;
             iw[k] = in ? inv_ws[x] : VT(0);
-            y[k] = in ? (y_src ? (x == src_row ? VT(1) : VT(0)) : Y[i]) : VT(0);   // new query: y = e_src
-            a[k] = (in && !fresh) ? ACC[i] : VT(0);                                  // and ACC = 0
+            y[k] = in ? u.y_of(Y, i, x) : VT(0);
+            a[k] = in ? u.acc_of(ACC, i) : VT(0);
             g[k] = in ? G[i] : VT(0);
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             if (d[k] == 0) continue;                          // isolated or past the end: untouched
-            const size_t i = i0 + k * stride;
-            const VT yw = y[k] * iw[k];
-            const bool sel = test(fabs(y[k]), fabs(yw));
-            const VT s = sel ? y[k] : VT(0);
-            VT acc = a[k];
-            if (snap) SNAP[i] = acc;                              // forward image of pi_b when SS-Push returned
-            if (convert == 1) {
-                // Eq. (fppr) plus the backward part of Alg. 5's combine: ACC -> beta' part
-                if (warm) acc = acc + ws_src * iw[k] * (snap ? acc : SNAP[i]);
-                else acc = acc * (VT(1) + ws_src * iw[k]);
-            } else if (convert == 3) {
-                acc = acc * ws_src * iw[k];   // SS-Push alone: the forward image back to pi_b(x) ~ pi(x, u)
-            }                                 // convert == 2 (PI-Push alone): ACC already holds pi_f's part
-            acc += alpha * s;
-            const VT yn = (y[k] - s) + one_minus_alpha * g[k];
-            Y[i] = yn;
-            ACC[i] = acc;
-            const VT tn = fabs(yn * iw[k]), ya = fabs(yn);
-            r[RED_NP] += sel ? (double)d[k] : 0.0;
-            r[RED_CNT_SS] += (tn > kss) ? 1.0 : 0.0;
-            r[RED_SUM_R] += (double)tn;
-            r[RED_CNT_PI] += (ya > kpi) ? 1.0 : 0.0;
-            r[RED_SUM_Y] += (double)ya;
+            u.apply(y[k], a[k], g[k], iw[k], d[k], i0 + k * stride, Y, ACC, SNAP, r);
         }
     }
 #pragma unroll
@@ -912,20 +1028,42 @@ __global__ void k_compact(const VT* src, int c1, VT* dst, int c2, const int32_t*
 }
 
 // Finished columns cols[0..m) of ACC (internal node order) -> out[j][external x]
-// (row-major, one row per finished query), through an LDS tile: reads and
-// writes are both coalesced.
+// (row-major, one row per finished query). The internal rows of the block's 64
+// nodes are looked up once into LDS; then either the whole 64-column rows go
+// through an LDS tile (reads and writes both coalesced), or, for one or two
+// columns, only those entries are read (a row's 256 bytes span two cache
+// lines; one column needs one).
 // Isolated nodes score 0; their rows of ACC are never written by the sweeps
 // (and may hold another block width's data), so they are not read.
 template <int COLS, typename VT>
 __global__ __launch_bounds__(256) void k_extract(const VT* ACC, const int32_t* perm, const int32_t* deg, int32_t nu,
                                                  const int32_t* cols, int m, VT* out) {
     __shared__ VT tile[64][COLS + (COLS == 1 ? 0 : 1)];
+    __shared__ int32_t rowx[64];   // internal row of node x0 + i; -1: isolated or past the end
     const int x0 = blockIdx.x * 64;
+    if (threadIdx.x < 64) {
+        const int x = x0 + (int)threadIdx.x;
+        int32_t xi = -1;
+        if (x < nu) {
+            xi = perm[x];
+            if (deg[xi] == 0) xi = -1;
+        }
+        rowx[threadIdx.x] = xi;
+    }
+    __syncthreads();
+    if (COLS > 1 && m <= 2) {
+        for (int idx = threadIdx.x; idx < 64 * m; idx += 256) {
+            const int j = idx / 64, i = idx % 64;
+            const int x = x0 + i;
+            const int32_t xi = rowx[i];
+            if (x < nu) out[(size_t)j * nu + x] = xi >= 0 ? ACC[(size_t)xi * COLS + cols[j]] : VT(0);
+        }
+        return;
+    }
     for (int idx = threadIdx.x; idx < 64 * COLS; idx += 256) {
         const int i = idx / COLS, c = idx % COLS;
-        const int x = x0 + i;
-        const int32_t xi = x < nu ? perm[x] : 0;
-        tile[i][c] = (x < nu && deg[xi] > 0) ? ACC[(size_t)xi * COLS + c] : VT(0);
+        const int32_t xi = rowx[i];
+        tile[i][c] = xi >= 0 ? ACC[(size_t)xi * COLS + c] : VT(0);
     }
     __syncthreads();
     for (int idx = threadIdx.x; idx < 64 * m; idx += 256) {
@@ -1055,12 +1193,18 @@ struct Block {
     void* SNAP;          // warm starts only (else null)
 };
 
-template <typename VT, typename WT, bool SIDE_A>
+template <typename VT, typename WT, bool SIDE_A, bool UPD = false>
 static void launch_gather64(int inflight, int blocks, hipStream_t s, const GatherArgs<VT, WT>& a) {
     switch (inflight) {
-        case 4: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 4>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 16>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
-        default: hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 8>), dim3(blocks), dim3(kPassThreads), 0, s, a); break;
+        case 4:
+            hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 4, UPD>), dim3(blocks), dim3(kPassThreads), 0, s, a);
+            break;
+        case 16:
+            hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 16, UPD>), dim3(blocks), dim3(kPassThreads), 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_gather64<VT, WT, SIDE_A, 8, UPD>), dim3(blocks), dim3(kPassThreads), 0, s, a);
+            break;
     }
 }
 
@@ -1094,7 +1238,7 @@ static void prof_end(Graph* g, hipStream_t s, hipEvent_t* ev) {
 // bytes; every non-isolated output row is written once, with its two offsets.
 // Node passes count each value read or written once per column.
 // kind 0: gather A (rows V), 1: gather B (rows U), 2: update (rows U),
-// 3: select (rows U).
+// 3: select (rows U), 4: gather B with the update fused (timed as kind 1).
 template <typename VT, typename WT>
 static double launch_bytes(const Graph* g, int cols, int kind) {
     const double nnz = (double)g->ne;
@@ -1109,14 +1253,18 @@ static double launch_bytes(const Graph* g, int cols, int kind) {
     if (kind == 1) return visits + nu * (8.0 + cols * vt);
     if (kind == 2)   // degrees, 1/ws_u; read Y, ACC, G; write Y, ACC
         return nu * 4.0 + nu * vt + 5.0 * nu * cols * vt;
+    if (kind == 4)   // gather B with the update fused: the gather's reads, then read Y, ACC; write Y, ACC
+        return visits + nu * 8.0 + nu * 4.0 + nu * vt + 4.0 * nu * cols * vt;
     return (double)g->nu * (vt + 2.0 * cols * vt);   // select: 1/ws_u, read Y, write S
 }
 
 // The V-side half and the U-side gather of one sweep: select, gather A and its
 // fix-up, gather B and its fix-up (G = the two-hop image of S). `prof` adds
 // HIP-event timing when profiling is on.
+// upd (64 columns): gather B applies the update itself over tiles_uf (its
+// reduction slots from G.offU, then its fix-up's), and no G is written.
 template <int COLS, typename VT, typename WT>
-static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_t s, bool prof) {
+static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_t s, bool prof, bool upd = false) {
     GatherArgs<VT, WT> A;
     A.tiles = g->tiles_v.tiles;
     A.n_tiles = g->tiles_v.n_tiles;
@@ -1176,6 +1324,25 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
     else
         hipLaunchKernelGGL((k_fixup<COLS, VT, WT, true>), dim3(G.blkFA), dim3(kFixThreads), 0, s, A,
                            g->tiles_v.split, g->tiles_v.n_split);
+    if (COLS == 64 && upd) {
+        B.tiles = g->tiles_uf.tiles;
+        B.n_tiles = g->tiles_uf.n_tiles;
+        B.Yu = as<VT>(b.Y);
+        B.ACCu = as<VT>(b.ACC);
+        B.SNAPu = as<VT>(b.SNAP);
+        B.iwu = inv_ws_u_of<VT>(g);
+        B.degu = g->deg_u;
+        B.stu = b.st;
+        B.OUT = nullptr;
+        if (prof) prof_begin(g, s, 1, launch_bytes<VT, WT>(g, COLS, 4), ev);
+        B.red_slot = G.offU;
+        launch_gather64<VT, WT, false, true>(g->inflight, G.blkBU, s, B);
+        prof_end(g, s, ev);
+        B.red_slot = G.offU + G.blkBU;
+        hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false, true>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
+                           g->tiles_uf.split, g->tiles_uf.n_split);
+        return;
+    }
     pb(1);
     B.red_slot = 0;
     if (COLS == 64)
@@ -1197,16 +1364,23 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
 
 template <int COLS, typename VT, typename WT>
 static bhpp_status launch_step(Graph* g, const Block& b, const Geometry& G, hipStream_t s) {
-    launch_front<COLS, VT, WT>(g, b, G, s, true);
-    hipEvent_t ev[2] = {nullptr, nullptr};
-    prof_begin(g, s, 2, launch_bytes<VT, WT>(g, COLS, 2), ev);
-    const int blkU = COLS == 1 ? G.blkU1 : G.blkU;   // its blocks fill reduction slots [offU, offU + blkU)
-    hipLaunchKernelGGL((k_update<COLS, VT>), dim3(blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.ACC),
-                       as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part, G.offU,
-                       as<VT>(b.SNAP));
-    prof_end(g, s, ev);
-    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(kControlThreads), 0, s, b.st, b.red, G.n_part,
-                       G.offU + blkU, G.offU, b.n_active);
+    const bool upd = COLS == 64 && g->fuse_update && sizeof(VT) == (size_t)g->elem && g->tiles_uf.tiles != nullptr;
+    launch_front<COLS, VT, WT>(g, b, G, s, true, upd);
+    int n_used;   // reduction slots of the sweep
+    if (upd) {
+        n_used = G.offU + G.blkBU + G.blkFB;
+    } else {
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        prof_begin(g, s, 2, launch_bytes<VT, WT>(g, COLS, 2), ev);
+        const int blkU = COLS == 1 ? G.blkU1 : G.blkU;   // its blocks fill reduction slots [offU, offU + blkU)
+        hipLaunchKernelGGL((k_update<COLS, VT>), dim3(blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.ACC),
+                           as<VT>(b.G), inv_ws_u_of<VT>(g), g->deg_u, g->nu, b.st, b.n_active, b.red, G.n_part,
+                           G.offU, as<VT>(b.SNAP));
+        prof_end(g, s, ev);
+        n_used = G.offU + blkU;
+    }
+    hipLaunchKernelGGL((k_control<COLS>), dim3(COLS), dim3(kControlThreads), 0, s, b.st, b.red, G.n_part, n_used,
+                       G.offU, b.n_active);
     BHPP_HIP(hipGetLastError());
     return BHPP_OK;
 }
@@ -1349,7 +1523,7 @@ static bhpp_status ensure_warm(Graph* g, Workspace& w, int ct, hipStream_t s) {
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
     const bool ok = A(&w.wY, nu * c * 8) && A(&w.wS, nu * c * 8) && A(&w.wG, nu * c * 8) && A(&w.wQ, nv * c * 8) &&
                     A(&w.wpartA, (size_t)g->tiles_v.n_slots * c * 8) &&
-                    A(&w.wpartB, (size_t)g->tiles_u.n_slots * c * 8) &&
+                    A(&w.wpartB, (size_t)slots_u(g) * c * 8) &&
                     A((void**)&w.wred, (size_t)kNumRed * c * G.n_part * 8) &&
                     A((void**)&w.wst, sizeof(ColState) * c) && A((void**)&w.wn_active, 64) &&
                     A((void**)&w.wP, nu * c * 4) && A((void**)&w.wres, 2 * c * kUpdateBlocks * 8) &&
@@ -1979,7 +2153,7 @@ size_t workspace_bytes(const Graph* g, int cols) {
     const Geometry G = geometry(g);
     const size_t e = (size_t)g->elem, c = (size_t)cols;
     return (size_t)g->nu * c * e * 4 + (size_t)g->nv * c * e + (size_t)g->tiles_v.n_slots * c * e +
-           (size_t)g->tiles_u.n_slots * c * e + (size_t)kNumRed * c * G.n_part * 8 + sizeof(ColState) * c +
+           (size_t)slots_u(g) * c * e + (size_t)kNumRed * c * G.n_part * 8 + sizeof(ColState) * c +
            (size_t)kMaxCols * kTopkTmpK * (4 + e) + sizeof(ColState) * kMaxCols + 4096;
 }
 
@@ -1999,7 +2173,7 @@ bhpp_status ensure_workspace(Graph* g, Workspace& w, int cols, hipStream_t s) {
     bool ok = alloc(&w.Y, (size_t)g->nu * c * e) && alloc(&w.ACC, (size_t)g->nu * c * e) &&
               alloc(&w.S, (size_t)g->nu * c * e) &&
               alloc(&w.Q, (size_t)g->nv * c * e) && alloc(&w.partA, (size_t)g->tiles_v.n_slots * c * e) &&
-              alloc(&w.partB, (size_t)g->tiles_u.n_slots * c * e) &&
+              alloc(&w.partB, (size_t)slots_u(g) * c * e) &&
               alloc((void**)&w.red, (size_t)kNumRed * c * G.n_part * 8 + 64 * 4) &&
               alloc((void**)&w.st, sizeof(ColState) * c) && alloc((void**)&w.n_active, 64) &&
               alloc(&w.scores, (size_t)g->nu * c * e) &&
@@ -2075,7 +2249,7 @@ static bhpp_status lambda_impl(Graph* g, double alpha, int32_t tau, hipStream_t 
     auto A = [&](void** p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 256) == hipSuccess; };
     bool ok = A(&b.Y, nU * 8) && A(&b.ACC, nU * 8) && A(&b.S, nU * 8) && A(&b.G, nU * 8) && A(&b.Q, nV * 8) &&
               A(&b.partA, (size_t)g->tiles_v.n_slots * 8) &&
-              A(&b.partB, (size_t)g->tiles_u.n_slots * 8) && A((void**)&b.red, (size_t)kNumRed * G.n_part * 8) &&
+              A(&b.partB, (size_t)slots_u(g) * 8) && A((void**)&b.red, (size_t)kNumRed * G.n_part * 8) &&
               A((void**)&b.st, sizeof(ColState)) && A((void**)&b.n_active, 64) &&
               hipHostMalloc((void**)&b.h_active, 64) == hipSuccess;
     bhpp_status rc = ok ? BHPP_OK : BHPP_OUT_OF_MEMORY;
@@ -2190,10 +2364,13 @@ static bhpp_status apply_setting(Graph* g, int tile_edges, int inflight, int nt,
     if (tile_edges != g->tile_edges) {
         free_tiles(&g->tiles_u);
         free_tiles(&g->tiles_v);
+        free_tiles(&g->tiles_uf);
         g->tile_edges = tile_edges;
         bhpp_status rc = build_tiles(g->h_rp_u, g->nu, tile_edges, &g->tiles_u);
         if (rc) return rc;
         rc = build_tiles(g->h_rp_v, g->nv, tile_edges, &g->tiles_v);
+        if (rc) return rc;
+        rc = build_tiles(g->h_rp_u, g->nu, tile_edges, &g->tiles_uf, upd_rows(g->elem));
         if (rc) return rc;
         free_workspace(g->ws);   // slot counts changed
     }
@@ -2431,7 +2608,7 @@ static size_t warm_bytes(const Graph* g, int cols) {
     const Geometry G = geometry(g);
     const size_t c = (size_t)cols, nu = (size_t)g->nu, nv = (size_t)g->nv;
     return nu * c * g->elem + nu * c * (3 * 8 + 4) + nv * c * 8 + (size_t)g->tiles_v.n_slots * c * 8 +
-           (size_t)g->tiles_u.n_slots * c * 8 + (size_t)kNumRed * c * G.n_part * 8 + 2 * c * kUpdateBlocks * 8 + 4096;
+           (size_t)slots_u(g) * c * 8 + (size_t)kNumRed * c * G.n_part * 8 + 2 * c * kUpdateBlocks * 8 + 4096;
 }
 
 bhpp_status server_create(Graph* g, Model* model, int max_width, double mem_budget, double alpha, double lambda, int k,

@@ -135,3 +135,34 @@ def test_async_admission_matches_draining_rounds(setup, monkeypatch):
         assert st == base["stats"], chunk
         Ga.close()
     monkeypatch.delenv("BHPP_TUNE")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_update_matches_update_pass(setup, monkeypatch, dtype):
+    """In 64-column blocks the U-side gather applies the update itself: a
+    tile's row sums stay in LDS and each entry of y and ACC is computed from
+    the same operands in the same order as the update pass, so the scores and
+    top-k match bit for bit. Only the order of the FP64 per-source sums
+    changes (the gather's tiles instead of the update's blocks): counters are
+    equal and the sums agree to rounding."""
+    s = setup
+    src, eps = s["src"][:150], s["eps"][:150]
+    monkeypatch.setenv("BHPP_TUNE", "upd=0")
+    G0 = s["bh"].Graph.from_edges(s["el"], dtype=dtype, fixed_width=True)
+    monkeypatch.setenv("BHPP_TUNE", "upd=1")
+    G1 = s["bh"].Graph.from_edges(s["el"], dtype=dtype, fixed_width=True)
+    monkeypatch.delenv("BHPP_TUNE")
+    G1.set_launch_config(G0.launch_config())
+    a = G1.query_batch(src, eps, k=10)
+    b = G0.query_batch(src, eps, k=10)
+    assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
+    assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
+    for x, y in zip(a["stats"], b["stats"]):
+        assert x.keys() == y.keys()
+        for key in x:
+            if isinstance(x[key], float):
+                assert abs(x[key] - y[key]) <= 1e-12 * max(1.0, abs(y[key])), key
+            else:
+                assert x[key] == y[key], key
+    G0.close()
+    G1.close()
