@@ -416,11 +416,11 @@ __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, cons
 }
 
 // The update of a tile's rows [rb, re) from their sums in lrow (gather B with
-// the update fused): four rows' loads in flight, then UpdateRule::apply.
-template <typename VT, typename WT>
+// the update fused): B rows' loads in flight, then UpdateRule::apply.
+template <typename VT, typename WT, int B>
 __device__ __forceinline__ void update_tile_rows(const GatherArgs<VT, WT>& p, const VT* lrow, int rb, int re, int col,
                                                  double* r) {
-    constexpr int COLS = 64, B = 2;
+    constexpr int COLS = 64;
     const UpdateRule<VT> u(p.stu[col], p.SNAPu != nullptr);
     for (int x0 = rb; x0 < re; x0 += B) {
         VT y[B], a[B], iw[B];
@@ -445,12 +445,13 @@ __device__ __forceinline__ void update_tile_rows(const GatherArgs<VT, WT>& p, co
     }
 }
 
-// UPD (gather B only): tiles of at most upd_rows whole rows, whose sums stay
+// UPD > 0 (gather B only; UPD rows' loads in flight in the update): tiles of
+// at most upd_rows whole rows, whose sums stay
 // in LDS (each lane writes and reads only its own column: no barrier); after
 // each whole-row tile its rows are updated. Split pieces go to the partial
 // sums as usual (their rows are updated by the fix-up). The block's update
 // reductions go to slots red_slot + blockIdx.x.
-template <typename VT, typename WT, bool SIDE_A, int INF, bool UPD>
+template <typename VT, typename WT, bool SIDE_A, int INF, int UPD>
 __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p) {
     constexpr int COLS = 64;
     constexpr int LROWS = UPD ? 4096 / (COLS * (int)sizeof(VT)) : 1;   // upd_rows()
@@ -500,21 +501,21 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
             st.rend = rl(m_rel, 0);
             if (fused) {
                 if (n == kWave)
-                    gather64_chunk<VT, WT, SIDE_A, INF, true, true, UPD>(p, X, test, T, split, ns, on, col, xcol, cb,
+                    gather64_chunk<VT, WT, SIDE_A, INF, true, true, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol, cb,
                                                                          n, lx, lw, liw, mbase, m_rel, st, lrow);
                 else
-                    gather64_chunk<VT, WT, SIDE_A, INF, false, true, UPD>(p, X, test, T, split, ns, on, col, xcol, cb,
+                    gather64_chunk<VT, WT, SIDE_A, INF, false, true, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol, cb,
                                                                           n, lx, lw, liw, mbase, m_rel, st, lrow);
             } else {
                 if (n == kWave)
-                    gather64_chunk<VT, WT, SIDE_A, INF, true, false, UPD>(p, X, test, T, split, ns, on, col, xcol, cb,
+                    gather64_chunk<VT, WT, SIDE_A, INF, true, false, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol, cb,
                                                                           n, lx, lw, liw, mbase, m_rel, st, lrow);
                 else
-                    gather64_chunk<VT, WT, SIDE_A, INF, false, false, UPD>(p, X, test, T, split, ns, on, col, xcol,
+                    gather64_chunk<VT, WT, SIDE_A, INF, false, false, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol,
                                                                            cb, n, lx, lw, liw, mbase, m_rel, st, lrow);
             }
         }
-        if (UPD && !split && on) update_tile_rows(p, lrow, T.row_begin, T.row_end, col, r);
+        if (UPD && !split && on) update_tile_rows<VT, WT, (UPD > 0 ? UPD : 1)>(p, lrow, T.row_begin, T.row_end, col, r);
     }
     if (!on) st.np = 0.0;
     if (SIDE_A) block_column_sum<COLS>(st.np, sh, p.red + (size_t)RED_NP * COLS * p.n_part, p.n_part,
@@ -1193,7 +1194,7 @@ struct Block {
     void* SNAP;          // warm starts only (else null)
 };
 
-template <typename VT, typename WT, bool SIDE_A, bool UPD = false>
+template <typename VT, typename WT, bool SIDE_A, int UPD = 0>
 static void launch_gather64(int inflight, int blocks, hipStream_t s, const GatherArgs<VT, WT>& a) {
     switch (inflight) {
         case 4:
@@ -1336,7 +1337,10 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
         B.OUT = nullptr;
         if (prof) prof_begin(g, s, 1, launch_bytes<VT, WT>(g, COLS, 4), ev);
         B.red_slot = G.offU;
-        launch_gather64<VT, WT, false, true>(g->inflight, G.blkBU, s, B);
+        if (g->upd_inflight == 4)
+            launch_gather64<VT, WT, false, 4>(g->inflight, G.blkBU, s, B);
+        else
+            launch_gather64<VT, WT, false, 2>(g->inflight, G.blkBU, s, B);
         prof_end(g, s, ev);
         B.red_slot = G.offU + G.blkBU;
         hipLaunchKernelGGL((k_fixup<COLS, VT, WT, false, true>), dim3(G.blkFB), dim3(kFixThreads), 0, s, B,
