@@ -184,7 +184,10 @@ bhpp_status bhpp_query(bhpp_graph* g, int32_t source, double alpha, double eps,
  * own phase, thresholds and stopping point. With more than 64 sources the
  * block is fed from a queue: as sources finish, their results are written out
  * and the next sources take their columns, so sources of very different cost
- * share the sweeps without waiting for each other.
+ * share the sweeps without waiting for each other. Sources enter the block
+ * longest expected first (smaller eps, then lower degree); outputs stay in
+ * the caller's order, and a source's result does not depend on when it
+ * entered.
  *   sources      host int32[n_src]
  *   eps          host double[n_src] (per-source error threshold) or NULL to use eps_all
  *   scores_out   device [n_src][n_u] row-major of the graph dtype, or NULL

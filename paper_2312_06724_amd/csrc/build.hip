@@ -683,7 +683,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
     Graph* g = new (std::nothrow) Graph();
     if (!g) return BHPP_OUT_OF_MEMORY;
     // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=,
-    // hub=, chunk=, async=, upd=, urows=)
+    // hub=, chunk=, async=, upd=, urows=, order=)
     if (const char* e = getenv("BHPP_TUNE")) {
         int v;
         const char* q;
@@ -700,6 +700,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "async=")) && sscanf(q, "async=%d", &v) == 1) g->async_sched = v ? 1 : 0;
         if ((q = strstr(e, "upd=")) && sscanf(q, "upd=%d", &v) == 1) g->fuse_update = v ? 1 : 0;
         if ((q = strstr(e, "urows=")) && sscanf(q, "urows=%d", &v) == 1 && (v == 2 || v == 4)) g->upd_inflight = v;
+        if ((q = strstr(e, "order=")) && sscanf(q, "order=%d", &v) == 1) g->order_admit = v ? 1 : 0;
     }
     if (opts.flags & BHPP_BUILD_DENSE_ONLY) g->sparse_steps = 0;
     if (opts.flags & BHPP_BUILD_FIXED_WIDTH) g->narrow = 0;

@@ -207,6 +207,7 @@ struct Graph {
     int chunk_sweeps = 8;            // sweeps per launched chunk (captured graph), 1..8
     int async_sched = 1;             // queue-fed 64-column batches admit without draining the stream
     int fuse_update = 1;             // 64-column blocks: the U-side gather applies the update (no G array)
+    int order_admit = 1;             // batches admit the longest expected queries first
     int upd_inflight = 2;            // rows whose y and ACC loads the fused update keeps in flight (2 or 4)
     double eps_b_paper = 0.5;        // eps_b / eps of Eq. (epsilon-b); info.eps_b_ratio is the one in use
     bool sticky_error = false;
