@@ -166,3 +166,21 @@ def test_fused_update_matches_update_pass(setup, monkeypatch, dtype):
                 assert x[key] == y[key], key
     G0.close()
     G1.close()
+
+
+def test_admission_order_does_not_change_results(setup, monkeypatch):
+    """Queues admit the longest expected queries first (smaller eps, then lower
+    degree); with the caller's order instead every query gets the same bits and
+    counters, and outputs stay in the caller's order either way."""
+    s = setup
+    src, eps = s["src"], s["eps"]
+    monkeypatch.setenv("BHPP_TUNE", "order=0")
+    G0 = s["bh"].Graph.from_edges(s["el"], dtype="f32")
+    monkeypatch.delenv("BHPP_TUNE")
+    G0.set_launch_config(s["G"].launch_config())
+    a = s["G"].query_batch(src, eps, k=10)
+    b = G0.query_batch(src, eps, k=10)
+    assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
+    assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
+    assert a["stats"] == b["stats"]
+    G0.close()
