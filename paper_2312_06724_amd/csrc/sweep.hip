@@ -1901,7 +1901,8 @@ __global__ void k_admit(ColState* st, const ColState* adm, const int32_t* cols, 
 // A queue-fed 64-column batch that never drains the stream to admit queries.
 // After every chunk the column states are copied to a pinned host ring; the
 // host reads the copy of chunk i while chunk i+1 runs and, for the columns
-// whose query finished by chunk i, enqueues behind chunk i+1: the extraction
+// whose query finished by chunk i or runs its last sweep (MODE_FINAL) in chunk
+// i+1, enqueues behind chunk i+1: the extraction
 // of their beta' rows, their top-k and output copies, then the admission of
 // the next queries into those columns (k_admit). A finished column is inert
 // (its rules are NONE: its ACC is rewritten with the same bits), so reading
@@ -1967,6 +1968,31 @@ static bhpp_status run_sched_async(Graph* g, int target, int n, const int32_t* s
     }
     hipGraphExec_t* cache = &w.chunk_exec[log2i(COLS)];
     int64_t chunk = 0, idle_sweeps = 0, rounds = 0;
+    // a query exported in its last sweep gets its statistics from the state
+    // copy of that chunk (taken before the admission that reuses its column)
+    struct PendingStats {
+        int32_t col, q;
+        int64_t copy;   // index of the state copy to read
+    };
+    std::vector<PendingStats> pend;
+    auto flush_stats = [&](int64_t copy, const ColState* snap) {
+        size_t keep = 0;
+        for (size_t i = 0; i < pend.size(); ++i) {
+            if (pend[i].copy == copy) {
+                if (stats) fill_stats(snap[pend[i].col], stats[pend[i].q]);
+            } else {
+                pend[keep++] = pend[i];
+            }
+        }
+        pend.resize(keep);
+    };
+    // after the stream has drained: every pending copy is in the ring (none
+    // newer was taken)
+    auto flush_all_stats = [&]() {
+        for (const PendingStats& p : pend)
+            if (stats) fill_stats(h_snap[(size_t)(p.copy % NS) * COLS + p.col], stats[p.q]);
+        pend.clear();
+    };
     // export the columns `cols` (finished as of the state copy `snap`) and
     // admit the next queries into them, behind the work already queued
     auto export_round = [&](const std::vector<int32_t>& cols, const ColState* snap) -> bhpp_status {
@@ -1983,7 +2009,10 @@ static bhpp_status run_sched_async(Graph* g, int target, int n, const int32_t* s
             const int q = snap[c].qid;
             lc[j] = c;
             lx[j] = exclude_self ? src_ext[q] : -1;
-            if (stats) fill_stats(snap[c], stats[q]);
+            if (snap[c].mode == MODE_FINAL)
+                pend.push_back(PendingStats{c, q, chunk - 1});   // the copy behind the chunk just launched
+            else if (stats)
+                fill_stats(snap[c], stats[q]);
         }
         BHPP_HIP(hipMemcpyAsync(w.ex_tmp, lc, sizeof(int32_t) * 2 * COLS, hipMemcpyHostToDevice, s));
         VT* rows = as<VT>(w.scores);   // [m][nu]; G is rewritten by the next sweep
@@ -2044,9 +2073,11 @@ static bhpp_status run_sched_async(Graph* g, int target, int n, const int32_t* s
         const int ps = (int)((chunk - 2) % NS);
         if (hipEventSynchronize(ev_snap[ps]) != hipSuccess) { rc = BHPP_DEVICE_ERROR; break; }
         const ColState* snap = h_snap + (size_t)ps * COLS;
+        flush_stats(chunk - 2, snap);
         fin.clear();
         for (int c = 0; c < ncols; ++c)
-            if (qid[c] >= 0 && snap[c].qid == qid[c] && snap[c].mode == MODE_DONE) fin.push_back(c);
+            if (qid[c] >= 0 && snap[c].qid == qid[c] && (snap[c].mode == MODE_DONE || snap[c].mode == MODE_FINAL))
+                fin.push_back(c);
         if (!fin.empty()) {
             rc = export_round(fin, snap);
             idle_sweeps = 0;
@@ -2066,6 +2097,7 @@ static bhpp_status run_sched_async(Graph* g, int target, int n, const int32_t* s
                 break;
             }
             for (int i = 0; i < NS; ++i) adm_busy[i] = false;   // the stream has drained
+            flush_all_stats();
             // columns that finished since the last copy leave first
             fin.clear();
             for (int c = 0; c < ncols; ++c)
@@ -2116,6 +2148,7 @@ static bhpp_status run_sched_async(Graph* g, int target, int n, const int32_t* s
         }
     }
     if (hipStreamSynchronize(s) != hipSuccess && rc == BHPP_OK) rc = BHPP_DEVICE_ERROR;
+    if (rc == BHPP_OK) flush_all_stats();
     if (rc == BHPP_OK && g->prof_on) {
         int32_t live_sweeps = 0;
         if (hipMemcpy(&live_sweeps, w.n_active + 4, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
