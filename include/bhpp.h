@@ -313,9 +313,10 @@ bhpp_status bhpp_autotune(bhpp_graph* g, void* hip_stream, int32_t config_out[4]
  * copies of the column states one chunk behind and queues the finished
  * queries' extraction, top-k and the next admissions behind the running
  * sweeps), 0 for draining export rounds. Results do not depend on them.
- * bhpp_autotune also sets sched[0] from the sweep time it measured (chunks
- * of about 2 ms). Errors: INVALID_ARG (also while a server of this graph
- * exists).
+ * The build sets sched[0] from an estimate of a 64-column sweep (chunks of
+ * about 2 ms: 1 sweep from some 10M edges up, 8 on small graphs), and
+ * bhpp_autotune from the sweep time it measured. Errors: INVALID_ARG (also
+ * while a server of this graph exists).
  */
 bhpp_status bhpp_set_schedule(bhpp_graph* g, const int32_t sched[2]);
 bhpp_status bhpp_get_schedule(const bhpp_graph* g, int32_t sched_out[2]);

@@ -684,6 +684,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
     if (!g) return BHPP_OUT_OF_MEMORY;
     // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=,
     // hub=, chunk=, async=, upd=, urows=, order=)
+    bool chunk_set = false;
     if (const char* e = getenv("BHPP_TUNE")) {
         int v;
         const char* q;
@@ -696,7 +697,10 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "narrow=")) && sscanf(q, "narrow=%d", &v) == 1) g->narrow = v ? 1 : 0;
         if ((q = strstr(e, "fuse=")) && sscanf(q, "fuse=%d", &v) == 1) g->fuse_select = v ? 1 : 0;
         if ((q = strstr(e, "hub=")) && sscanf(q, "hub=%d", &v) == 1) g->hub_lds = v ? 1 : 0;
-        if ((q = strstr(e, "chunk=")) && sscanf(q, "chunk=%d", &v) == 1 && v >= 1 && v <= 8) g->chunk_sweeps = v;
+        if ((q = strstr(e, "chunk=")) && sscanf(q, "chunk=%d", &v) == 1 && v >= 1 && v <= 8) {
+            g->chunk_sweeps = v;
+            chunk_set = true;
+        }
         if ((q = strstr(e, "async=")) && sscanf(q, "async=%d", &v) == 1) g->async_sched = v ? 1 : 0;
         if ((q = strstr(e, "upd=")) && sscanf(q, "upd=%d", &v) == 1) g->fuse_update = v ? 1 : 0;
         if ((q = strstr(e, "urows=")) && sscanf(q, "urows=%d", &v) == 1 && (v == 2 || v == 4)) g->upd_inflight = v;
@@ -717,6 +721,15 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         (void)hipGetLastError();
         free_graph(g);
         return rc;
+    }
+    if (!chunk_set) {
+        // sweeps per chunk before any autotuning, by the autotuner's rule (about
+        // 2 ms of sweeps per chunk) on an estimate of a 64-column sweep: both
+        // gathers read a 256-byte row per entry at about 6 TB/s
+        const double sweep_ms = 2.0 * (double)g->ne * 264.0 / 6.0e9;
+        int chunk = 8;
+        while (chunk > 1 && chunk * sweep_ms > 2.0) chunk /= 2;
+        g->chunk_sweeps = chunk;
     }
     *out = g;
     return BHPP_OK;
