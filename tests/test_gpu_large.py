@@ -2,8 +2,8 @@
 run through the queue-fed 64-column block (FP32, autotuned launch setting as
 the benchmark runs it), top-100 each. The scores of 32 sampled sources of
 that very batch (the highest- and lowest-degree sources among them) are
-compared with the exact series; every result is checked for properties that
-hold at any size.
+compared with the exact series, and so are the PISP baseline's scores of 8 of
+them; every result is checked for properties that hold at any size.
 
 Tolerance: -1e-6 <= beta - beta' <= eps + 1e-6 (Definition 1, Theorem 3 plus
 FP32 rounding). The exact rows are the forward series of Eq. (hpp) summed to
@@ -52,6 +52,10 @@ def test_large_uneven_batch(uncaptured):
     assert pick.size == N_SAMPLE
     S = out["scores"][torch.as_tensor(pick, device="cuda")].cpu().numpy()
     del out
+    # the paper's PISP baseline at full size on 8 of the sampled sources (a block of 8)
+    pp = pick[np.linspace(0, pick.size - 1, 8).round().astype(int)]
+    print("[gpu] PISP on 8 of them", flush=True)
+    P = G.query_batch(src[pp], wl.eps, method="pisp")["scores"].cpu().numpy()
     G.close()
     with uncaptured():
         print(f"[gpu] oracle: exact rows of {pick.size} sources (series to {TAIL})", flush=True)
@@ -74,3 +78,10 @@ def test_large_uneven_batch(uncaptured):
             assert set(ids[i].tolist()) == set(eid[:wl.k].tolist()), u
             strict += 1
     print(f"[gpu] top-k sets compared strictly for {strict} of {pick.size} sources", flush=True)
+    # PISP: SelectivePush at eps/2 plus PowerIteration's tail below eps/2 gives the same band
+    row = {int(i): j for j, i in enumerate(pick)}
+    for k, i in enumerate(pp):
+        d = ex[row[int(i)]] - P[k].astype(np.float64)
+        lo, hi = float(d.min()), float((d + 2 * TAIL).max())
+        print(f"[gpu] PISP source {int(src[i])}: min {lo:.3e}, max - eps {hi - wl.eps:.3e}", flush=True)
+        assert lo >= -1e-6 and hi <= wl.eps + 1e-6, (int(src[i]), lo, hi - wl.eps)
