@@ -115,3 +115,25 @@ def test_pisp_on_benchmark_graph(medium):
         print(f"[gpu] pisp source {int(u)}: {st['steps']} sweeps (t = {st['t']}, SelectivePush "
               f"{st['ss_sel_iters']}), Approx-BHPP {sa['steps']} sweeps", flush=True)
         assert st["t"] == 89          # (1-0.15)^(t+1) <= 5e-7: t = 89 at eps = 1e-6
+
+
+def test_mcsp_on_benchmark_graph(medium):
+    """The MCSP baseline (Sec. 3.3) at the size the bench compares it on: four
+    of the 64 sources at eps = 1e-2 (2.2M walks each) on the same graph built
+    with its alias tables, within eps of the same exact rows (the walk count
+    bounds the forward error by eps/2 with probability 1 - 1e-6; SelectivePush
+    at eps/2 bounds the backward part)."""
+    import paper_2312_06724_amd as bh
+    wl, src = medium["wl"], medium["src"]
+    eps = 1e-2
+    print("[gpu] MCSP: building the 1M x 2M graph with alias tables", flush=True)
+    Gm = bh.Graph.from_edges(medium["el"], alpha=wl.alpha, dtype="f32", mcsp=True)
+    pick = src[[0, 16, 32, 48]]
+    out = Gm.query_mcsp(pick, eps, seed=77, k=wl.k)
+    assert out["walks"] > 2_000_000
+    S = out["scores"].cpu().numpy()
+    for i, u in enumerate(pick):
+        d = medium["ex"][int(u)] - S[i].astype(np.float64)
+        print(f"[gpu] mcsp source {int(u)}: max |beta - beta'| = {np.abs(d).max():.3e}", flush=True)
+        assert np.abs(d).max() <= eps + 1e-6, (int(u), np.abs(d).max())
+    Gm.close()
