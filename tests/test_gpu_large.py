@@ -3,6 +3,7 @@ run through the queue-fed 64-column block (FP32, autotuned launch setting as
 the benchmark runs it), top-100 each. The scores of 32 sampled sources of
 that very batch (the highest- and lowest-degree sources among them) are
 compared with the exact series, and so are the PISP baseline's scores of 8 of
+them and the lone-source path's scores of the highest- and lowest-degree of
 them; every result is checked for properties that hold at any size.
 
 Tolerance: -1e-6 <= beta - beta' <= eps + 1e-6 (Definition 1, Theorem 3 plus
@@ -56,6 +57,11 @@ def test_large_uneven_batch(uncaptured):
     pp = pick[np.linspace(0, pick.size - 1, 8).round().astype(int)]
     print("[gpu] PISP on 8 of them", flush=True)
     P = G.query_batch(src[pp], wl.eps, method="pisp")["scores"].cpu().numpy()
+    # the one-source path (bhpp_query: sparse frontier steps, entry-parallel gathers,
+    # fix-ups of hub rows split into hundreds of pieces) for the sample's extremes by degree
+    ends = [int(pick[np.argmax(deg[src[pick]])]), int(pick[np.argmin(deg[src[pick]])])]
+    print(f"[gpu] lone-source queries of sources {[int(src[i]) for i in ends]}", flush=True)
+    L1 = [G.query(int(src[i]), wl.eps)[0].cpu().numpy() for i in ends]
     G.close()
     with uncaptured():
         print(f"[gpu] oracle: exact rows of {pick.size} sources (series to {TAIL})", flush=True)
@@ -78,8 +84,14 @@ def test_large_uneven_batch(uncaptured):
             assert set(ids[i].tolist()) == set(eid[:wl.k].tolist()), u
             strict += 1
     print(f"[gpu] top-k sets compared strictly for {strict} of {pick.size} sources", flush=True)
-    # PISP: SelectivePush at eps/2 plus PowerIteration's tail below eps/2 gives the same band
     row = {int(i): j for j, i in enumerate(pick)}
+    for k, i in enumerate(ends):
+        d = ex[row[i]] - L1[k].astype(np.float64)
+        lo, hi = float(d.min()), float((d + 2 * TAIL).max())
+        print(f"[gpu] lone source {int(src[i])} (degree {deg[src[i]]}): min {lo:.3e}, max - eps {hi - wl.eps:.3e}",
+              flush=True)
+        assert lo >= -1e-6 and hi <= wl.eps + 1e-6, (int(src[i]), lo, hi - wl.eps)
+    # PISP: SelectivePush at eps/2 plus PowerIteration's tail below eps/2 gives the same band
     for k, i in enumerate(pp):
         d = ex[row[int(i)]] - P[k].astype(np.float64)
         lo, hi = float(d.min()), float((d + 2 * TAIL).max())
