@@ -684,11 +684,14 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
     if (!g) return BHPP_OUT_OF_MEMORY;
     // launch settings: defaults, or BHPP_TUNE="tile=512,inflight=8,nt=0,graphs=1" (also sparse=, narrow=, fuse=,
     // hub=, chunk=, async=, upd=, urows=, order=)
-    bool chunk_set = false;
+    bool chunk_set = false, tile_set = false;
     if (const char* e = getenv("BHPP_TUNE")) {
         int v;
         const char* q;
-        if ((q = strstr(e, "tile=")) && sscanf(q, "tile=%d", &v) == 1 && v >= 64) g->tile_edges = v;
+        if ((q = strstr(e, "tile=")) && sscanf(q, "tile=%d", &v) == 1 && v >= 64) {
+            g->tile_edges = v;
+            tile_set = true;
+        }
         if ((q = strstr(e, "inflight=")) && sscanf(q, "inflight=%d", &v) == 1 && (v == 4 || v == 8 || v == 16))
             g->inflight = v;
         if ((q = strstr(e, "nt=")) && sscanf(q, "nt=%d", &v) == 1) g->nt_stream = v ? 1 : 0;
@@ -708,6 +711,14 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
     }
     if (opts.flags & BHPP_BUILD_DENSE_ONLY) g->sparse_steps = 0;
     if (opts.flags & BHPP_BUILD_FIXED_WIDTH) g->narrow = 0;
+    if (!tile_set) {
+        // entries per work tile before any autotuning: about three tiles per
+        // wavefront of the gathers' largest grid (2048 blocks of 4 waves),
+        // a power of two in [256, 4096] (4096 measured best on 100M edges)
+        int te = 256;
+        while (te < 4096 && (double)te * 3.0 * 8192.0 < (double)n_edges) te *= 2;
+        g->tile_edges = te;
+    }
     g->nu = n_u;
     g->nv = n_v;
     g->dtype = opts.dtype;

@@ -13,7 +13,7 @@
 namespace bhpp {
 
 constexpr int kWave = 64;            // CDNA wavefront width
-constexpr int kTileEdges = 512;      // target adjacency entries per work tile
+constexpr int kTileEdges = 512;      // target adjacency entries per work tile (the build scales it with |E|)
 constexpr int kMaxCols = 64;         // sources per dense residue block (one per lane)
 constexpr int kPassThreads = 256;    // threads per block of the sweep kernels
 constexpr int kNumRed = 5;           // per-source reductions after a step (see Red)

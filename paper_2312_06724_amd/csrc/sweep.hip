@@ -2442,7 +2442,7 @@ bhpp_status autotune(Graph* g, hipStream_t s, int* out_cfg) {
     if (!g->work) BHPP_HIP(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
     hipStream_t ws = g->work;
     BHPP_HIP(hipStreamSynchronize(s));
-    const int tiles[] = {256, 512, 1024};
+    const int tiles[] = {512, 1024, 2048, 4096};
     const int infl[] = {4, 8, 16};
     int best[4] = {g->tile_edges, g->inflight, g->nt_stream, g->use_graphs};
     float best_ms = 1e30f;
