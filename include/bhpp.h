@@ -296,9 +296,10 @@ bhpp_status bhpp_profile_sweeps(bhpp_graph* g, int64_t* live_out);
  * on them, only the time does.
  *
  * bhpp_autotune times a few sweeps of a 64-source block for each candidate
- * (tile sizes 256/512/1024, 4/8/16 gathers in flight, streaming off/on) on
- * hip_stream's device, keeps the fastest and writes it to config_out (host).
- * It synchronises hip_stream. bhpp_set_launch_config applies a setting saved
+ * (tile sizes 512/1024/2048/4096, 4/8/16 gathers in flight, streaming
+ * off/on) on hip_stream's device, keeps the fastest and writes it to
+ * config_out (host); it then sets the sweeps per chunk so that a chunk takes
+ * about 2 ms. It synchronises hip_stream. bhpp_set_launch_config applies a setting saved
  * earlier (e.g. a cache keyed by the graph); bhpp_get_launch_config reads the
  * current one. Errors: INVALID_ARG (also while a server of this graph
  * exists: its captured sweeps refer to the current tiles), OUT_OF_MEMORY,
