@@ -192,8 +192,8 @@ struct GatherArgs {
     // itself, S(x) = y(x)/ws(x) for the pushed x, reading Y, 1/ws of each
     // entry's neighbour (iwf, stored beside the adjacency so that it arrives
     // with the indices) and the column states (stf) instead of a selected copy
-    // S; a sweep in which a column starts a query (lazy reset) reads the S
-    // written by k_select
+    // S; a column that starts a query in this sweep (lazy reset, or PISP's
+    // residue restart) takes y = e_src instead of its Y
     const VT* Yf = nullptr;
     const VT* iwf = nullptr;     // per adjacency entry, beside ci and w
     const ColState* stf = nullptr;
@@ -366,11 +366,11 @@ struct Gather64State {
 // bounds test; otherwise loads past n re-read entry n-1 and are not used.
 // UPD: whole rows go to this wavefront's LDS rows (lrow, row st.row at
 // (st.row - T.row_begin) * 64) for the update at the end of the tile.
-template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL, bool FUSED, bool UPD>
+template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL, int FUSED, bool UPD>
 __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, const VT* X, const PushTest<VT>& test,
-                                               const Tile& T, bool split, bool ns, bool on, int col, int xcol,
-                                               int64_t cb, int n, int32_t lx, VT lw, VT liw, int mbase, int m_rel,
-                                               Gather64State<VT, WT>& st, VT* lrow) {
+                                               bool ysrc, int32_t src_row, const Tile& T, bool split, bool ns,
+                                               bool on, int col, int xcol, int64_t cb, int n, int32_t lx, VT lw,
+                                               VT liw, int mbase, int m_rel, Gather64State<VT, WT>& st, VT* lrow) {
     constexpr int COLS = 64;
     const int jend = FULL ? kWave : n;
     for (int j0 = 0; j0 < jend; j0 += INF) {
@@ -386,6 +386,7 @@ __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, cons
             if (FULL || j < n) {
                 VT sv = v[jj];
                 if (FUSED) {   // the select pass's arithmetic: S = y/ws if pushed, else 0
+                    if (FUSED == 2 && ysrc) sv = rl(lx, j) == src_row ? VT(1) : VT(0);   // a new query: y = e_src
                     const VT yw = sv * rl(liw, j);
                     sv = test(fabs(sv), fabs(yw)) ? yw : VT(0);
                 }
@@ -468,15 +469,20 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
     // line, so no extra traffic and no divergent branch around the loads);
     // their sums are never stored and their push cost is dropped
     const int xcol = on ? col : 0;
-    // gather A with the push rule applied here (see GatherArgs::Yf), unless a
-    // live column starts a query in this sweep
-    bool fused = false;
+    // gather A with the push rule applied here (see GatherArgs::Yf)
+    const bool fused = SIDE_A && p.Yf != nullptr;
     PushTest<VT> test(RULE_NONE, VT(0), VT(0));
-    if (SIDE_A && p.Yf != nullptr) {
+    bool ysrc = false;
+    int32_t src_row = -1;
+    if (fused) {
         const ColState& cs = p.stf[col];
-        fused = __ballot(on && (cs.fresh != 0 || cs.reset_y != 0)) == 0ull;
         test = PushTest<VT>(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
+        ysrc = on && (cs.fresh != 0 || cs.reset_y != 0);
+        src_row = cs.src_row;
     }
+    // the comparison with the source's row only in sweeps where a column starts
+    // a query (wave-uniform: every wavefront holds all 64 columns)
+    const bool new_q = fused && __ballot(ysrc) != 0ull;
     const VT* X = fused ? p.Yf : p.X;
     Gather64State<VT, WT> st;
     st.np = 0.0;
@@ -499,21 +505,17 @@ __global__ __launch_bounds__(kPassThreads) void k_gather64(GatherArgs<VT, WT> p)
             // row ends relative to the chunk start (> 64: not in this chunk)
             const int m_rel = (int)min(m_end - cb, (int64_t)(1 << 30));
             st.rend = rl(m_rel, 0);
-            if (fused) {
-                if (n == kWave)
-                    gather64_chunk<VT, WT, SIDE_A, INF, true, true, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol, cb,
-                                                                         n, lx, lw, liw, mbase, m_rel, st, lrow);
-                else
-                    gather64_chunk<VT, WT, SIDE_A, INF, false, true, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol, cb,
-                                                                          n, lx, lw, liw, mbase, m_rel, st, lrow);
+            // FUSED: 0 the select pass's S, 1 the push rule applied here, 2 also
+            // y = e_src for the columns that start a query in this sweep
+#define BHPP_CHUNK(FULL, FUSED)                                                                                   \
+    gather64_chunk<VT, WT, SIDE_A, INF, FULL, FUSED, (UPD > 0)>(p, X, test, ysrc, src_row, T, split, ns, on, col, \
+                                                                xcol, cb, n, lx, lw, liw, mbase, m_rel, st, lrow)
+            if (n == kWave) {
+                if (new_q) BHPP_CHUNK(true, 2); else if (fused) BHPP_CHUNK(true, 1); else BHPP_CHUNK(true, 0);
             } else {
-                if (n == kWave)
-                    gather64_chunk<VT, WT, SIDE_A, INF, true, false, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol, cb,
-                                                                          n, lx, lw, liw, mbase, m_rel, st, lrow);
-                else
-                    gather64_chunk<VT, WT, SIDE_A, INF, false, false, (UPD > 0)>(p, X, test, T, split, ns, on, col, xcol,
-                                                                           cb, n, lx, lw, liw, mbase, m_rel, st, lrow);
+                if (new_q) BHPP_CHUNK(false, 2); else if (fused) BHPP_CHUNK(false, 1); else BHPP_CHUNK(false, 0);
             }
+#undef BHPP_CHUNK
         }
         if (UPD && !split && on) update_tile_rows<VT, WT, (UPD > 0 ? UPD : 1)>(p, lrow, T.row_begin, T.row_end, col, r);
     }
@@ -732,15 +734,9 @@ __global__ __launch_bounds__(kFixThreads) void k_fixup(GatherArgs<VT, WT> p, con
 template <int COLS, typename VT>
 __global__ __launch_bounds__(kPassThreads) void k_select(const VT* __restrict__ Y, VT* __restrict__ S,
                                                         const VT* __restrict__ inv_ws, int32_t n_rows,
-                                                        const ColState* st, const int32_t* n_active, int only_fresh) {
+                                                        const ColState* st, const int32_t* n_active) {
     if (*n_active == 0) return;
     const int col = threadIdx.x & (COLS - 1);
-    if (only_fresh) {
-        // gather A applies the rule itself unless a live column starts a query
-        // (each wavefront covers all COLS == 64 columns, so this is uniform)
-        const bool fr = col < live_cols(n_active, COLS) && (st[col].fresh != 0 || st[col].reset_y != 0);
-        if (__ballot(fr) == 0ull) return;
-    }
     if (col >= live_cols(n_active, COLS)) return;   // no barrier below
     const ColState& cs = st[col];
     const PushTest<VT> test(cs.ruleA, (VT)cs.k_ss, (VT)cs.k_pi);
@@ -1247,7 +1243,7 @@ static double launch_bytes(const Graph* g, int cols, int kind) {
     const double vt = sizeof(VT);
     const double visits = nnz * ((4.0 + sizeof(WT)) + cols * vt);
     // gather A applying the push rule also reads 1/ws of each entry's
-    // neighbour; k_select then only runs in sweeps where a query starts
+    // neighbour; there is no select pass then
     const bool fused = cols == 64 && g->fuse_select && vt == (double)g->elem;
     if (kind == 0) return visits + (fused ? nnz * vt : 0.0) + nv * (8.0 + cols * vt);
     if (kind == 3 && fused) return 0.0;
@@ -1304,10 +1300,12 @@ static void launch_front(Graph* g, const Block& b, const Geometry& G, hipStream_
         A.iwf = reinterpret_cast<const VT*>(g->iw_v);
         A.stf = b.st;
     }
-    pb(3);
-    hipLaunchKernelGGL((k_select<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.S),
-                       inv_ws_u_of<VT>(g), g->nu, b.st, b.n_active, fuse ? 1 : 0);
-    prof_end(g, s, ev);
+    if (!fuse) {
+        pb(3);
+        hipLaunchKernelGGL((k_select<COLS, VT>), dim3(G.blkU), dim3(kPassThreads), 0, s, as<VT>(b.Y), as<VT>(b.S),
+                           inv_ws_u_of<VT>(g), g->nu, b.st, b.n_active);
+        prof_end(g, s, ev);
+    }
     pb(0);
     A.red_slot = G.offA;
     if (COLS == 64)

@@ -93,8 +93,8 @@ def test_fused_select_matches_select_pass(setup, monkeypatch):
     """In 64-column blocks gather A applies the push rule itself (S = y/ws for
     the pushed x) instead of reading a copy written by a select pass: same
     products in the same order, so the same bits. 200 sources refill the
-    columns, so sweeps in which a column starts a query (where the select pass
-    still runs) are mixed in."""
+    columns, so sweeps in which columns start a query (y = e_src taken in the
+    gather) are mixed in; PISP's batch adds the mid-query residue restart."""
     s = setup
     monkeypatch.setenv("BHPP_TUNE", "fuse=0")
     G0 = s["bh"].Graph.from_edges(s["el"], dtype="f32", fixed_width=True)
@@ -103,6 +103,11 @@ def test_fused_select_matches_select_pass(setup, monkeypatch):
     src, eps = s["src"], s["eps"]
     a = s["Gf"].query_batch(src, eps, k=10)
     b = G0.query_batch(src, eps, k=10)
+    assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
+    assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
+    assert a["stats"] == b["stats"]
+    a = s["Gf"].query_batch(src[:80], 1e-5, k=10, method="pisp")
+    b = G0.query_batch(src[:80], 1e-5, k=10, method="pisp")
     assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
     assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
     assert a["stats"] == b["stats"]
