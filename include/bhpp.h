@@ -85,7 +85,9 @@ typedef struct {
    selection pass; same bits either way), upd=<0|1> (64-column blocks: the
    U-side gather applies the update itself instead of a separate update
    pass; same bits per entry, per-source sums added in another order; on by
-   default) and hub=<0|1> (one-source gathers read the values of the
+   default), bufa=<0|1> (64-column FP32 blocks: the V-side gather reads its
+   rows with buffer loads; same bits either way; on by default) and
+   hub=<0|1> (one-source gathers read the values of the
    highest-degree nodes from a copy in LDS; same bits either way; off by
    default). */
 #define BHPP_BUILD_FIXED_WIDTH   8u

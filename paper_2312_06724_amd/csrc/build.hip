@@ -700,6 +700,7 @@ bhpp_status build_graph(int32_t n_u, int32_t n_v, int64_t n_edges, const int32_t
         if ((q = strstr(e, "narrow=")) && sscanf(q, "narrow=%d", &v) == 1) g->narrow = v ? 1 : 0;
         if ((q = strstr(e, "fuse=")) && sscanf(q, "fuse=%d", &v) == 1) g->fuse_select = v ? 1 : 0;
         if ((q = strstr(e, "hub=")) && sscanf(q, "hub=%d", &v) == 1) g->hub_lds = v ? 1 : 0;
+        if ((q = strstr(e, "bufa=")) && sscanf(q, "bufa=%d", &v) == 1) g->buf_rows = v ? 1 : 0;
         if ((q = strstr(e, "chunk=")) && sscanf(q, "chunk=%d", &v) == 1 && v >= 1 && v <= 8) {
             g->chunk_sweeps = v;
             chunk_set = true;

@@ -204,6 +204,7 @@ struct Graph {
     int sparse_steps = 1;            // one-source queries: sparse frontier steps while the frontier is small
     int narrow = 1;                  // batches narrow their block as sources finish
     int hub_lds = 0;                 // one-source gathers read the hub slice of their vector from LDS (hub=1)
+    int buf_rows = 1;                // gather A (push rule applied, FP32) reads rows with buffer loads (bufa=1)
     int chunk_sweeps = 8;            // sweeps per launched chunk (captured graph), 1..8
     int async_sched = 1;             // queue-fed 64-column batches admit without draining the stream
     int fuse_update = 1;             // 64-column blocks: the U-side gather applies the update (no G array)

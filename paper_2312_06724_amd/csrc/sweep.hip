@@ -370,7 +370,7 @@ struct Gather64State {
 // UPD: whole rows go to this wavefront's LDS rows (lrow, row st.row at
 // (st.row - T.row_begin) * 64) for the update at the end of the tile.
 // BUF (FP32): the row reads are buffer loads through xr (X as a buffer of at
-// most 4 GiB): the row's byte offset goes in a scalar register and the lane's
+// most 2 GiB): the row's byte offset goes in a scalar register and the lane's
 // column offset in a vector register, so no 64-bit address is formed per entry.
 template <typename VT, typename WT, bool SIDE_A, int INF, bool FULL, int FUSED, bool UPD, bool BUF>
 __device__ __forceinline__ void gather64_chunk(const GatherArgs<VT, WT>& p, const VT* X, __amdgpu_buffer_rsrc_t xr,
@@ -459,7 +459,7 @@ __device__ __forceinline__ void update_tile_rows(const GatherArgs<VT, WT>& p, co
 
 // AM (gather A): 0 reads S written by the select pass; 1 applies the push rule
 // itself (GatherArgs::Yf); 2 does so with buffer-load row reads (FP32, the
-// gathered block under 4 GiB). Each mode is a kernel of its own, which keeps
+// gathered block under 2 GiB). Each mode is a kernel of its own, which keeps
 // the code of one launch small.
 // UPD > 0 (gather B only; UPD rows' loads in flight in the update): tiles of
 // at most upd_rows whole rows, whose sums stay
@@ -1214,13 +1214,13 @@ struct Block {
 };
 
 // Gather A's kernel (the AM of k_gather64): with the push rule applied in the
-// gather, FP32 blocks under 4 GiB read their rows with buffer loads (measured
-// 1% faster for gather A; the U-side gather keeps global loads, which measured
-// faster there).
+// gather, FP32 blocks under 2 GiB (so that every byte offset is a positive
+// 32-bit value) read their rows with buffer loads (measured 1% faster for
+// gather A; the U-side gather keeps global loads, which measured faster there).
 template <typename VT>
 static int gather_a_mode(const Graph* g, bool fuse) {
     if (!fuse) return 0;
-    return sizeof(VT) == 4 && (uint64_t)g->nu * 64 * sizeof(VT) < (1ull << 32) ? 2 : 1;
+    return g->buf_rows && sizeof(VT) == 4 && (uint64_t)g->nu * 64 * sizeof(VT) < (1ull << 31) ? 2 : 1;
 }
 
 template <typename VT, typename WT, bool SIDE_A, int UPD = 0>

@@ -94,18 +94,24 @@ def test_fused_select_matches_select_pass(setup, monkeypatch):
     the pushed x) instead of reading a copy written by a select pass: same
     products in the same order, so the same bits. 200 sources refill the
     columns, so sweeps in which columns start a query (y = e_src taken in the
-    gather) are mixed in; PISP's batch adds the mid-query residue restart."""
+    gather) are mixed in; PISP's batch adds the mid-query residue restart.
+    The fused gather's rows come by buffer loads by default; bufa=0 takes
+    global loads: same bits."""
     s = setup
     monkeypatch.setenv("BHPP_TUNE", "fuse=0")
     G0 = s["bh"].Graph.from_edges(s["el"], dtype="f32", fixed_width=True)
+    monkeypatch.setenv("BHPP_TUNE", "bufa=0")
+    G1 = s["bh"].Graph.from_edges(s["el"], dtype="f32", fixed_width=True)
     monkeypatch.delenv("BHPP_TUNE")
     G0.set_launch_config(s["Gf"].launch_config())
+    G1.set_launch_config(s["Gf"].launch_config())
     src, eps = s["src"], s["eps"]
     a = s["Gf"].query_batch(src, eps, k=10)
-    b = G0.query_batch(src, eps, k=10)
-    assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
-    assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
-    assert a["stats"] == b["stats"]
+    for Gx in (G0, G1):
+        b = Gx.query_batch(src, eps, k=10)
+        assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
+        assert np.array_equal(a["ids"].cpu().numpy(), b["ids"].cpu().numpy())
+        assert a["stats"] == b["stats"]
     a = s["Gf"].query_batch(src[:80], 1e-5, k=10, method="pisp")
     b = G0.query_batch(src[:80], 1e-5, k=10, method="pisp")
     assert np.array_equal(a["scores"].cpu().numpy(), b["scores"].cpu().numpy())
