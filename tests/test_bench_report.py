@@ -48,6 +48,19 @@ def test_roofline_bytes_update_fused():
     assert r["kernel"].startswith("U-side gather with the update fused")
     assert r["algorithmic_bytes_per_launch"] == int(alg_b / 10)
     assert set(r["kernels"]) == {"gather_a", "gather_b"}   # kinds without launches are left out
+    # compulsory: adjacency once per sweep, each dense row of both sides once per running column
+    V1 = 180
+    comp_b = L * (8 * E + 8 * U1) + 4 * (U1 + V1) * CS + L * 8 * U1 + 12 * U1 * CS
+    assert r["compulsory"]["bytes_per_launch"] == int(comp_b / 10)
+    assert r["compulsory"]["frac"] == pytest.approx(round(comp_b / 5e-3 / 1e9 / bench.HBM_PEAK_GBS, 4))
+
+
+def test_traffic_rate_from_stored_counters(monkeypatch):
+    prof = dict(ms=[3.0, 5.0, 0.0, 0.0], launches=[10, 10, 0, 0], live_sweeps=10)
+    monkeypatch.setattr(bench, "stored_traffic", lambda wl, kind: 4_000_000_000 if kind == "gather_b" else None)
+    r = bench.roofline(prof, stats(2, 4, 50.0, 70.0), INFO, "wl")
+    assert r["traffic"] == 4_000_000_000
+    assert r["traffic_gbs"] == pytest.approx(8000.0)   # 4 GB per launch in 0.5 ms
 
 
 def test_stored_traffic_needs_the_profiled_source(tmp_path, monkeypatch):
