@@ -267,7 +267,8 @@ bhpp_status bhpp_graph_export(const bhpp_graph* g, int64_t* rp_u, int32_t* ci_u,
  * Device-time profile of the sweep kernels. While enabled, every launch of the
  * V-side gather (kind 0), the U-side gather (kind 1; in 64-column blocks it
  * also applies the update, and kind 2 then has no launches), the U-side update
- * (kind 2) and the push selection (kind 3) on a query stream is bracketed by
+ * (kind 2) and the push selection (kind 3; none in 64-column blocks, whose
+ * V-side gather applies the push rule itself) on a query stream is bracketed by
  * HIP events on that stream and the
  * elapsed times are accumulated; bhpp_profile_read synchronises and returns,
  * per kind, the total milliseconds, the number of launches and the
